@@ -1,0 +1,353 @@
+"""FP64 reference of the DTT-based PSTD method: operators, time stepping, closed forms, combination.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Canonical layout (the reading of "N nodes" used throughout): along an axis with ``n`` pressure nodes
+p sits at x_j = j*dx, j = 0..n-1, with the two walls on nodes 0 and n-1, so L = (n-1)*dx and every
+boundary case has the implied period M = 2(n-1).  The particle velocity sits on the n-1 staggered
+points (j+1/2)*dx.  A Dirichlet wall node is not an unknown and holds p = 0.
+
+Each function cites the passage of arXiv:2005.00322 it follows.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from itertools import product
+
+import numpy as np
+
+from . import dtt
+
+NEUMANN = 0
+DIRICHLET = 1
+
+# Table transform_choices (§4.1): boundary pair (left, right) -> sequence types of p and u, the forward
+# transforms T1 (acts on p) and T2 (acts on u), and the signs of the k-space coefficients a1 = ±k, a2 = ±k.
+_TRANSFORM_CHOICES = {
+    (NEUMANN, NEUMANN): ("NN", "WSWS", "HAHA", ("C", 1), ("S", 2), -1.0, +1.0),
+    (NEUMANN, DIRICHLET): ("ND", "WSWA", "HAHS", ("C", 3), ("S", 4), -1.0, +1.0),
+    (DIRICHLET, NEUMANN): ("DN", "WAWS", "HSHA", ("S", 3), ("C", 4), +1.0, -1.0),
+    (DIRICHLET, DIRICHLET): ("DD", "WAWA", "HSHS", ("S", 1), ("C", 2), +1.0, -1.0),
+}
+
+
+def wavenumber_indices(kind: str, typ: int, M: int) -> tuple[np.ndarray, bool]:
+    """Wavenumber index n carried by each output entry of a transform, and whether its group is periodic.
+
+    Table DTT_wavenumber_groups: periodic group I has k_n = 2*pi*n/(M dx) with n = 0..M/2 (DCT-I),
+    0..M/2-1 (DCT-II), 1..M/2-1 (DST-I), 1..M/2 (DST-II); antiperiodic group II has
+    k_n = 2*pi*(n+1/2)/(M dx) with n = 0..M/2-1 for DCT/DST-III and -IV.
+    """
+    h = M // 2
+    if (kind, typ) == ("C", 1):
+        return np.arange(0, h + 1), True
+    if (kind, typ) == ("C", 2):
+        return np.arange(0, h), True
+    if (kind, typ) == ("S", 1):
+        return np.arange(1, h), True
+    if (kind, typ) == ("S", 2):
+        return np.arange(1, h + 1), True
+    if typ in (3, 4):
+        return np.arange(0, h), False
+    raise ValueError((kind, typ))
+
+
+def wavenumbers(idx: np.ndarray, periodic: bool, M: int, dx: float) -> np.ndarray:
+    """k_n of Table DTT_wavenumber_groups for the given indices."""
+    shift = 0.0 if periodic else 0.5
+    return 2.0 * np.pi * (idx + shift) / (M * dx)
+
+
+def _reindex(coef: np.ndarray, src_idx: np.ndarray, dst_idx: np.ndarray) -> np.ndarray:
+    """Move k-space entries from one transform's wavenumber range to another's (last axis).
+
+    §3.3: where the two ranges differ, the DC / Nyquist entries the inverse transform does not carry
+    are dropped and those it carries but the forward transform did not produce are set to zero.
+    """
+    out = np.zeros(coef.shape[:-1] + (len(dst_idx),), dtype=coef.dtype)
+    pos = {int(n): m for m, n in enumerate(src_idx)}
+    for m_dst, n in enumerate(dst_idx):
+        m_src = pos.get(int(n))
+        if m_src is not None:
+            out[..., m_dst] = coef[..., m_src]
+    return out
+
+
+@dataclass
+class Axis:
+    """One axis of the grid with its boundary pair, following Table transform_choices (§4.1).
+
+    ``grad`` is the velocity-step operator T2^{-1}{a1 T1{p}} (p nodes -> staggered points) and
+    ``div`` the pressure-step operator T1^{-1}{a2 T2{u}} (staggered points -> p nodes), both built
+    from the rows of the appendix tables "Differentiation with staggered grids" for groups I and II.
+    """
+
+    n: int
+    bc_left: int
+    bc_right: int
+    dx: float
+
+    def __post_init__(self):
+        if self.n < 3:
+            raise ValueError("an axis needs at least 3 nodes")
+        (self.name, self.p_sym, self.u_sym, self.T1_id, self.T2_id,
+         self.a1_sign, self.a2_sign) = _TRANSFORM_CHOICES[(self.bc_left, self.bc_right)]
+        n = self.n
+        # Representative sample of p: a whole-sample antisymmetric (Dirichlet) end excludes its wall node.
+        self.p_lo = 0 if self.bc_left == NEUMANN else 1
+        self.p_hi = n - 1 if self.bc_right == NEUMANN else n - 2
+        Lp = self.p_hi - self.p_lo + 1
+        Lu = n - 1
+        self.M = dtt.period(*self.T1_id, Lp)
+        if self.M != dtt.period(*self.T2_id, Lu) or self.M != 2 * (n - 1):
+            raise AssertionError("inconsistent implied periods")
+        self.T1 = dtt.matrix(*self.T1_id, Lp)
+        self.T2 = dtt.matrix(*self.T2_id, Lu)
+        self.T1inv = dtt.inverse_matrix(*self.T1_id, Lp)
+        self.T2inv = dtt.inverse_matrix(*self.T2_id, Lu)
+        self.n1, per1 = wavenumber_indices(*self.T1_id, self.M)
+        self.n2, per2 = wavenumber_indices(*self.T2_id, self.M)
+        if per1 != per2:
+            raise AssertionError("T1 and T2 must be in the same group")
+        self.periodic = per1
+        self.k1 = wavenumbers(self.n1, per1, self.M, self.dx)
+        self.k2 = wavenumbers(self.n2, per2, self.M, self.dx)
+
+    # -- the two operators of Eq. (dtt_pstd_solution), along the last axis --------------------------
+    def grad(self, p: np.ndarray) -> np.ndarray:
+        """T2^{-1}{a1 T1{p}}: derivative of p interpolated to the staggered points (last axis)."""
+        sample = p[..., self.p_lo:self.p_hi + 1]
+        coef = sample @ self.T1.T                                  # forward T1
+        coef = coef * (self.a1_sign * self.k1)                     # multiply by a1 = ±k
+        coef = _reindex(coef, self.n1, self.n2)                    # onto the range of T2^{-1}
+        return coef @ self.T2inv.T                                 # inverse of T2 = (1/M) T2_pair
+
+    def div(self, u: np.ndarray) -> np.ndarray:
+        """T1^{-1}{a2 T2{u}}: derivative of u interpolated back to the p nodes (last axis)."""
+        coef = u @ self.T2.T                                       # forward T2
+        coef = coef * (self.a2_sign * self.k2)                     # multiply by a2 = ±k
+        coef = _reindex(coef, self.n2, self.n1)                    # onto the range of T1^{-1}
+        sample = coef @ self.T1inv.T                               # inverse of T1 = (1/M) T1_pair
+        out = np.zeros(u.shape[:-1] + (self.n,), dtype=np.float64)
+        out[..., self.p_lo:self.p_hi + 1] = sample                 # Dirichlet wall nodes stay 0
+        return out
+
+    # -- helpers used by the closed forms and invariants --------------------------------------------
+    def node_weights(self) -> np.ndarray:
+        """Quadrature weights on the p nodes: 1/2 at a Neumann wall node, 0 at a Dirichlet one, else 1."""
+        w = np.ones(self.n)
+        w[0] = 0.5 if self.bc_left == NEUMANN else 0.0
+        w[-1] = 0.5 if self.bc_right == NEUMANN else 0.0
+        return w
+
+    def grad_matrix(self) -> np.ndarray:
+        """The linear map ``grad`` as an (n-1) x n matrix (columns of Dirichlet nodes are zero)."""
+        return self.grad(np.eye(self.n)).T
+
+    def div_matrix(self) -> np.ndarray:
+        """The linear map ``div`` as an n x (n-1) matrix (rows of Dirichlet nodes are zero)."""
+        return self.div(np.eye(self.n - 1)).T
+
+
+def _along(fn, x: np.ndarray, axis: int) -> np.ndarray:
+    return np.moveaxis(fn(np.moveaxis(x, axis, -1)), -1, axis)
+
+
+@dataclass
+class Problem:
+    """A rectangular domain with a boundary pair per axis and homogeneous (or mapped) sound speed.
+
+    ``bcs`` holds (left, right) per axis.  ``c0`` is a scalar; an optional ``c0_map`` on the p nodes
+    replaces it in the pressure step (pointwise c0(x)^2, an extension not in the paper).
+    """
+
+    shape: tuple
+    bcs: tuple
+    dx: float
+    dt: float
+    c0: float
+    rho0: float = 1000.0
+    c0_map: np.ndarray | None = None
+
+    def __post_init__(self):
+        self.shape = tuple(int(s) for s in self.shape)
+        self.bcs = tuple((int(a), int(b)) for a, b in self.bcs)
+        if len(self.shape) != len(self.bcs):
+            raise ValueError("one boundary pair per axis")
+        self.axes = [Axis(n, bl, br, self.dx) for n, (bl, br) in zip(self.shape, self.bcs)]
+
+    @property
+    def ndim(self) -> int:
+        return len(self.shape)
+
+    def u_shape(self, a: int) -> tuple:
+        s = list(self.shape)
+        s[a] -= 1
+        return tuple(s)
+
+    def project(self, p: np.ndarray) -> np.ndarray:
+        """Zero p on Dirichlet wall nodes (they are not unknowns of the method)."""
+        q = np.array(p, dtype=np.float64, copy=True)
+        for a, ax in enumerate(self.axes):
+            idx = [slice(None)] * self.ndim
+            if ax.bc_left == DIRICHLET:
+                idx[a] = 0
+                q[tuple(idx)] = 0.0
+            if ax.bc_right == DIRICHLET:
+                idx[a] = self.shape[a] - 1
+                q[tuple(idx)] = 0.0
+        return q
+
+    def grad(self, p: np.ndarray, a: int) -> np.ndarray:
+        return _along(self.axes[a].grad, p, a)
+
+    def div(self, u: np.ndarray, a: int) -> np.ndarray:
+        return _along(self.axes[a].div, u, a)
+
+    def c2(self):
+        return self.c0 ** 2 if self.c0_map is None else np.asarray(self.c0_map, dtype=np.float64) ** 2
+
+    def initial_velocity(self, p0: np.ndarray, mode: str = "centred") -> list:
+        """u^{-1/2} on every axis.
+
+        The paper starts from zero particle velocity "accounting for the staggered grid" (§4.2) without
+        a formula.  ``centred`` reads that as a time-centred u(t=0) = 0, i.e.
+        u^{-1/2} = +(dt / (2 rho0)) * grad p^0, the half step of Eq. (dtt_pstd_solution_a) run
+        backwards; ``zero`` is the literal u^{-1/2} = 0.
+        """
+        p0 = self.project(p0)
+        if mode == "zero":
+            return [np.zeros(self.u_shape(a)) for a in range(self.ndim)]
+        if mode == "centred":
+            return [(self.dt / (2.0 * self.rho0)) * self.grad(p0, a) for a in range(self.ndim)]
+        raise ValueError(mode)
+
+    def step(self, p: np.ndarray, u: list) -> tuple[np.ndarray, list]:
+        """One time step, Eq. (dtt_pstd_solution) and its multi-dimensional form (§4.3).
+
+        Every u_a is advanced from p^n first; then p^{n+1} uses all the new u_a.
+        """
+        u_new = [u[a] - (self.dt / self.rho0) * self.grad(p, a) for a in range(self.ndim)]
+        acc = np.zeros(self.shape)
+        for a in range(self.ndim):
+            acc += self.div(u_new[a], a)
+        p_new = p - self.dt * self.rho0 * self.c2() * acc
+        return p_new, u_new
+
+    def run(self, p0: np.ndarray, n_steps: int, u_mode: str = "centred", u0=None):
+        """Advance (p^0, u^{-1/2}) by n_steps; returns (p^{n}, [u_a^{n-1/2}])."""
+        p = self.project(p0)
+        u = self.initial_velocity(p, u_mode) if u0 is None else [np.array(x, dtype=np.float64) for x in u0]
+        for _ in range(int(n_steps)):
+            p, u = self.step(p, u)
+        return p, u
+
+    # -- invariants and closed forms -----------------------------------------------------------------
+    def energy(self, p: np.ndarray, u_prev: list, u_next: list) -> float:
+        """Discrete acoustic energy conserved exactly by the staggered step (derived from §4.1, §4.3).
+
+        F = sum_j w_j p_j^2 / (rho0 c0^2) + rho0 * sum_a <u_a^{n-1/2}, u_a^{n+1/2}>_a, where w is the
+        product of the per-axis node weights and <.,.>_a weights the non-differentiated axes of u_a
+        the same way.  It is conserved because W D_a = -G_a^T on every axis.
+        """
+        ws = [ax.node_weights() for ax in self.axes]
+        W = ws[0]
+        for w in ws[1:]:
+            W = np.multiply.outer(W, w)
+        F = float(np.sum(W * p * p / (self.rho0 * self.c2())))
+        for a in range(self.ndim):
+            Wa = np.ones(1)
+            for b in range(self.ndim):
+                Wa = np.multiply.outer(Wa, np.ones(self.shape[a] - 1) if b == a else ws[b])
+            Wa = Wa.reshape(self.u_shape(a))
+            F += self.rho0 * float(np.sum(Wa * u_prev[a] * u_next[a]))
+        return F
+
+    def modal_solution(self, p0: np.ndarray, m: int, u_mode: str = "centred") -> np.ndarray:
+        """p^m in closed form by expanding p^0 in the eigenfunctions of the T1 basis (homogeneous c0).
+
+        Along each axis div o grad = T1^{-1} diag(-k^2) T1, so every T1 mode evolves on its own under
+        the leapfrog with sin(theta/2) = c0 dt |k| / 2: p^m = P cos(m theta) for the centred start and
+        P cos(m theta + theta/2) / cos(theta/2) for u^{-1/2} = 0.
+        """
+        if self.c0_map is not None:
+            raise ValueError("modal closed form needs a homogeneous medium")
+        p0 = self.project(p0)
+        sample = p0[tuple(slice(ax.p_lo, ax.p_hi + 1) for ax in self.axes)]
+        P = sample
+        ksq = np.zeros(())
+        for a, ax in enumerate(self.axes):
+            P = dtt.apply(ax.T1, P, a)
+            shp = [1] * self.ndim
+            shp[a] = -1
+            ksq = ksq + (ax.k1 ** 2).reshape(shp)
+        s = self.c0 * self.dt * np.sqrt(ksq) / 2.0
+        if np.any(s > 1.0):
+            raise ValueError("unstable: c0 dt |k| / 2 > 1")
+        theta = 2.0 * np.arcsin(s)
+        if u_mode == "centred":
+            fac = np.cos(m * theta)
+        elif u_mode == "zero":
+            fac = np.cos(m * theta + theta / 2.0) / np.cos(theta / 2.0)
+        else:
+            raise ValueError(u_mode)
+        Q = P * fac
+        for a, ax in enumerate(self.axes):
+            Q = dtt.apply(ax.T1inv, Q, a)
+        out = np.zeros(self.shape)
+        out[tuple(slice(ax.p_lo, ax.p_hi + 1) for ax in self.axes)] = Q
+        return out
+
+    def cfl_limit(self) -> float:
+        """Largest stable c0 dt / dx: 2 / (dx * max|k|), max|k|^2 = sum over axes of the largest k^2.
+
+        For a Neumann-Neumann axis max k = pi / dx, which gives the 1D limit 2/pi quoted in §4.2.
+        """
+        kmax2 = sum(float(np.max(ax.k1) ** 2) for ax in self.axes)
+        return 2.0 / (self.dx * np.sqrt(kmax2))
+
+
+# -- §5: arbitrary real reflection coefficients by weighted sums of the Neumann/Dirichlet fields ------
+
+# Columns: image-source polarities of the four basic 1D cases (R_L, R_R) = (1,1), (1,-1), (-1,1), (-1,-1);
+# rows: left image, source, right image, doubly reflected image (matrix M of §5).
+IMAGE_MATRIX = np.array([[1, 1, -1, -1],
+                         [1, 1, 1, 1],
+                         [1, -1, 1, -1],
+                         [1, -1, -1, 1]], dtype=np.float64)
+
+# (left, right) boundary pairs in the order of the columns of IMAGE_MATRIX (reflection 1 = Neumann).
+BASIC_CASES = [(NEUMANN, NEUMANN), (NEUMANN, DIRICHLET), (DIRICHLET, NEUMANN), (DIRICHLET, DIRICHLET)]
+
+
+def combination_weights_1d(RL: float, RR: float) -> np.ndarray:
+    """w = (1/4) M^T r with r = [R_L, 1, R_R, R_L R_R] (§5)."""
+    r = np.array([RL, 1.0, RR, RL * RR], dtype=np.float64)
+    return IMAGE_MATRIX.T @ r / 4.0
+
+
+def combination_weights(R_faces) -> dict:
+    """Weights of the 2^(2d) basic fields for per-face reflection coefficients [(R_L, R_R) per axis].
+
+    §5 states the 1D weights and that the same idea extends to d dimensions with 2^(2d) fields; with
+    separable image sources the d-dimensional weight is the product of the per-axis 1D weights.
+    Keys are tuples of (left, right) boundary pairs, one per axis.
+    """
+    per_axis = [combination_weights_1d(RL, RR) for RL, RR in R_faces]
+    out = {}
+    for choice in product(range(4), repeat=len(per_axis)):
+        w = 1.0
+        for a, c in enumerate(choice):
+            w *= per_axis[a][c]
+        out[tuple(BASIC_CASES[c] for c in choice)] = w
+    return out
+
+
+def combine_R(p_dirichlet: np.ndarray, p_neumann: np.ndarray, R: float) -> np.ndarray:
+    """Two-field combination p_R = (1/2)(1+R) p_N + (1/2)(1-R) p_D for one coefficient R on all faces.
+
+    This is the single-reflection restriction of §5: with every face sharing R, the all-Neumann and
+    all-Dirichlet fields carry each singly reflected image with weights whose sum is R.  It is exact
+    only until doubly reflected arrivals (which it weights by 1 instead of R^2).
+    """
+    return 0.5 * (1.0 + R) * np.asarray(p_neumann, np.float64) + 0.5 * (1.0 - R) * np.asarray(p_dirichlet, np.float64)
