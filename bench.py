@@ -1,0 +1,223 @@
+"""Benchmark of the PSTD time-step hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d]
+
+One bench step is one PSTD time step over the whole grid: every axis's velocity update (forward DTT,
+k-space multiply with the type switch, inverse DTT, leapfrog update; one fused contraction kernel per
+axis) followed by every axis's share of the pressure update.  The default workload is the 2D
+256 x 256 box (Dirichlet x faces, Neumann y faces, FP32, CFL 0.3).  The state is resident in HBM before
+the timed region; K steps are timed between device synchronisations.
+
+Printed: one JSON line with grid-point updates/s, the relative L2 error of the final field against the
+FP64 oracle's closed form, the roofline of the dominant kernel (its average duration measured with
+HIP events on the plan's stream) and the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_TFs": 157.3,
+    "fp64_TFs": 78.6,
+    "bf16_TFs": 2500.0,
+}
+
+WORKLOADS = {
+    # name: (builder, precision, default steps, default warmup)
+    "pstd2d": ("pstd2d", "fp32", 2000, 200),
+    "pstd3d": ("pstd3d", "split_bf16", 100, 10),
+    "pstd1d": ("pstd1d", "fp64", 1000, 100),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_00322_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def contraction_cost(shape, axis, which, precision):
+    """Algorithmic flops and bytes of one contraction launch (kernel table).
+
+    Flops: 2*n_in per output point (a dense n_out x n_in operator applied along the axis; three bf16
+    products for split-bf16).  Bytes: the input field read once, the output field read and written once.
+    """
+    n = shape[axis]
+    n_in = n if which == 0 else n - 1
+    n_out = n - 1 if which == 0 else n
+    lines = int(np.prod(shape)) // n
+    esz = 8 if precision == "fp64" else 4
+    flops = 2.0 * n_in * n_out * lines * (3 if precision == "split_bf16" else 1)
+    bytes_ = esz * lines * (n_in + 2 * n_out)
+    return flops, bytes_
+
+
+def time_dominant_kernel(plan, st, reps=50):
+    """Average duration (ms) of each single-contraction launch, timed with events on the plan's stream."""
+    import torch
+    stream = plan._stream
+    out = {}
+    for which in (0, 1):
+        for a in range(plan.ndim):
+            plan.apply_axis(st, a, which)          # warm
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                plan.apply_axis(st, a, which)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[(a, which)] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def load_traffic(workload, key, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != src_hash:
+        return None
+    ent = rec.get("kernels", {}).get(key)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_leg(case, gpu_p, total_steps, budget_s=12.0):
+    """The FP64 oracle on the host: time a bounded run and compare the GPU field with its closed form."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import pstd as opstd
+
+    prob = opstd.Problem(case.shape, case.bcs, case.dx, case.dt, case.c0, rho0=case.rho0)
+    p = prob.project(case.p0)
+    u = prob.initial_velocity(p)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        p, u = prob.step(p, u)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= case.steps:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    ref = prob.modal_solution(case.p0, total_steps)
+    err = float(np.linalg.norm(gpu_p - ref) / np.linalg.norm(ref))
+    base = {"value": case.points * steps / dt, "unit": "grid-point updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d of %d time steps of the same %s workload, FP64 NumPy, direct DST/DCT matrices"
+                      % (steps, case.steps, case.name)}
+    return base, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="pstd2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import Plan
+
+    builder, precision, dsteps, dwarm = WORKLOADS[args.workload]
+    K = dsteps if args.steps is None else args.steps
+    W = dwarm if args.warmup is None else args.warmup
+    case = getattr(workloads, builder)()
+    torch.cuda.set_device(0)
+
+    plan = Plan(case.shape, case.dx, case.dt, case.c0, case.bcs, rho0=case.rho0, precision=precision)
+    st = plan.new_state(case.p0)
+    plan.init_state(st)
+    plan.step(st, W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(st, K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    p_final = st.p.double().cpu().numpy()
+    value = case.points * K / elapsed
+
+    # dominant kernel: the single contraction launch with the largest average duration
+    state_copy = plan.new_state(case.p0)
+    plan.init_state(state_copy)
+    durs = time_dominant_kernel(plan, state_copy)
+    (axis, which), dur_ms = max(durs.items(), key=lambda kv: kv[1])
+    flops, bytes_ = contraction_cost(case.shape, axis, which, precision)
+    gbs = bytes_ / (dur_ms * 1e-3) / 1e9
+    tfs = flops / (dur_ms * 1e-3) / 1e12
+    peak_c = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"], "split_bf16": PEAK["bf16_TFs"]}[precision]
+    ai = flops / bytes_
+    ridge = peak_c * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    src_hash = kernel_source_hash()
+    key = "axis%d_%s" % (axis, "velocity" if which == 0 else "pressure")
+    traffic = load_traffic(args.workload, key, src_hash)
+    if ai < ridge:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak_c, "unit": "TFLOP/s",
+                "frac": round(tfs / peak_c, 4), "traffic": traffic}
+    roof.update({"kernel": key, "avg_ms": round(dur_ms, 5), "algorithmic_bytes": int(bytes_),
+                 "algorithmic_flops": int(flops), "arith_intensity": round(ai, 2)})
+    plan.close()
+
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        cpu, err = cpu_baseline_leg(case, p_final, W + K)
+
+    dtype = {"fp32": "f32", "fp64": "f64", "split_bf16": "bf16x3->f32"}[precision]
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": case.name, "grid": list(case.shape),
+                   "bc": ["%s%s" % ("ND"[l], "ND"[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
+                   "precision": precision, "parallelism": "single-gpu"},
+        "accuracy": {"rel_l2_vs_fp64_oracle": err, "after_steps": W + K,
+                     "tolerance": {"fp32": 1e-5, "fp64": 1e-10, "split_bf16": 1e-3}[precision]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * pstd.h - C ABI of libpstd: the time-step hot path of the sine/cosine-basis PSTD method
+ * (Wise, Jaros, Cox & Treeby, "Pseudospectral time-domain (PSTD) methods for the wave equation:
+ * realising boundary conditions with discrete sine and cosine transforms", arXiv:2005.00322)
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the linear acoustic system of Eq. (wave_eq),
+ *     du/dt = -(1/rho0) dp/dx,   dp/dt = -rho0 c0^2 du/dx,
+ * in a rectangular box whose faces are each sound-hard (Neumann) or sound-soft (Dirichlet), with the
+ * staggered DTT-based scheme of Eq. (dtt_pstd_solution) (1D) and its 2D/3D form (§4.3): per axis a
+ * forward discrete sine/cosine transform, a multiply by +-k with the sine<->cosine type switch of
+ * Table transform_choices, the inverse transform onto the staggered grid, then the leapfrog update.
+ *
+ * Grid layout (all arrays row-major, the LAST axis contiguous):
+ *   - an axis with n pressure nodes has walls on nodes 0 and n-1 (spacing dx, length L = (n-1) dx);
+ *   - p has shape n[0] x ... x n[ndim-1]; p must be 0 on Dirichlet wall nodes (pstd_state_init
+ *     zeroes them and the step keeps them 0);
+ *   - u[a] (velocity along axis a) has the shape of p with n[a] replaced by n[a]-1 and sits at the
+ *     staggered points (j + 1/2) dx of axis a.
+ * A step advances (p^n, u^{n-1/2}) to (p^{n+1}, u^{n+1/2}).
+ *
+ * Conventions: every call returns a pstd_status (0 = success); nothing throws across the ABI.
+ * Device pointers are plain HIP device addresses; the caller owns every buffer it passes in and the
+ * library never frees caller memory.  A plan owns its operator tables and work buffers and runs all
+ * its kernels on the HIP stream given at creation (0 = the null stream); calls return once the work
+ * is enqueued.  A plan is used from one host thread at a time.  pstd_last_error() returns a
+ * thread-local message for the last failing call.
+ */
+#ifndef PSTD_H
+#define PSTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSTD_OK = 0,
+  PSTD_E_INVALID_ARG = -1,  /* null pointer, bad enum, n < 3, non-positive dx/dt/c0/rho0 ...      */
+  PSTD_E_UNSTABLE = -2,     /* c0 dt / dx above 2 / (dx max|k|) (the 2/pi limit of §4.2 in 1D)    */
+  PSTD_E_UNSUPPORTED = -3,  /* size or mode this build does not handle                             */
+  PSTD_E_HIP = -4,          /* a HIP runtime call failed (message in pstd_last_error)              */
+  PSTD_E_OOM = -5,          /* device allocation failed                                            */
+  PSTD_E_NONFINITE = -6     /* the state holds NaN or Inf (pstd_check_finite)                      */
+} pstd_status;
+
+/* Boundary condition of one face (§1: Neumann = sound-hard, Dirichlet = sound-soft). */
+typedef enum { PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1 } pstd_bc;
+
+/* Arithmetic of the transform contractions.  FP64: state and operators in double.  FP32: state and
+ * operators in float, FP32 accumulation.  SPLIT_BF16: float state; each contraction is
+ * A_hi X_hi + A_hi X_lo + A_lo X_hi with bfloat16 hi/lo parts and FP32 accumulation. */
+typedef enum { PSTD_FP64 = 0, PSTD_FP32 = 1, PSTD_SPLIT_BF16 = 2 } pstd_precision;
+
+typedef struct {
+  int32_t ndim;   /* 1, 2 or 3 */
+  int64_t n[3];   /* pressure nodes per axis, both wall nodes included, n >= 3 */
+} pstd_grid;
+
+/* Caller-owned device state.  p and u[0..ndim-1] are double (PSTD_FP64) or float (otherwise). */
+typedef struct {
+  void* p;
+  void* u[3];
+  int64_t step;   /* time-step counter, advanced by pstd_step */
+} pstd_state;
+
+typedef struct pstd_plan_s* pstd_plan;
+
+/* Create a plan: homogeneous medium, rho0 = 1000 kg/m^3, FP32, null stream.
+ * bc_per_face = {x-, x+, y-, y+, z-, z+} (entries beyond 2*ndim are ignored).
+ * Builds, in FP64 on the host, the per-axis operators of Table transform_choices: the velocity
+ * operator G_a = T2^{-1} diag(a1) T1 ((n-1) x n) and the pressure operator D_a = T1^{-1} diag(a2) T2
+ * (n x (n-1)), with the DC/Nyquist entries dropped or zero-padded as in the appendix tables
+ * "Differentiation with staggered grids", folds -dt/rho0 and -dt rho0 c0^2 into them, rounds them to
+ * the plan's precision and copies them to the device.  Returns PSTD_E_UNSTABLE if the time step is
+ * above the stability limit. */
+int pstd_plan_create(const pstd_grid* grid, double dx, double dt, double c0,
+                     const int32_t bc_per_face[6], pstd_plan* out);
+
+/* As pstd_plan_create with density, precision, an optional sound-speed map and a stream.
+ * c0_map_dev: nullable device array of float c0(x) on the p nodes (same shape as p); when given, the
+ * pressure step uses c0(x)^2 pointwise (an extension beyond the paper's homogeneous medium) and c0 is
+ * only used for the stability check (pass the map's maximum).  The map must outlive the plan.
+ * hip_stream: a hipStream_t or NULL. */
+int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0,
+                        const int32_t bc_per_face[6], double rho0, int32_t precision,
+                        const float* c0_map_dev, void* hip_stream, pstd_plan* out);
+
+/* Prepare a caller-filled state: zero p on Dirichlet wall nodes, then set u[a]^{-1/2}.
+ * u_mode 0: u^{-1/2} = +(dt / (2 rho0)) G_a p^0, i.e. particle velocity zero at t = 0 on the
+ *           staggered time grid (the reading of "set to zero, accounting for the staggered grid",
+ *           §4.2);  u_mode 1: u^{-1/2} = 0;  u_mode 2: keep the caller's u.
+ * Sets state->step = 0. */
+int pstd_state_init(pstd_plan plan, pstd_state* state, int32_t u_mode);
+
+/* Advance the state by n_steps >= 0 steps of Eq. (dtt_pstd_solution) (§4.3 for 2D/3D): every u_a from
+ * p^n first, then p^{n+1} from all u_a^{n+1/2}.  Asynchronous on the plan's stream. */
+int pstd_step(pstd_plan plan, pstd_state* state, int64_t n_steps);
+
+/* One term of the step on its own: which = 0 applies the velocity update of axis `axis`,
+ * u_a += -(dt/rho0) G_a p (Eq. (dtt_pstd_solution_a) along that axis); which = 1 applies that axis's share
+ * of the pressure update, p += -(dt rho0 c0^2) D_a u_a (one summand of Eq. (dtt_pstd_solution_b) in the
+ * form of §4.3).  A full step is every which = 0 term followed by every which = 1 term.  One kernel
+ * launch, asynchronous on the plan's stream; state->step is not changed. */
+int pstd_apply_axis(pstd_plan plan, pstd_state* state, int32_t axis, int32_t which);
+
+/* p_out = (1+R)/2 * p_neumann + (1-R)/2 * p_dirichlet, elementwise over count floats.
+ * The single-reflection form of §5's weighted sum of Neumann and Dirichlet fields for one real
+ * reflection coefficient R on every face (exact until doubly reflected arrivals).  p_out may alias
+ * either input.  Asynchronous on hip_stream (NULL = null stream). */
+int pstd_combine_R(const float* p_dirichlet, const float* p_neumann, double R,
+                   float* p_out, int64_t count, void* hip_stream);
+
+/* p_out = sum_i w[i] * fields[i], elementwise over count floats (the general weighted sum of §5;
+ * weights from w = M^T r / 4 per axis).  fields: host array of nfields device pointers.  p_out may
+ * alias fields[0].  Asynchronous on hip_stream. */
+int pstd_combine_fields(const float* const* fields, const double* w, int32_t nfields,
+                        float* p_out, int64_t count, void* hip_stream);
+
+/* Check that p and every u_a are finite.  Synchronises the plan's stream.  Returns PSTD_OK or
+ * PSTD_E_NONFINITE. */
+int pstd_check_finite(pstd_plan plan, const pstd_state* state);
+
+/* Copy the plan's device operators back to the host as double (for inspection and tests).
+ * which: 0 = velocity operator G_a ((n_a-1) x n_a), 1 = pressure operator D_a (n_a x (n_a-1)), both
+ * with the time-step constants folded in and rounded to the plan's precision (SPLIT_BF16 returns
+ * hi + lo).  out must hold the matrix row-major.  Synchronous. */
+int pstd_plan_get_operator(pstd_plan plan, int32_t axis, int32_t which, double* out);
+
+/* Host only (no GPU needed): the unscaled FP64 operator of one axis, exactly as the plan builder forms
+ * it before folding the time-step constants in.  n nodes, boundary pair (bc_left, bc_right), spacing dx.
+ * which 0: velocity operator T2^{-1} diag(a1) T1, (n-1) x n row-major (derivative of p on the
+ * staggered points); which 1: pressure operator T1^{-1} diag(a2) T2, n x (n-1) row-major.  out must
+ * hold the matrix.  Synchronous. */
+int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out);
+
+/* Number of elements of p / of u[axis] for this plan. */
+int64_t pstd_plan_numel(pstd_plan plan, int32_t field /* -1 = p, 0..2 = u[axis] */);
+
+int pstd_plan_destroy(pstd_plan plan);
+
+const char* pstd_status_string(int status);
+const char* pstd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSTD_H */

@@ -93,6 +93,5 @@ def inverse_matrix(kind: str, typ: int, L: int) -> np.ndarray:
 
 def apply(T: np.ndarray, x: np.ndarray, axis: int) -> np.ndarray:
     """Apply a transform matrix along one axis of an nd array (a plain matrix product per line)."""
-    xm = np.moveaxis(x, axis, -1)
-    y = xm @ T.T
-    return np.moveaxis(y, -1, axis)
+    y = np.tensordot(T, x, axes=([1], [axis]))   # one matrix product over all lines
+    return np.moveaxis(y, 0, axis)

@@ -1,0 +1,11 @@
+"""MI355X-native hot path of the sine/cosine-basis PSTD method (arXiv:2005.00322).
+
+The computation runs in the HIP kernels of ``libpstd.so`` (built from ``csrc/`` for gfx950); this
+package only marshals arguments across its C ABI (``include/pstd.h``).  PyTorch supplies device memory
+and the current stream.  There is no CPU fallback: every call raises if the library is missing.
+"""
+from .pstd import (DIRICHLET, NEUMANN, Plan, PstdError, State, axis_operator, combine_R, combine_fields,
+                   lib_path, load_library)
+
+__all__ = ["Plan", "State", "PstdError", "combine_R", "combine_fields", "axis_operator", "NEUMANN", "DIRICHLET",
+           "load_library", "lib_path"]

@@ -1,0 +1,455 @@
+// libpstd C ABI: plan creation (operator tables), state initialisation, stepping, combination.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+
+namespace pstd {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+namespace {
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+float bf16_to_float(uint16_t h) {
+  uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Round the FP64 matrix (M x K, already scaled) to the plan precision and upload it zero padded.
+int upload_operator(pstd_plan_s* P, const std::vector<double>& m, int M, int K, double scale, DevOperator* op) {
+  op->M = M;
+  op->K = K;
+  op->Mp = static_cast<int>(round_up(M, kRowPad));
+  op->Kp = static_cast<int>(round_up(K, kColPad));
+  const size_t cnt = static_cast<size_t>(op->Mp) * op->Kp;
+  const bool want_t = (P->ndim == 1);
+  if (P->prec == PSTD_FP64 || P->prec == PSTD_FP32) {
+    const size_t esz = P->prec == PSTD_FP64 ? 8 : 4;
+    std::vector<unsigned char> host(cnt * esz, 0), hostT(want_t ? cnt * esz : 0, 0);
+    for (int i = 0; i < M; ++i)
+      for (int k = 0; k < K; ++k) {
+        const double v = scale * m[static_cast<size_t>(i) * K + k];
+        const size_t a = static_cast<size_t>(i) * op->Kp + k;
+        const size_t t = static_cast<size_t>(k) * op->Mp + i;
+        if (esz == 8) {
+          reinterpret_cast<double*>(host.data())[a] = v;
+          if (want_t) reinterpret_cast<double*>(hostT.data())[t] = v;
+        } else {
+          reinterpret_cast<float*>(host.data())[a] = static_cast<float>(v);
+          if (want_t) reinterpret_cast<float*>(hostT.data())[t] = static_cast<float>(v);
+        }
+      }
+    if (hipMalloc(&op->data, cnt * esz) != hipSuccess) return fail(PSTD_E_OOM, "hipMalloc of an operator failed");
+    PSTD_HIP(hipMemcpy(op->data, host.data(), cnt * esz, hipMemcpyHostToDevice));
+    if (want_t) {
+      if (hipMalloc(&op->dataT, cnt * esz) != hipSuccess) return fail(PSTD_E_OOM, "hipMalloc of an operator failed");
+      PSTD_HIP(hipMemcpy(op->dataT, hostT.data(), cnt * esz, hipMemcpyHostToDevice));
+    }
+    return PSTD_OK;
+  }
+  // split bf16: hi = bf16(v), lo = bf16(v - hi), both rounded from the FP64 value
+  std::vector<uint16_t> host(2 * cnt, 0);
+  for (int i = 0; i < M; ++i)
+    for (int k = 0; k < K; ++k) {
+      const double v = scale * m[static_cast<size_t>(i) * K + k];
+      const uint16_t hi = bf16_rne(static_cast<float>(v));
+      const uint16_t lo = bf16_rne(static_cast<float>(v - static_cast<double>(bf16_to_float(hi))));
+      host[static_cast<size_t>(i) * op->Kp + k] = hi;
+      host[cnt + static_cast<size_t>(i) * op->Kp + k] = lo;
+    }
+  if (hipMalloc(&op->data, 2 * cnt * 2) != hipSuccess) return fail(PSTD_E_OOM, "hipMalloc of an operator failed");
+  PSTD_HIP(hipMemcpy(op->data, host.data(), 2 * cnt * 2, hipMemcpyHostToDevice));
+  return PSTD_OK;
+}
+
+void free_plan(pstd_plan_s* P) {
+  if (!P) return;
+  for (int a = 0; a < 3; ++a) {
+    if (P->G[a].data) (void)hipFree(P->G[a].data);
+    if (P->G[a].dataT) (void)hipFree(P->G[a].dataT);
+    if (P->D[a].data) (void)hipFree(P->D[a].data);
+    if (P->D[a].dataT) (void)hipFree(P->D[a].dataT);
+  }
+  if (P->c2map) (void)hipFree(P->c2map);
+  if (P->flag) (void)hipFree(P->flag);
+  if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  delete P;
+}
+
+int64_t numel_p(const pstd_plan_s* P) { return P->n[0] * P->n[1] * P->n[2]; }
+int64_t numel_u(const pstd_plan_s* P, int a) { return numel_p(P) / P->n[a] * (P->n[a] - 1); }
+
+// Geometry of the contraction along axis a for a field whose extent along a is `len`.
+void axis_geometry(const pstd_plan_s* P, int a, int64_t* outer, int64_t* inner) {
+  int64_t o = 1, i = 1;
+  for (int b = 0; b < a; ++b) o *= P->n[b];
+  for (int b = a + 1; b < P->ndim; ++b) i *= P->n[b];
+  *outer = o;
+  *inner = i;
+}
+
+hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const void* X, void* Y, double alpha,
+                    double beta, const void* scale, hipStream_t s) {
+  ContractArgs c{};
+  c.A = op.data;
+  c.A_lo = nullptr;
+  c.lda = op.Kp;
+  c.M = op.M;
+  c.K = op.K;
+  c.X = X;
+  c.Y = Y;
+  c.alpha = static_cast<float>(alpha);
+  c.beta = static_cast<float>(beta);
+  c.alpha_d = alpha;
+  c.beta_d = beta;
+  c.scale = scale;
+  int64_t outer, inner;
+  axis_geometry(P, a, &outer, &inner);
+  const bool contiguous = (a == P->ndim - 1);
+  if (contiguous) {
+    c.ncols = outer;
+    c.batch = 1;
+    c.x_bstride = 0;
+    c.y_bstride = 0;
+  } else {
+    c.ncols = inner;
+    c.batch = outer;
+    c.x_bstride = static_cast<int64_t>(op.K) * inner;
+    c.y_bstride = static_cast<int64_t>(op.M) * inner;
+  }
+  if (P->prec == PSTD_FP64) return launch_contract_fp64(c, contiguous, s);
+  if (P->prec == PSTD_FP32) return launch_contract_fp32(c, contiguous, s);
+  c.A_lo = static_cast<const uint16_t*>(op.data) + static_cast<size_t>(op.Mp) * op.Kp;
+  return launch_contract_split(c, contiguous, s);
+}
+
+// Enqueue n steps of the 2D/3D scheme: all velocity contractions, then all pressure contractions.
+hipError_t enqueue_steps(pstd_plan_s* P, pstd_state* st, int64_t nsteps, hipStream_t s) {
+  for (int64_t t = 0; t < nsteps; ++t) {
+    for (int a = 0; a < P->ndim; ++a) {
+      hipError_t e = contract(P, P->G[a], a, st->p, st->u[a], 1.0, 1.0, nullptr, s);
+      if (e != hipSuccess) return e;
+    }
+    for (int a = 0; a < P->ndim; ++a) {
+      hipError_t e = contract(P, P->D[a], a, st->u[a], st->p, 1.0, 1.0, P->c2map, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+constexpr int64_t kGraphChunk = 50;  // steps captured per graph launch
+
+}  // namespace
+}  // namespace pstd
+
+using namespace pstd;
+
+extern "C" {
+
+const char* pstd_status_string(int status) {
+  switch (status) {
+    case PSTD_OK: return "ok";
+    case PSTD_E_INVALID_ARG: return "invalid argument";
+    case PSTD_E_UNSTABLE: return "time step above the stability limit";
+    case PSTD_E_UNSUPPORTED: return "unsupported size or mode";
+    case PSTD_E_HIP: return "HIP runtime error";
+    case PSTD_E_OOM: return "out of device memory";
+    case PSTD_E_NONFINITE: return "non-finite values in the state";
+    default: return "unknown status";
+  }
+}
+
+const char* pstd_last_error(void) { return g_err; }
+
+int pstd_plan_create(const pstd_grid* grid, double dx, double dt, double c0, const int32_t bc_per_face[6],
+                     pstd_plan* out) {
+  return pstd_plan_create_ex(grid, dx, dt, c0, bc_per_face, 1000.0, PSTD_FP32, nullptr, nullptr, out);
+}
+
+int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, const int32_t bc_per_face[6],
+                        double rho0, int32_t precision, const float* c0_map_dev, void* hip_stream, pstd_plan* out) {
+  if (!out) return fail(PSTD_E_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (!grid || !bc_per_face) return fail(PSTD_E_INVALID_ARG, "grid or bc_per_face is null");
+  if (grid->ndim < 1 || grid->ndim > 3) return fail(PSTD_E_INVALID_ARG, "ndim must be 1, 2 or 3");
+  if (!(dx > 0) || !(dt > 0) || !(c0 > 0) || !(rho0 > 0) || !std::isfinite(dx) || !std::isfinite(dt) ||
+      !std::isfinite(c0) || !std::isfinite(rho0))
+    return fail(PSTD_E_INVALID_ARG, "dx, dt, c0 and rho0 must be positive and finite");
+  if (precision < PSTD_FP64 || precision > PSTD_SPLIT_BF16) return fail(PSTD_E_INVALID_ARG, "bad precision");
+  for (int a = 0; a < grid->ndim; ++a) {
+    if (grid->n[a] < 3) return fail(PSTD_E_INVALID_ARG, "axis %d has %lld nodes (need >= 3)", a, (long long)grid->n[a]);
+    if (grid->n[a] > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: %lld nodes above 4097", a, (long long)grid->n[a]);
+    for (int f = 0; f < 2; ++f)
+      if (bc_per_face[2 * a + f] != PSTD_NEUMANN && bc_per_face[2 * a + f] != PSTD_DIRICHLET)
+        return fail(PSTD_E_INVALID_ARG, "bad boundary condition on face %d", 2 * a + f);
+  }
+  if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
+    return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
+  if (grid->ndim == 1 && grid->n[0] > 1365) return fail(PSTD_E_UNSUPPORTED, "1D grids are limited to 1365 nodes");
+  int64_t total = 1;
+  for (int a = 0; a < grid->ndim; ++a) total *= grid->n[a];
+  if (total > (int64_t(1) << 31)) return fail(PSTD_E_UNSUPPORTED, "grid above 2^31 points");
+
+  // stability: c0 dt |k|_max / 2 <= 1 with |k|_max^2 the sum of the per-axis maxima
+  double kmax2 = 0.0;
+  for (int a = 0; a < grid->ndim; ++a) {
+    const AxisTables& t = axis_tables(static_cast<int>(grid->n[a]), axis_case(bc_per_face[2 * a], bc_per_face[2 * a + 1]));
+    kmax2 += (t.kmax / dx) * (t.kmax / dx);
+  }
+  if (c0 * dt * std::sqrt(kmax2) / 2.0 > 1.0)
+    return fail(PSTD_E_UNSTABLE, "c0*dt/dx = %g above the limit %g", c0 * dt / dx, 2.0 / (dx * std::sqrt(kmax2)));
+
+  pstd_plan_s* P = new pstd_plan_s();
+  P->ndim = grid->ndim;
+  for (int a = 0; a < 3; ++a) P->n[a] = a < grid->ndim ? grid->n[a] : 1;
+  for (int f = 0; f < 2 * grid->ndim; ++f) P->bc[f] = bc_per_face[f];
+  P->dx = dx;
+  P->dt = dt;
+  P->c0 = c0;
+  P->rho0 = rho0;
+  P->prec = precision;
+  P->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    free_plan(P);
+    return fail(PSTD_E_HIP, "hipGetDevice failed");
+  }
+
+  // velocity: u += -(dt/rho0) G p ; pressure: p += -(dt rho0 c0^2) D u (c0^2 from the map if given)
+  const double sG = -dt / rho0 / dx;
+  const double sD = -dt * rho0 * (c0_map_dev ? 1.0 : c0 * c0) / dx;
+  for (int a = 0; a < P->ndim; ++a) {
+    const int n = static_cast<int>(P->n[a]);
+    const AxisTables& t = axis_tables(n, axis_case(P->bc[2 * a], P->bc[2 * a + 1]));
+    int st = upload_operator(P, t.G, n - 1, n, sG, &P->G[a]);
+    if (st == PSTD_OK) st = upload_operator(P, t.D, n, n - 1, sD, &P->D[a]);
+    if (st != PSTD_OK) {
+      free_plan(P);
+      return st;
+    }
+  }
+  if (hipMalloc(&P->flag, sizeof(int)) != hipSuccess) {
+    free_plan(P);
+    return fail(PSTD_E_OOM, "hipMalloc failed");
+  }
+  if (c0_map_dev) {
+    if (hipMalloc(&P->c2map, (precision == PSTD_FP64 ? 8 : 4) * total) != hipSuccess) {
+      free_plan(P);
+      return fail(PSTD_E_OOM, "hipMalloc of the c0^2 map failed");
+    }
+    if (launch_square(precision, c0_map_dev, P->c2map, total, P->stream) != hipSuccess) {
+      free_plan(P);
+      return fail(PSTD_E_HIP, "squaring the c0 map failed");
+    }
+  }
+  *out = P;
+  return PSTD_OK;
+}
+
+int pstd_plan_destroy(pstd_plan plan) {
+  if (!plan) return PSTD_OK;
+  if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+  else (void)hipDeviceSynchronize();
+  free_plan(plan);
+  return PSTD_OK;
+}
+
+int64_t pstd_plan_numel(pstd_plan plan, int32_t field) {
+  if (!plan) return -1;
+  if (field < 0) return numel_p(plan);
+  if (field >= plan->ndim) return -1;
+  return numel_u(plan, field);
+}
+
+int pstd_state_init(pstd_plan P, pstd_state* st, int32_t u_mode) {
+  if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state/p");
+  for (int a = 0; a < P->ndim; ++a)
+    if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
+  if (u_mode < 0 || u_mode > 2) return fail(PSTD_E_INVALID_ARG, "u_mode must be 0, 1 or 2");
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int a = 0; a < P->ndim; ++a) {
+    lo[a] = P->bc[2 * a] == PSTD_DIRICHLET;
+    hi[a] = P->bc[2 * a + 1] == PSTD_DIRICHLET;
+  }
+  PSTD_HIP(launch_zero_dirichlet(P->prec, st->p, P->ndim, P->n, lo, hi, P->stream));
+  for (int a = 0; a < P->ndim; ++a) {
+    if (u_mode == 2) break;
+    if (u_mode == 1) {
+      PSTD_HIP(launch_fill_zero(P->prec, st->u[a], numel_u(P, a), P->stream));
+      continue;
+    }
+    // u^{-1/2} = +(dt/(2 rho0)) G p = -1/2 * (folded operator) p  (beta = 0: u is not read)
+    PSTD_HIP(contract(P, P->G[a], a, st->p, st->u[a], -0.5, 0.0, nullptr, P->stream));
+  }
+  st->step = 0;
+  return PSTD_OK;
+}
+
+int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
+  if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state/p");
+  for (int a = 0; a < P->ndim; ++a)
+    if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
+  if (n_steps < 0) return fail(PSTD_E_INVALID_ARG, "n_steps < 0");
+  if (n_steps == 0) return PSTD_OK;
+  if (P->ndim == 1) {
+    PSTD_HIP(launch_step1d(P->prec, P->G[0], P->D[0], st->p, st->u[0], static_cast<int>(P->n[0]), n_steps,
+                           P->c2map, P->stream));
+    st->step += n_steps;
+    return PSTD_OK;
+  }
+  // chunks of kGraphChunk steps replay one captured graph; the remainder is launched directly
+  int64_t left = n_steps;
+  const bool same_key = P->graph_exec && P->graph_key[0] == st->p && P->graph_key[1] == st->u[0] &&
+                        P->graph_key[2] == st->u[1] && P->graph_key[3] == st->u[2];
+  if (left >= kGraphChunk && !same_key) {
+    if (P->graph_exec) {
+      (void)hipGraphExecDestroy(P->graph_exec);
+      P->graph_exec = nullptr;
+    }
+    if (P->graph) {
+      (void)hipGraphDestroy(P->graph);
+      P->graph = nullptr;
+    }
+    hipStream_t cs;
+    PSTD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = enqueue_steps(P, st, kGraphChunk, cs);
+      e = hipStreamEndCapture(cs, &P->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(PSTD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    P->graph_key[0] = st->p;
+    P->graph_key[1] = st->u[0];
+    P->graph_key[2] = st->u[1];
+    P->graph_key[3] = st->u[2];
+  }
+  while (left >= kGraphChunk) {
+    PSTD_HIP(hipGraphLaunch(P->graph_exec, P->stream));
+    left -= kGraphChunk;
+  }
+  if (left > 0) PSTD_HIP(enqueue_steps(P, st, left, P->stream));
+  st->step += n_steps;
+  return PSTD_OK;
+}
+
+int pstd_apply_axis(pstd_plan P, pstd_state* st, int32_t axis, int32_t which) {
+  if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state/p");
+  if (axis < 0 || axis >= P->ndim || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  if (!st->u[axis]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", axis);
+  if (which == 0) PSTD_HIP(contract(P, P->G[axis], axis, st->p, st->u[axis], 1.0, 1.0, nullptr, P->stream));
+  else PSTD_HIP(contract(P, P->D[axis], axis, st->u[axis], st->p, 1.0, 1.0, P->c2map, P->stream));
+  return PSTD_OK;
+}
+
+int pstd_combine_R(const float* p_dirichlet, const float* p_neumann, double R, float* p_out, int64_t count,
+                   void* hip_stream) {
+  if (count < 0) return fail(PSTD_E_INVALID_ARG, "count < 0");
+  if (!std::isfinite(R)) return fail(PSTD_E_INVALID_ARG, "R must be finite");
+  if (count == 0) return PSTD_OK;
+  if (!p_dirichlet || !p_neumann || !p_out) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  const float* f[2] = {p_neumann, p_dirichlet};
+  const float w[2] = {static_cast<float>(0.5 * (1.0 + R)), static_cast<float>(0.5 * (1.0 - R))};
+  PSTD_HIP(launch_combine(f, w, 2, p_out, count, static_cast<hipStream_t>(hip_stream)));
+  return PSTD_OK;
+}
+
+int pstd_combine_fields(const float* const* fields, const double* w, int32_t nfields, float* p_out, int64_t count,
+                        void* hip_stream) {
+  if (!fields || !w || !p_out) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  if (nfields < 1 || nfields > 64) return fail(PSTD_E_INVALID_ARG, "nfields must be 1..64");
+  if (count < 0) return fail(PSTD_E_INVALID_ARG, "count < 0");
+  for (int i = 0; i < nfields; ++i)
+    if (!fields[i]) return fail(PSTD_E_INVALID_ARG, "fields[%d] is null", i);
+  if (count == 0) return PSTD_OK;
+  float wf[64];
+  for (int i = 0; i < nfields; ++i) wf[i] = static_cast<float>(w[i]);
+  PSTD_HIP(launch_combine(fields, wf, nfields, p_out, count, static_cast<hipStream_t>(hip_stream)));
+  return PSTD_OK;
+}
+
+int pstd_check_finite(pstd_plan P, const pstd_state* st) {
+  if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state");
+  PSTD_HIP(hipMemsetAsync(P->flag, 0, sizeof(int), P->stream));
+  PSTD_HIP(launch_nonfinite(P->prec, st->p, numel_p(P), P->flag, P->stream));
+  for (int a = 0; a < P->ndim; ++a)
+    if (st->u[a]) PSTD_HIP(launch_nonfinite(P->prec, st->u[a], numel_u(P, a), P->flag, P->stream));
+  int h = 0;
+  PSTD_HIP(hipMemcpyAsync(&h, P->flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  PSTD_HIP(hipStreamSynchronize(P->stream));
+  return h ? fail(PSTD_E_NONFINITE, "non-finite value in the state") : PSTD_OK;
+}
+
+int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out) {
+  if (!out) return fail(PSTD_E_INVALID_ARG, "out is null");
+  if (n < 3 || n > 4097) return fail(PSTD_E_INVALID_ARG, "n must be in [3, 4097]");
+  if ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) || (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET))
+    return fail(PSTD_E_INVALID_ARG, "bad boundary condition");
+  if (!(dx > 0) || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad dx or which");
+  const AxisTables& t = axis_tables(static_cast<int>(n), axis_case(bc_left, bc_right));
+  const std::vector<double>& m = which == 0 ? t.G : t.D;
+  for (size_t i = 0; i < m.size(); ++i) out[i] = m[i] / dx;
+  return PSTD_OK;
+}
+
+int pstd_plan_get_operator(pstd_plan P, int32_t axis, int32_t which, double* out) {
+  if (!P || !out) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  if (axis < 0 || axis >= P->ndim || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  const DevOperator& op = which == 0 ? P->G[axis] : P->D[axis];
+  const size_t cnt = static_cast<size_t>(op.Mp) * op.Kp;
+  if (P->prec == PSTD_FP64) {
+    std::vector<double> h(cnt);
+    PSTD_HIP(hipMemcpy(h.data(), op.data, cnt * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < op.M; ++i)
+      for (int k = 0; k < op.K; ++k) out[static_cast<size_t>(i) * op.K + k] = h[static_cast<size_t>(i) * op.Kp + k];
+  } else if (P->prec == PSTD_FP32) {
+    std::vector<float> h(cnt);
+    PSTD_HIP(hipMemcpy(h.data(), op.data, cnt * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < op.M; ++i)
+      for (int k = 0; k < op.K; ++k) out[static_cast<size_t>(i) * op.K + k] = h[static_cast<size_t>(i) * op.Kp + k];
+  } else {
+    std::vector<uint16_t> h(2 * cnt);
+    PSTD_HIP(hipMemcpy(h.data(), op.data, cnt * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < op.M; ++i)
+      for (int k = 0; k < op.K; ++k) {
+        const size_t a = static_cast<size_t>(i) * op.Kp + k;
+        out[static_cast<size_t>(i) * op.K + k] =
+            static_cast<double>(bf16_to_float(h[a])) + static_cast<double>(bf16_to_float(h[cnt + a]));
+      }
+  }
+  return PSTD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations shared by the libpstd sources (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pstd.h"
+
+namespace pstd {
+
+// ---- error reporting ------------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+int fail(int status, const char* fmt, ...);
+
+#define PSTD_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::pstd::fail(PSTD_E_HIP, "%s failed: %s (%s:%d)", #expr,                    \
+                          hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+// ---- host operator tables (tables.cpp) ------------------------------------------------------------
+// Per-axis boundary case of Table transform_choices.
+enum AxisCase { CASE_NN = 0, CASE_ND = 1, CASE_DN = 2, CASE_DD = 3 };
+
+inline AxisCase axis_case(int left, int right) {
+  return static_cast<AxisCase>(2 * (left == PSTD_DIRICHLET) + (right == PSTD_DIRICHLET));
+}
+
+// Unscaled FP64 operators of one axis for dx = 1 (scale by 1/dx):
+//   G: (n-1) x n row-major, velocity operator T2^{-1} diag(a1) T1
+//   D: n x (n-1) row-major, pressure operator T1^{-1} diag(a2) T2
+struct AxisTables {
+  int n = 0;
+  AxisCase c = CASE_NN;
+  std::vector<double> G, D;
+  double kmax = 0.0;  // largest |k| the pressure basis carries (dx = 1)
+};
+
+// Returns a cached table (built once per (n, case) in the process).
+const AxisTables& axis_tables(int n, AxisCase c);
+
+// ---- device helpers ------------------------------------------------------------------------------
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Padding of every device operator matrix: rows to a multiple of kRowPad, columns to kColPad.
+constexpr int kRowPad = 128;
+constexpr int kColPad = 64;
+
+// One operator (an M x K row-major matrix, zero padded) in the precision of its plan.
+struct DevOperator {
+  int M = 0, K = 0;        // logical size
+  int Mp = 0, Kp = 0;      // padded size (row stride = Kp)
+  void* data = nullptr;    // FP64: double[Mp*Kp]; FP32: float[Mp*Kp]; SPLIT: bf16 hi[Mp*Kp] then lo[Mp*Kp]
+  void* dataT = nullptr;   // 1D plans: transposed copy, Kp x Mp (row stride Mp)
+};
+
+struct ContractArgs {
+  const void* A;        // operator, row-major, row stride lda, zero padded
+  const void* A_lo;     // SPLIT_BF16 only: low part
+  int lda;
+  int M, K;             // output length and input length along the contracted axis
+  const void* X;        // input field
+  void* Y;              // output field (read-modify-write)
+  int64_t ncols;        // strided: contiguous extent C; contiguous: number of rows R
+  int64_t batch;        // strided: number of outer blocks; contiguous: 1
+  int64_t x_bstride;    // strided: elements between outer blocks of X (= K*C)
+  int64_t y_bstride;    // strided: elements between outer blocks of Y (= M*C)
+  float alpha, beta;    // Y = beta*Y + alpha * scale * (A X)
+  double alpha_d, beta_d;
+  const void* scale;    // optional per-point factor with Y's layout (c0(x)^2 map, state dtype), may be null
+};
+
+// Launchers (kernels_*.hip).  contiguous = the contracted axis is the last (unit-stride) one.
+hipError_t launch_contract_fp32(const ContractArgs& a, bool contiguous, hipStream_t s);
+hipError_t launch_contract_fp64(const ContractArgs& a, bool contiguous, hipStream_t s);
+hipError_t launch_contract_split(const ContractArgs& a, bool contiguous, hipStream_t s);
+hipError_t launch_step1d(int prec, const DevOperator& G, const DevOperator& D, void* p, void* u, int n,
+                         int64_t steps, const void* scale, hipStream_t s);
+hipError_t launch_zero_dirichlet(int prec, void* p, int ndim, const int64_t* n, const int* dir_lo,
+                                 const int* dir_hi, hipStream_t s);
+hipError_t launch_fill_zero(int prec, void* x, int64_t count, hipStream_t s);
+hipError_t launch_square(int prec, const float* in, void* out, int64_t count, hipStream_t s);
+hipError_t launch_combine(const float* const* f, const float* w, int nf, float* out, int64_t count,
+                          hipStream_t s);
+hipError_t launch_nonfinite(int prec, const void* x, int64_t count, int* flag, hipStream_t s);
+
+}  // namespace pstd
+
+// ---- the plan --------------------------------------------------------------------------------------
+struct pstd_plan_s {
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  double dx = 0, dt = 0, c0 = 0, rho0 = 1000.0;
+  int prec = PSTD_FP32;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  pstd::DevOperator G[3], D[3];
+  void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
+  int* flag = nullptr;         // device int for reductions (owned)
+  // captured step graphs
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int64_t graph_steps = 0;
+  void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+};

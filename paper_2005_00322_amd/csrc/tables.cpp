@@ -1,0 +1,192 @@
+// FP64 host construction of the per-axis PSTD operators.
+//
+// For one axis with n pressure nodes (walls on nodes 0 and n-1, implied period M = 2(n-1)) and the
+// boundary pair of Table transform_choices, the velocity step of Eq. (dtt_pstd_solution_a) applies
+//     G = T2^{-1} R12 diag(a1 k) T1            (p nodes -> staggered points)
+// and the pressure step of Eq. (dtt_pstd_solution_b) applies
+//     D = T1^{-1} R21 diag(a2 k) T2            (staggered points -> p nodes),
+// where T1/T2 are the FFTW-convention DCT/DST of §3.2, T^{-1} = T_pair / M per Eq.
+// (inverse_transforms), k_n are the wavenumbers of Table DTT_wavenumber_groups and R12/R21 move the
+// k-space entries between the two transforms' wavenumber ranges (dropping or zero-filling the DC and
+// Nyquist entries, appendix tables "Differentiation with staggered grids").  The product is formed once
+// per (n, case) in double precision; the GPU then applies the collapsed matrices as one contraction
+// per axis, which is the same linear map as the three-stage recipe.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "common.h"
+
+namespace pstd {
+namespace {
+
+enum Kind { COS = 0, SIN = 1 };
+
+struct Transform {
+  Kind kind;
+  int type;
+};
+
+// FFTW REDFT/RODFT definitions (unnormalised): entry (k, j) of the length-L forward transform.
+double dtt_entry(Transform t, int L, int k, int j) {
+  const double pi = M_PI;
+  if (t.kind == COS) {
+    switch (t.type) {
+      case 1:  // REDFT00
+        if (j == 0) return 1.0;
+        if (j == L - 1) return (k % 2) ? -1.0 : 1.0;
+        return 2.0 * std::cos(pi * j * k / (L - 1));
+      case 2:  // REDFT10
+        return 2.0 * std::cos(pi * (j + 0.5) * k / L);
+      case 3:  // REDFT01
+        if (j == 0) return 1.0;
+        return 2.0 * std::cos(pi * j * (k + 0.5) / L);
+      default:  // REDFT11
+        return 2.0 * std::cos(pi * (j + 0.5) * (k + 0.5) / L);
+    }
+  }
+  switch (t.type) {
+    case 1:  // RODFT00
+      return 2.0 * std::sin(pi * (j + 1.0) * (k + 1.0) / (L + 1));
+    case 2:  // RODFT10
+      return 2.0 * std::sin(pi * (j + 0.5) * (k + 1.0) / L);
+    case 3:  // RODFT01
+      if (j == L - 1) return (k % 2) ? -1.0 : 1.0;
+      return 2.0 * std::sin(pi * (j + 1.0) * (k + 0.5) / L);
+    default:  // RODFT11
+      return 2.0 * std::sin(pi * (j + 0.5) * (k + 0.5) / L);
+  }
+}
+
+// Logical period of a length-L sample (Table DTT_wavenumber_groups).
+int dtt_period(Transform t, int L) {
+  if (t.type == 1) return t.kind == COS ? 2 * (L - 1) : 2 * (L + 1);
+  return 2 * L;
+}
+
+// Eq. (inverse_transforms) for types 1..4: the inverse of T_j is T_pair / M.
+Transform inverse_partner(Transform t) {
+  if (t.type == 2) return {t.kind, 3};
+  if (t.type == 3) return {t.kind, 2};
+  return t;
+}
+
+// Wavenumber index n of output entry m (Table DTT_wavenumber_groups): DST-I/II start at n = 1.
+int wave_index(Transform t, int m) { return (t.kind == SIN && t.type <= 2) ? m + 1 : m; }
+bool antiperiodic(Transform t) { return t.type >= 3; }
+
+struct CaseInfo {
+  Transform T1, T2;
+  double a1, a2;
+};
+
+// Table transform_choices.
+CaseInfo case_info(AxisCase c) {
+  switch (c) {
+    case CASE_NN: return {{COS, 1}, {SIN, 2}, -1.0, +1.0};
+    case CASE_ND: return {{COS, 3}, {SIN, 4}, -1.0, +1.0};
+    case CASE_DN: return {{SIN, 3}, {COS, 4}, +1.0, -1.0};
+    default:      return {{SIN, 1}, {COS, 2}, +1.0, -1.0};
+  }
+}
+
+std::vector<double> dense(Transform t, int L) {
+  std::vector<double> T(static_cast<size_t>(L) * L);
+  for (int k = 0; k < L; ++k)
+    for (int j = 0; j < L; ++j) T[static_cast<size_t>(k) * L + j] = dtt_entry(t, L, k, j);
+  return T;
+}
+
+// out (Lo x Li) = Inv (Lo x Lo, = partner(Tout)/M) * S (Lo x Li), rows split across threads.
+void matmul(const std::vector<double>& A, const std::vector<double>& B, std::vector<double>& C, int Mr,
+            int Kc, int Nc) {
+  C.assign(static_cast<size_t>(Mr) * Nc, 0.0);
+  auto work = [&](int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+      double* c = &C[static_cast<size_t>(i) * Nc];
+      for (int k = 0; k < Kc; ++k) {
+        const double a = A[static_cast<size_t>(i) * Kc + k];
+        if (a == 0.0) continue;
+        const double* b = &B[static_cast<size_t>(k) * Nc];
+        for (int j = 0; j < Nc; ++j) c[j] += a * b[j];
+      }
+    }
+  };
+  const int64_t flops = static_cast<int64_t>(Mr) * Kc * Nc;
+  unsigned nt = flops > (1 << 22) ? std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1u;
+  if (nt == 1) {
+    work(0, Mr);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    int r0 = static_cast<int>(static_cast<int64_t>(Mr) * t / nt);
+    int r1 = static_cast<int>(static_cast<int64_t>(Mr) * (t + 1) / nt);
+    th.emplace_back(work, r0, r1);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Build  Out = Tout^{-1} * Reindex(diag(sign*k) * Tin)  as an (Lout x Lin) matrix.
+std::vector<double> collapsed(Transform Tin, int Lin, Transform Tout, int Lout, double sign, int M) {
+  std::vector<double> Fin = dense(Tin, Lin);
+  // k-space matrix with the rows re-indexed from Tin's wavenumber range onto Tout's.
+  std::vector<double> S(static_cast<size_t>(Lout) * Lin, 0.0);
+  const double shift = antiperiodic(Tin) ? 0.5 : 0.0;
+  for (int mo = 0; mo < Lout; ++mo) {
+    const int nw = wave_index(Tout, mo);
+    int mi = -1;
+    for (int m = 0; m < Lin; ++m)
+      if (wave_index(Tin, m) == nw) { mi = m; break; }
+    if (mi < 0) continue;  // wavenumber absent from the forward range: zero entry
+    const double k = 2.0 * M_PI * (nw + shift) / M;  // dx = 1
+    for (int j = 0; j < Lin; ++j) S[static_cast<size_t>(mo) * Lin + j] = sign * k * Fin[static_cast<size_t>(mi) * Lin + j];
+  }
+  std::vector<double> Inv = dense(inverse_partner(Tout), Lout);
+  for (double& v : Inv) v /= M;
+  std::vector<double> Out;
+  matmul(Inv, S, Out, Lout, Lout, Lin);
+  return Out;
+}
+
+std::mutex g_cache_mu;
+std::map<std::pair<int, int>, AxisTables> g_cache;
+
+}  // namespace
+
+const AxisTables& axis_tables(int n, AxisCase c) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto key = std::make_pair(n, static_cast<int>(c));
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) return it->second;
+
+  const CaseInfo ci = case_info(c);
+  const bool left_d = (c == CASE_DN || c == CASE_DD);
+  const bool right_d = (c == CASE_ND || c == CASE_DD);
+  const int p_lo = left_d ? 1 : 0;
+  const int p_hi = right_d ? n - 2 : n - 1;
+  const int Lp = p_hi - p_lo + 1;
+  const int Lu = n - 1;
+  const int M = 2 * (n - 1);
+
+  AxisTables t;
+  t.n = n;
+  t.c = c;
+  // velocity operator: p sample (Lp) -> u (Lu)
+  std::vector<double> g = collapsed(ci.T1, Lp, ci.T2, Lu, ci.a1, M);
+  // pressure operator: u (Lu) -> p sample (Lp)
+  std::vector<double> d = collapsed(ci.T2, Lu, ci.T1, Lp, ci.a2, M);
+  t.G.assign(static_cast<size_t>(Lu) * n, 0.0);
+  t.D.assign(static_cast<size_t>(n) * Lu, 0.0);
+  for (int i = 0; i < Lu; ++i)
+    for (int j = 0; j < Lp; ++j) t.G[static_cast<size_t>(i) * n + (p_lo + j)] = g[static_cast<size_t>(i) * Lp + j];
+  for (int i = 0; i < Lp; ++i)
+    for (int j = 0; j < Lu; ++j) t.D[static_cast<size_t>(p_lo + i) * Lu + j] = d[static_cast<size_t>(i) * Lu + j];
+  // largest wavenumber of the pressure basis
+  const double shift = antiperiodic(ci.T1) ? 0.5 : 0.0;
+  t.kmax = 2.0 * M_PI * (wave_index(ci.T1, Lp - 1) + shift) / M;
+  return g_cache.emplace(key, std::move(t)).first->second;
+}
+
+}  // namespace pstd

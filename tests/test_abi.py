@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI (no GPU): the library loads and exports every declared symbol, its FP64 host
+tables equal the oracle's operators formed independently, and argument errors are reported before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import pstd as opstd
+from paper_2005_00322_amd import _lib
+from paper_2005_00322_amd.pstd import axis_operator
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+N, D = opstd.NEUMANN, opstd.DIRICHLET
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(pstd_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert names <= set(_lib.SIGNATURES), names - set(_lib.SIGNATURES)
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.pstd_status_string(code)
+    assert lib.pstd_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("bc", [(N, N), (N, D), (D, N), (D, D)])
+@pytest.mark.parametrize("n", [3, 4, 17, 64, 129, 384])
+def test_host_tables_match_oracle(bc, n):
+    dx = 1e-4
+    ax = opstd.Axis(n, bc[0], bc[1], dx)
+    G = axis_operator(n, bc[0], bc[1], dx, 0)
+    Dm = axis_operator(n, bc[0], bc[1], dx, 1)
+    scale = np.pi / dx
+    assert np.max(np.abs(G - ax.grad_matrix())) < 2e-13 * scale
+    assert np.max(np.abs(Dm - ax.div_matrix())) < 2e-13 * scale
+
+
+def _grid(shape):
+    g = _lib.Grid()
+    g.ndim = len(shape)
+    for a, s in enumerate(shape):
+        g.n[a] = s
+    return g
+
+
+def _faces(*f):
+    arr = (C.c_int32 * 6)()
+    for i, v in enumerate(f):
+        arr[i] = v
+    return arr
+
+
+def test_argument_errors_need_no_device():
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.pstd_plan_create(C.byref(_grid((10, 10))), 1e-4, 1e-8, 1500.0, _faces(0, 0, 0, 0), None) == _lib.E_INVALID_ARG
+    g0 = _lib.Grid()
+    g0.ndim = 0
+    assert lib.pstd_plan_create(C.byref(g0), 1e-4, 1e-8, 1500.0, _faces(), C.byref(h)) == _lib.E_INVALID_ARG
+    assert lib.pstd_plan_create(C.byref(_grid((2, 10))), 1e-4, 1e-8, 1500.0, _faces(), C.byref(h)) == _lib.E_INVALID_ARG
+    assert lib.pstd_plan_create(C.byref(_grid((10,))), -1e-4, 1e-8, 1500.0, _faces(), C.byref(h)) == _lib.E_INVALID_ARG
+    assert lib.pstd_plan_create(C.byref(_grid((10,))), 1e-4, 1e-8, 1500.0, _faces(0, 7), C.byref(h)) == _lib.E_INVALID_ARG
+    assert lib.pstd_plan_create(C.byref(_grid((5000,))), 1e-4, 1e-8, 1500.0, _faces(), C.byref(h)) == _lib.E_UNSUPPORTED
+    assert b"nodes" in lib.pstd_last_error()
+
+
+@pytest.mark.parametrize("shape,bcs", [((65,), (N, N)), ((33, 40), (N, N, D, N)), ((20, 20, 20), (N, D, D, D, N, N))])
+def test_stability_limit_enforced(shape, bcs):
+    lib = _lib.load()
+    dx, c0 = 1e-4, 1500.0
+    prob = opstd.Problem(shape, tuple(zip(bcs[0::2], bcs[1::2])), dx, 1e-9, c0)
+    limit = prob.cfl_limit()
+    h = C.c_void_p()
+    dt_bad = 1.001 * limit * dx / c0
+    assert lib.pstd_plan_create(C.byref(_grid(shape)), dx, dt_bad, c0, _faces(*bcs), C.byref(h)) == _lib.E_UNSTABLE
+    if len(shape) == 1:
+        assert abs(limit - 2.0 / np.pi) < 1e-12     # §4.2's 1D limit for Neumann at both ends
