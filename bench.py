@@ -67,13 +67,40 @@ def contraction_cost(shape, axis, which, precision):
     return flops, bytes_
 
 
-def time_dominant_kernel(plan, st, reps=50):
-    """Average duration (ms) of each single-contraction launch, timed with events on the plan's stream."""
+def phase_cost(shape, which, precision):
+    """Algorithmic flops and bytes of one fused phase launch (every axis at once).
+
+    Velocity phase: every axis's contraction; p read once, each u_a read and written once.
+    Pressure phase: every axis's contraction; each u_a read once, p read and written once.
+    """
+    flops = 0.0
+    esz = 8 if precision == "fp64" else 4
+    pts = int(np.prod(shape))
+    u_pts = [pts // n * (n - 1) for n in shape]
+    for a in range(len(shape)):
+        flops += contraction_cost(shape, a, which, precision)[0]
+    if which == 0:
+        bytes_ = esz * (pts + 2 * sum(u_pts))
+    else:
+        bytes_ = esz * (sum(u_pts) + 2 * pts)
+    return flops, bytes_
+
+
+def uses_fused_path(shape, precision):
+    """Mirrors the library's automatic path choice (2D FP32 grids up to 512 x 512 use two fused kernels)."""
+    return len(shape) == 2 and precision == "fp32" and max(shape) <= 512
+
+
+def time_dominant_kernel(plan, st, fused, reps=50):
+    """Average duration (ms) of each kernel launch of the step, timed with events on the plan's stream.
+
+    Keys are (axis, which); axis -1 is a fused phase kernel covering every axis.
+    """
     import torch
     stream = plan._stream
     out = {}
     for which in (0, 1):
-        for a in range(plan.ndim):
+        for a in ([-1] if fused else range(plan.ndim)):
             plan.apply_axis(st, a, which)          # warm
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -167,16 +194,20 @@ def main():
     # dominant kernel: the single contraction launch with the largest average duration
     state_copy = plan.new_state(case.p0)
     plan.init_state(state_copy)
-    durs = time_dominant_kernel(plan, state_copy)
+    fused = uses_fused_path(case.shape, precision)
+    durs = time_dominant_kernel(plan, state_copy, fused)
     (axis, which), dur_ms = max(durs.items(), key=lambda kv: kv[1])
-    flops, bytes_ = contraction_cost(case.shape, axis, which, precision)
+    if axis < 0:
+        flops, bytes_ = phase_cost(case.shape, which, precision)
+    else:
+        flops, bytes_ = contraction_cost(case.shape, axis, which, precision)
     gbs = bytes_ / (dur_ms * 1e-3) / 1e9
     tfs = flops / (dur_ms * 1e-3) / 1e12
     peak_c = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"], "split_bf16": PEAK["bf16_TFs"]}[precision]
     ai = flops / bytes_
     ridge = peak_c * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     src_hash = kernel_source_hash()
-    key = "axis%d_%s" % (axis, "velocity" if which == 0 else "pressure")
+    key = ("fused" if axis < 0 else "axis%d" % axis) + "_" + ("velocity" if which == 0 else "pressure")
     traffic = load_traffic(args.workload, key, src_hash)
     if ai < ridge:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",

@@ -98,11 +98,21 @@ int pstd_state_init(pstd_plan plan, pstd_state* state, int32_t u_mode);
  * p^n first, then p^{n+1} from all u_a^{n+1/2}.  Asynchronous on the plan's stream. */
 int pstd_step(pstd_plan plan, pstd_state* state, int64_t n_steps);
 
+/* Execution path of pstd_step.  AUTO picks FUSED for 2D FP32 grids of at most 512 x 512 nodes (two
+ * kernels per step: every velocity tile, then every pressure tile with both axes' terms) and PER_AXIS
+ * otherwise (one contraction kernel per axis and half step).  Both replay captured HIP graphs and
+ * compute the same step; the choice only changes speed and rounding order. */
+typedef enum { PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2 } pstd_path;
+
+/* Select the execution path of later pstd_step calls.  PSTD_E_UNSUPPORTED if the plan cannot use it. */
+int pstd_plan_set_path(pstd_plan plan, int32_t path);
+
 /* One term of the step on its own: which = 0 applies the velocity update of axis `axis`,
  * u_a += -(dt/rho0) G_a p (Eq. (dtt_pstd_solution_a) along that axis); which = 1 applies that axis's share
  * of the pressure update, p += -(dt rho0 c0^2) D_a u_a (one summand of Eq. (dtt_pstd_solution_b) in the
- * form of §4.3).  A full step is every which = 0 term followed by every which = 1 term.  One kernel
- * launch, asynchronous on the plan's stream; state->step is not changed. */
+ * form of §4.3).  A full step is every which = 0 term followed by every which = 1 term.  axis = -1
+ * applies the whole phase (every axis) the way pstd_step does it: one kernel on the FUSED path, one per
+ * axis otherwise.  Asynchronous on the plan's stream; state->step is not changed. */
 int pstd_apply_axis(pstd_plan plan, pstd_state* state, int32_t axis, int32_t which);
 
 /* p_out = (1+R)/2 * p_neumann + (1-R)/2 * p_dirichlet, elementwise over count floats.

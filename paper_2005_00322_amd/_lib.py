@@ -51,6 +51,7 @@ SIGNATURES = {
                                       C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pstd_state_init": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32]),
     "pstd_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int64]),
+    "pstd_plan_set_path": (C.c_int, [C.c_void_p, C.c_int32]),
     "pstd_apply_axis": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32, C.c_int32]),
     "pstd_combine_R": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "pstd_combine_fields": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.c_int32, C.c_void_p,

@@ -153,8 +153,19 @@ hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const vo
   return launch_contract_split(c, contiguous, s);
 }
 
-// Enqueue n steps of the 2D/3D scheme: all velocity contractions, then all pressure contractions.
+bool use_fused2d(const pstd_plan_s* P) {
+  return P->ndim == 2 && P->prec == PSTD_FP32 && P->path != PSTD_PATH_PER_AXIS &&
+         phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]));
+}
+
+// Enqueue n steps of the 2D/3D scheme: all velocity contractions, then all pressure contractions
+// (two fused phase kernels per step for small 2D FP32 plans, one kernel per axis and phase otherwise).
 hipError_t enqueue_steps(pstd_plan_s* P, pstd_state* st, int64_t nsteps, hipStream_t s) {
+  if (use_fused2d(P))
+    return launch_phase2d(P->G[0], P->G[1], P->D[0], P->D[1], static_cast<float*>(st->p),
+                          static_cast<float*>(st->u[0]), static_cast<float*>(st->u[1]),
+                          static_cast<const float*>(P->c2map), static_cast<int>(P->n[0]), static_cast<int>(P->n[1]),
+                          nsteps, s);
   for (int64_t t = 0; t < nsteps; ++t) {
     for (int a = 0; a < P->ndim; ++a) {
       hipError_t e = contract(P, P->G[a], a, st->p, st->u[a], 1.0, 1.0, nullptr, s);
@@ -220,6 +231,8 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   int64_t total = 1;
   for (int a = 0; a < grid->ndim; ++a) total *= grid->n[a];
   if (total > (int64_t(1) << 31)) return fail(PSTD_E_UNSUPPORTED, "grid above 2^31 points");
+  if (precision == PSTD_SPLIT_BF16 && 4 * total >= (int64_t(1) << 31))
+    return fail(PSTD_E_UNSUPPORTED, "split-bf16 plans need fields below 2 GiB (32-bit buffer offsets)");
 
   // stability: c0 dt |k|_max / 2 <= 1 with |k|_max^2 the sum of the per-axis maxima
   double kmax2 = 0.0;
@@ -365,9 +378,44 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
   return PSTD_OK;
 }
 
+int pstd_plan_set_path(pstd_plan P, int32_t path) {
+  if (!P) return fail(PSTD_E_INVALID_ARG, "null plan");
+  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_FUSED) return fail(PSTD_E_INVALID_ARG, "bad path");
+  if (path == PSTD_PATH_FUSED &&
+      !(P->ndim == 2 && P->prec == PSTD_FP32 &&
+        phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]))))
+    return fail(PSTD_E_UNSUPPORTED, "the fused path needs a 2D FP32 plan of at most 512 x 512 nodes");
+  P->path = path;
+  if (P->graph_exec) {  // a captured graph may belong to the other path
+    (void)hipGraphExecDestroy(P->graph_exec);
+    P->graph_exec = nullptr;
+  }
+  if (P->graph) {
+    (void)hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  return PSTD_OK;
+}
+
 int pstd_apply_axis(pstd_plan P, pstd_state* st, int32_t axis, int32_t which) {
   if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state/p");
-  if (axis < 0 || axis >= P->ndim || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  if (axis < -1 || axis >= P->ndim || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  if (axis == -1) {
+    for (int a = 0; a < P->ndim; ++a)
+      if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
+    if (use_fused2d(P)) {
+      PSTD_HIP(launch_phase2d_one(which, P->G[0], P->G[1], P->D[0], P->D[1], static_cast<float*>(st->p),
+                                  static_cast<float*>(st->u[0]), static_cast<float*>(st->u[1]),
+                                  static_cast<const float*>(P->c2map), static_cast<int>(P->n[0]),
+                                  static_cast<int>(P->n[1]), P->stream));
+      return PSTD_OK;
+    }
+    for (int a = 0; a < P->ndim; ++a) {
+      const int st2 = pstd_apply_axis(P, st, a, which);
+      if (st2 != PSTD_OK) return st2;
+    }
+    return PSTD_OK;
+  }
   if (!st->u[axis]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", axis);
   if (which == 0) PSTD_HIP(contract(P, P->G[axis], axis, st->p, st->u[axis], 1.0, 1.0, nullptr, P->stream));
   else PSTD_HIP(contract(P, P->D[axis], axis, st->u[axis], st->p, 1.0, 1.0, P->c2map, P->stream));

@@ -45,6 +45,15 @@ struct AxisTables {
 const AxisTables& axis_tables(int n, AxisCase c);
 
 // ---- device helpers ------------------------------------------------------------------------------
+// Block barrier ordering only LDS accesses.  __syncthreads() also orders global memory, which makes the
+// compiler drain every outstanding global load (s_waitcnt vmcnt(0)) at each barrier and so defeats
+// prefetching across it.  The kernels here exchange data between waves only through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Padding of every device operator matrix: rows to a multiple of kRowPad, columns to kColPad.
@@ -87,6 +96,13 @@ hipError_t launch_fill_zero(int prec, void* x, int64_t count, hipStream_t s);
 hipError_t launch_square(int prec, const float* in, void* out, int64_t count, hipStream_t s);
 hipError_t launch_combine(const float* const* f, const float* w, int nf, float* out, int64_t count,
                           hipStream_t s);
+bool phase2d_supported(int nx, int ny);
+hipError_t launch_phase2d(const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx, const DevOperator& Dy,
+                          float* p, float* ux, float* uy, const float* c2, int nx, int ny, int64_t steps,
+                          hipStream_t s);
+hipError_t launch_phase2d_one(int which, const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx,
+                              const DevOperator& Dy, float* p, float* ux, float* uy, const float* c2, int nx, int ny,
+                              hipStream_t s);
 hipError_t launch_nonfinite(int prec, const void* x, int64_t count, int* flag, hipStream_t s);
 
 }  // namespace pstd
@@ -103,6 +119,7 @@ struct pstd_plan_s {
   pstd::DevOperator G[3], D[3];
   void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
   int* flag = nullptr;         // device int for reductions (owned)
+  int path = 0;                // PSTD_PATH_* (0 = automatic)
   // captured step graphs
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;

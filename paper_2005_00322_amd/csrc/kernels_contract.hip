@@ -93,29 +93,43 @@ __global__ __launch_bounds__(64 * WM * WN) void contract_kernel(KArgs<T> a) {
   }
 
   for (int k0 = 0; k0 < a.K; k0 += BK) {
-    __syncthreads();
-    // operator slice: zero padded on the host, no bounds checks needed
-    for (int e = tid; e < BM * BK; e += NT) {
-      const int r = e / BK, k = e % BK;
-      As[r][k] = a.A[static_cast<int64_t>(m0 + r) * a.lda + k0 + k];
+    lds_barrier();
+    // operator and field slices: every load of the slice is issued before the first LDS store.
+    // The operator is zero padded on the host (no bounds checks); the field is zero-filled outside
+    // [0,K) x [0,ncols).
+    constexpr int AIT = BM * BK / NT, XIT = BN * BK / NT;
+    static_assert(AIT * NT == BM * BK && XIT * NT == BN * BK, "tile must split evenly over the block");
+    T av_[AIT], xv_[XIT];
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+      const int e = tid + it * NT;
+      av_[it] = a.A[static_cast<int64_t>(m0 + e / BK) * a.lda + k0 + e % BK];
     }
-    // field slice, zero-filled outside [0,K) x [0,ncols)
-    if (CONTIG) {
-      for (int e = tid; e < BN * BK; e += NT) {
-        const int r = e / BK, k = e % BK;
-        const int64_t gr = n0 + r;
-        const int gk = k0 + k;
-        Xs[r][k] = (gr < a.ncols && gk < a.K) ? X[gr * a.K + gk] : T(0);
-      }
-    } else {
-      for (int e = tid; e < BK * BN; e += NT) {
-        const int k = e / BN, c = e % BN;
-        const int64_t gc = n0 + c;
-        const int gk = k0 + k;
-        Xs[k][c] = (gc < a.ncols && gk < a.K) ? X[static_cast<int64_t>(gk) * a.ncols + gc] : T(0);
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int e = tid + it * NT;
+      if (CONTIG) {
+        const int64_t gr = n0 + e / BK;
+        const int gk = k0 + e % BK;
+        xv_[it] = (gr < a.ncols && gk < a.K) ? X[gr * a.K + gk] : T(0);
+      } else {
+        const int64_t gc = n0 + e % BN;
+        const int gk = k0 + e / BN;
+        xv_[it] = (gc < a.ncols && gk < a.K) ? X[static_cast<int64_t>(gk) * a.ncols + gc] : T(0);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+      const int e = tid + it * NT;
+      As[e / BK][e % BK] = av_[it];
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int e = tid + it * NT;
+      if (CONTIG) Xs[e / BK][e % BK] = xv_[it];
+      else Xs[e / BN][e % BN] = xv_[it];
+    }
+    lds_barrier();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
@@ -143,28 +157,39 @@ __global__ __launch_bounds__(64 * WM * WN) void contract_kernel(KArgs<T> a) {
     }
   }
 
-  // fused update epilogue
+  // fused update epilogue: every load of Y (and of the map) first, then every store
   T* Y = a.Y + b * a.y_bstride;
   const T* S = a.scale ? a.scale + b * a.y_bstride : nullptr;
+  auto out_index = [&](int i, int j, int r) -> int64_t {
+    const int64_t col = n0 + wn * WTN + j * 16 + (lane & 15);
+    const int m = m0 + wm * WTM + i * 16 + (sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r);
+    if (m >= a.M || col >= a.ncols) return -1;
+    return CONTIG ? col * a.M + m : static_cast<int64_t>(m) * a.ncols + col;
+  };
+  T yv[TM][TN][4], sv[TM][TN][4];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t col = n0 + wn * WTN + j * 16 + (lane & 15);
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * WTM + i * 16 + (sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r);
-        if (m < a.M && col < a.ncols) {
-          const int64_t idx = CONTIG ? col * a.M + m : static_cast<int64_t>(m) * a.ncols + col;
-          // the product, the map factor and the update are formed in FP64 and rounded once
-          double v = static_cast<double>(a.alpha) *
-                     (kFlush ? accd[kFlush ? i : 0][kFlush ? j : 0][r] : static_cast<double>(acc[i][j][r]));
-          if (S) v *= static_cast<double>(S[idx]);
-          Y[idx] = static_cast<T>((a.beta == T(0)) ? v : static_cast<double>(a.beta) * static_cast<double>(Y[idx]) + v);
-        }
+        const int64_t idx = out_index(i, j, r);
+        yv[i][j][r] = (idx >= 0 && a.beta != T(0)) ? Y[idx] : T(0);
+        sv[i][j][r] = (idx >= 0 && S) ? S[idx] : T(1);
       }
-    }
-  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t idx = out_index(i, j, r);
+        if (idx < 0) continue;
+        // the product, the map factor and the update are formed in FP64 and rounded once
+        const double prod = kFlush ? accd[kFlush ? i : 0][kFlush ? j : 0][r] : static_cast<double>(acc[i][j][r]);
+        const double v = static_cast<double>(a.alpha) * prod * static_cast<double>(sv[i][j][r]);
+        Y[idx] = static_cast<T>(static_cast<double>(a.beta) * static_cast<double>(yv[i][j][r]) + v);
+      }
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>

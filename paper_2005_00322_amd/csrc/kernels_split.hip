@@ -11,8 +11,13 @@
 // so the operand whose rows are unit-stride in Y goes to the Q port:
 //   strided layout   (Y[b][m][c]): P = operator rows m, Q = field columns c
 //   contiguous layout (Y[r][m]):   P = field rows r,   Q = operator rows m
-// Blocks sharing one field tile are placed on the same XCD back to back so the field tile is fetched
-// from HBM once and re-read from that XCD's L2.
+//
+// Pipeline: two LDS buffers and two register sets.  While the MFMAs consume K-slice s from one LDS
+// buffer, the global loads of slices s+1 and s+2 are in flight in the two register sets; after the
+// MFMAs slice s+1 is split into bf16 hi/lo and written to the other buffer, the loads of slice s+3 are
+// issued into the freed register set, and one barrier per slice separates the two buffers.  The epilogue issues every load of Y
+// before its first store.  Blocks sharing one field tile are placed on the same XCD back to back so
+// the tile comes from HBM once and from that XCD's L2 afterwards.
 #include "common.h"
 
 namespace pstd {
@@ -20,10 +25,13 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct SArgs {
   const uint16_t* Ahi;
   const uint16_t* Alo;
+  uint32_t lo_off;         // byte offset of the lo part from the hi part
   int lda, M, K;
   const float* X;
   float* Y;
@@ -34,41 +42,57 @@ struct SArgs {
   const float* scale;
 };
 
-constexpr int BK = 32;          // K slice staged per iteration (two MFMA K-steps)
-constexpr int LDK = BK + 8;     // LDS row stride in bf16 elements (80 bytes: conflict-free 16-byte reads)
+constexpr int BK = 32;            // K slice per pipeline stage (two MFMA K-steps)
+constexpr int LDK = BK + 8;       // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
+constexpr int BT = 128;           // tile edge along P and along Q
+constexpr int NT = 256;           // 4 waves, 2 x 2, each 64 x 64
+constexpr int TILE_ELEMS = BT * LDK;
+constexpr int OP_CH = BT * (BK / 8) / NT;    // 16-byte operator chunks per thread per part (2)
+constexpr int FL_G = BT * (BK / 8) / NT;     // 8-float field groups per thread (2)
 
-__device__ __forceinline__ void split2(float x, __bf16& hi, __bf16& lo) {
-  hi = static_cast<__bf16>(x);
-  lo = static_cast<__bf16>(x - static_cast<float>(hi));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOOB = 0x80000000u;   // byte offset past every buffer used here (all < 2 GiB)
+
+// Raw buffer resource over `bytes` bytes: a 4-byte load at an offset >= bytes returns 0 and a store
+// there is dropped, which replaces bounds checks by out-of-range offsets.  Only 4-byte buffer accesses
+// are used: this compiler shrinks 16-byte buffer loads to one dword when optimising.
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st_f32(rsrc_t r, float v, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
+}
+// 16-byte global load at a wave-uniform base plus a 32-bit byte offset
+template <typename V>
+__device__ __forceinline__ V ld16(const void* base, uint32_t off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
 }
 
-template <bool CONTIG, int BP, int BQ, int WP, int WQ>
-__global__ __launch_bounds__(64 * WP * WQ) void split_kernel(SArgs a) {
-  constexpr int NT = 64 * WP * WQ;
-  constexpr int WTP = BP / WP, WTQ = BQ / WQ;
-  constexpr int TP = WTP / 32, TQ = WTQ / 32;
-  static_assert(TP >= 1 && TQ >= 1, "wave tile must be a multiple of 32x32");
-  // operator tile rows and field tile extent in this layout
-  constexpr int BOP = CONTIG ? BQ : BP;   // operator rows per block
-  constexpr int BFL = CONTIG ? BP : BQ;   // field columns (strided) or rows (contiguous) per block
-  constexpr int OPCH = BOP * (BK / 8);    // 16-byte chunks of one operator part per slice
-  constexpr int OPC_PER_T = (OPCH + NT - 1) / NT;
-  constexpr int FLG = BFL * (BK / 8);     // (field line, 8-k group) pairs per slice
-  constexpr int FLG_PER_T = (FLG + NT - 1) / NT;
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& h, bf16x8& l) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 hj = static_cast<__bf16>(x[j]);
+    h[j] = hj;
+    l[j] = static_cast<__bf16>(x[j] - static_cast<float>(hj));
+  }
+}
 
-  __shared__ __attribute__((aligned(16))) __bf16 Ph[BP * LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Pl[BP * LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Qh[BQ * LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Ql[BQ * LDK];
-  __bf16* Oh = CONTIG ? Qh : Ph;   // operator tile
-  __bf16* Ol = CONTIG ? Ql : Pl;
-  __bf16* Fh = CONTIG ? Ph : Qh;   // field tile
-  __bf16* Fl = CONTIG ? Pl : Ql;
-
+// FMODE (contiguous layout only): 0 = one 4-byte load per field element; 2 = two 16-byte loads per 8
+// floats (X 16-byte aligned and K % 4 == 0).
+template <bool CONTIG, int FMODE>
+__global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
+  constexpr bool VEC = FMODE == 2;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2][4][TILE_ELEMS];   // [buffer][P hi, P lo, Q hi, Q lo]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wp = wave % WP, wq = wave / WP;
+  const int wp = wave & 1, wq = wave >> 1;
+  // operator / field roles of the P and Q ports
+  constexpr int OPH = CONTIG ? 2 : 0, OPL = CONTIG ? 3 : 1;
+  constexpr int FLH = CONTIG ? 0 : 2, FLL = CONTIG ? 1 : 3;
 
   // tile coordinates: XCD-grouped when the field tile count allows it
   const int64_t t = blockIdx.x;
@@ -85,167 +109,197 @@ __global__ __launch_bounds__(64 * WP * WQ) void split_kernel(SArgs a) {
   int64_t b, f0;
   if (CONTIG) {
     b = 0;
-    f0 = fl_t * BFL;
+    f0 = fl_t * BT;
   } else {
-    const int64_t per = (a.ncols + BFL - 1) / BFL;
+    const int64_t per = (a.ncols + BT - 1) / BT;
     b = fl_t / per;
-    f0 = (fl_t % per) * BFL;
+    f0 = (fl_t % per) * BT;
   }
-  const int o0 = op_t * BOP;
-  const float* X = a.X + b * a.x_bstride;
+  const int o0 = op_t * BT;
+  // buffer resources: the operator, this block's field slab and its output slab
+  const uint32_t x_bytes = static_cast<uint32_t>(4 * (CONTIG ? a.ncols * a.K : a.ncols * static_cast<int64_t>(a.K)));
+  const uint32_t y_bytes = static_cast<uint32_t>(4 * a.ncols * a.M);
+  const float* Xb = a.X + b * a.x_bstride;
+  const rsrc_t rX = make_rsrc(Xb, x_bytes);
+  const rsrc_t rY = make_rsrc(a.Y + b * a.y_bstride, y_bytes);
+  const rsrc_t rS = make_rsrc(a.scale ? a.scale + b * a.y_bstride : a.Y, a.scale ? y_bytes : 0u);
 
-  // register staging of one slice
-  uint4 rOh[OPC_PER_T], rOl[OPC_PER_T];
-  float rF[FLG_PER_T][8];
+  // this thread's staging coordinates (fixed for all slices)
+  int op_row[OP_CH], op_chk[OP_CH];
+#pragma unroll
+  for (int i = 0; i < OP_CH; ++i) {
+    const int e = tid + i * NT;
+    op_row[i] = e / (BK / 8);
+    op_chk[i] = e % (BK / 8);
+  }
+  int fl_line[FL_G], fl_grp[FL_G];
+#pragma unroll
+  for (int i = 0; i < FL_G; ++i) {
+    const int e = tid + i * NT;
+    fl_line[i] = CONTIG ? e / (BK / 8) : e % BT;
+    fl_grp[i] = CONTIG ? e % (BK / 8) : e / BT;
+  }
 
-  auto load_slice = [&](int k0) {
+  // per-thread byte offsets that stay fixed across slices (slices add a wave-uniform offset)
+  uint32_t op_voff[OP_CH];
 #pragma unroll
-    for (int i = 0; i < OPC_PER_T; ++i) {
-      const int e = tid + i * NT;
-      if (e < OPCH) {
-        const int r = e / (BK / 8), ch = e % (BK / 8);
-        const size_t off = static_cast<size_t>(o0 + r) * a.lda + k0 + ch * 8;
-        rOh[i] = *reinterpret_cast<const uint4*>(a.Ahi + off);
-        rOl[i] = *reinterpret_cast<const uint4*>(a.Alo + off);
-      }
-    }
+  for (int i = 0; i < OP_CH; ++i) op_voff[i] = 2u * static_cast<uint32_t>((o0 + op_row[i]) * a.lda + op_chk[i] * 8);
+  uint32_t fl_voff[FL_G];
+  bool fl_ok[FL_G];
 #pragma unroll
-    for (int i = 0; i < FLG_PER_T; ++i) {
-      const int e = tid + i * NT;
-      if (CONTIG) {
-        // field rows r, 8 consecutive k: lanes e%4 cover one 32-k row segment
-        const int r = e / (BK / 8), g = e % (BK / 8);
-        const int64_t gr = f0 + r;
-        const int kb = k0 + g * 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          rF[i][j] = (e < FLG && gr < a.ncols && kb + j < a.K) ? X[gr * a.K + kb + j] : 0.f;
-      } else {
-        // field column c, 8 consecutive k: lanes take consecutive columns (coalesced rows of X)
-        const int c = e % BFL, g = e / BFL;
-        const int64_t gc = f0 + c;
-        const int kb = k0 + g * 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          rF[i][j] = (e < FLG && gc < a.ncols && kb + j < a.K) ? X[static_cast<int64_t>(kb + j) * a.ncols + gc] : 0.f;
-      }
-    }
-  };
+  for (int i = 0; i < FL_G; ++i) {
+    const int64_t line = f0 + fl_line[i];
+    fl_ok[i] = line < a.ncols;
+    // strided: X[k][line] at (k * ncols + line) * 4; contiguous: X[line][k] at (line * K + k) * 4
+    fl_voff[i] = CONTIG ? static_cast<uint32_t>(4 * (line * a.K + fl_grp[i] * 8))
+                        : static_cast<uint32_t>(4 * (static_cast<int64_t>(fl_grp[i]) * 8 * a.ncols + line));
+  }
+  const uint32_t kstride = CONTIG ? 4u : static_cast<uint32_t>(4 * a.ncols);   // bytes per unit of k
 
-  auto store_slice = [&]() {
-#pragma unroll
-    for (int i = 0; i < OPC_PER_T; ++i) {
-      const int e = tid + i * NT;
-      if (e < OPCH) {
-        const int r = e / (BK / 8), ch = e % (BK / 8);
-        *reinterpret_cast<uint4*>(Oh + r * LDK + ch * 8) = rOh[i];
-        *reinterpret_cast<uint4*>(Ol + r * LDK + ch * 8) = rOl[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < FLG_PER_T; ++i) {
-      const int e = tid + i * NT;
-      if (e < FLG) {
-        int line, g;
-        if (CONTIG) {
-          line = e / (BK / 8);
-          g = e % (BK / 8);
-        } else {
-          line = e % BFL;
-          g = e / BFL;
-        }
-        bf16x8 h, l;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          __bf16 hj, lj;
-          split2(rF[i][j], hj, lj);
-          h[j] = hj;
-          l[j] = lj;
-        }
-        *reinterpret_cast<bf16x8*>(Fh + line * LDK + g * 8) = h;
-        *reinterpret_cast<bf16x8*>(Fl + line * LDK + g * 8) = l;
-      }
-    }
-  };
+  u32x4 rOh[2][OP_CH], rOl[2][OP_CH];
+  float rF[2][FL_G][8];
 
-  f32x16 acc[TP][TQ];
+#define PSTD_LOAD_SLICE(R, K0)                                                                        \
+  {                                                                                                   \
+    const int k0_ = (K0);                                                                             \
+    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) {                                               \
+      rOh[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + 2u * k0_);                                          \
+      rOl[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + a.lo_off + 2u * k0_);                               \
+    }                                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                                \
+      const int kb = k0_ + fl_grp[i] * 8;                                                             \
+      if (VEC) {                                                                                      \
+        /* each 16-byte half is all valid or all past the row (K % 4 == 0) */                         \
+        /* an invalid half reads offset 0 (in bounds) and is zeroed */                                \
+        const bool h0 = fl_ok[i] && kb + 4 <= a.K, h1 = fl_ok[i] && kb + 8 <= a.K;                    \
+        const f32x4 v0 = ld16<f32x4>(Xb, h0 ? fl_voff[i] + 4u * k0_ : 0u);                            \
+        const f32x4 v1 = ld16<f32x4>(Xb, h1 ? fl_voff[i] + 16u + 4u * k0_ : 0u);                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                               \
+          rF[R][i][j] = h0 ? v0[j] : 0.f;                                                             \
+          rF[R][i][4 + j] = h1 ? v1[j] : 0.f;                                                         \
+        }                                                                                             \
+      } else {                                                                                        \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j)                                                 \
+          rF[R][i][j] = ld_f32(rX, (fl_ok[i] && kb + j < a.K) ? fl_voff[i] + j * kstride : kOOB,      \
+                               static_cast<uint32_t>(k0_) * kstride);                                 \
+      }                                                                                               \
+    }                                                                                                 \
+  }
+
+#define PSTD_STORE_SLICE(R, BUF)                                                                      \
+  {                                                                                                   \
+    __bf16* L = &lds[(BUF)][0][0];                                                                    \
+    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) {                                               \
+      const int o = op_row[i] * LDK + op_chk[i] * 8;                                                  \
+      *reinterpret_cast<u32x4*>(L + OPH * TILE_ELEMS + o) = rOh[R][i];                                \
+      *reinterpret_cast<u32x4*>(L + OPL * TILE_ELEMS + o) = rOl[R][i];                                \
+    }                                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                                \
+      bf16x8 h, l;                                                                                    \
+      split8(rF[R][i], h, l);                                                                         \
+      const int o = fl_line[i] * LDK + fl_grp[i] * 8;                                                 \
+      *reinterpret_cast<bf16x8*>(L + FLH * TILE_ELEMS + o) = h;                                       \
+      *reinterpret_cast<bf16x8*>(L + FLL * TILE_ELEMS + o) = l;                                       \
+    }                                                                                                 \
+  }
+
+  f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < TP; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < TQ; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  load_slice(0);
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
-    __syncthreads();
-    store_slice();
-    __syncthreads();
-    if (k0 + BK < a.K) load_slice(k0 + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      bf16x8 ph[TP], pl[TP], qh[TQ], ql[TQ];
-      const int koff = kk + 8 * (lane >> 5);
-#pragma unroll
-      for (int i = 0; i < TP; ++i) {
-        const int row = wp * WTP + i * 32 + (lane & 31);
-        ph[i] = *reinterpret_cast<const bf16x8*>(Ph + row * LDK + koff);
-        pl[i] = *reinterpret_cast<const bf16x8*>(Pl + row * LDK + koff);
-      }
-#pragma unroll
-      for (int j = 0; j < TQ; ++j) {
-        const int row = wq * WTQ + j * 32 + (lane & 31);
-        qh[j] = *reinterpret_cast<const bf16x8*>(Qh + row * LDK + koff);
-        ql[j] = *reinterpret_cast<const bf16x8*>(Ql + row * LDK + koff);
-      }
-#pragma unroll
-      for (int i = 0; i < TP; ++i)
-#pragma unroll
-        for (int j = 0; j < TQ; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl[i], qh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], ql[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], qh[j], acc[i][j], 0, 0, 0);
-        }
-    }
+  const int prow = wp * 64 + (lane & 31);
+  const int qrow = wq * 64 + (lane & 31);
+
+#define PSTD_COMPUTE(BUF)                                                                             \
+  {                                                                                                   \
+    const __bf16* L = &lds[(BUF)][0][0];                                                              \
+    _Pragma("unroll") for (int kk = 0; kk < BK; kk += 16) {                                           \
+      const int koff = kk + 8 * (lane >> 5);                                                          \
+      bf16x8 ph[2], pl[2], qh[2], ql[2];                                                              \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                 \
+        ph[i] = *reinterpret_cast<const bf16x8*>(L + 0 * TILE_ELEMS + (prow + 32 * i) * LDK + koff);  \
+        pl[i] = *reinterpret_cast<const bf16x8*>(L + 1 * TILE_ELEMS + (prow + 32 * i) * LDK + koff);  \
+        qh[i] = *reinterpret_cast<const bf16x8*>(L + 2 * TILE_ELEMS + (qrow + 32 * i) * LDK + koff);  \
+        ql[i] = *reinterpret_cast<const bf16x8*>(L + 3 * TILE_ELEMS + (qrow + 32 * i) * LDK + koff);  \
+      }                                                                                               \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) {   \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl[i], qh[j], acc[i][j], 0, 0, 0);        \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], ql[j], acc[i][j], 0, 0, 0);        \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], qh[j], acc[i][j], 0, 0, 0);        \
+      }                                                                                               \
+    }                                                                                                 \
   }
 
-  // fused update epilogue; lanes 0..31 write 32 consecutive floats of one output line
-  float* Y = a.Y + b * a.y_bstride;
-  const float* S = a.scale ? a.scale + b * a.y_bstride : nullptr;
+  // slice s lives in LDS buffer s&1 and (before that) in register set s&1.  Prefetches past the last
+  // slice re-load the last slice (in bounds, never stored where it is read), which keeps the loop body
+  // straight-line so that each wait covers only the loads it needs.
+  const int nslices = (a.K + BK - 1) / BK;
+  const int last = nslices - 1;
+  PSTD_LOAD_SLICE(0, 0);
+  PSTD_LOAD_SLICE(1, min(1, last) * BK);
+  PSTD_STORE_SLICE(0, 0);
+  PSTD_LOAD_SLICE(0, min(2, last) * BK);
+  lds_barrier();
+  for (int s = 0; s < nslices; s += 2) {
+    // even slice s: LDS buffer 0; slice s+1 waits in register set 1, slice s+2 in set 0
+    PSTD_COMPUTE(0);
+    PSTD_STORE_SLICE(1, 1);
+    PSTD_LOAD_SLICE(1, min(s + 3, last) * BK);
+    lds_barrier();
+    if (s + 1 >= nslices) break;
+    // odd slice s+1: LDS buffer 1; slice s+2 waits in register set 0, slice s+3 in set 1
+    PSTD_COMPUTE(1);
+    PSTD_STORE_SLICE(0, 0);
+    PSTD_LOAD_SLICE(0, min(s + 4, last) * BK);
+    lds_barrier();
+  }
+#undef PSTD_COMPUTE
+#undef PSTD_LOAD_SLICE
+#undef PSTD_STORE_SLICE
+
+  // fused update epilogue; lanes 0..31 write 32 consecutive floats of one output line.  Every load of
+  // Y (and of the c0 map) is issued before the first store: one memory round trip.  Outside the field
+  // the offset is out of range: loads return 0 and stores are dropped.
+  uint32_t yoff[2][2][16];
 #pragma unroll
-  for (int i = 0; i < TP; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < TQ; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int prow = wp * WTP + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int qcol = wq * WTQ + j * 32 + (lane & 31);
-        int64_t idx;
-        bool ok;
-        if (CONTIG) {
-          const int64_t rr = f0 + prow;
-          const int m = o0 + qcol;
-          ok = rr < a.ncols && m < a.M;
-          idx = rr * a.M + m;
-        } else {
-          const int m = o0 + prow;
-          const int64_t c = f0 + qcol;
-          ok = m < a.M && c < a.ncols;
-          idx = static_cast<int64_t>(m) * a.ncols + c;
-        }
-        if (ok) {
-          float v = a.alpha * acc[i][j][r];
-          if (S) v *= S[idx];
-          Y[idx] = (a.beta == 0.f) ? v : a.beta * Y[idx] + v;
-        }
+        const int pr = wp * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int qc = wq * 64 + j * 32 + (lane & 31);
+        const int64_t line = f0 + (CONTIG ? pr : qc);
+        const int m = o0 + (CONTIG ? qc : pr);
+        const bool ok = line < a.ncols && m < a.M;
+        yoff[i][j][r] = ok ? static_cast<uint32_t>(4 * (CONTIG ? line * a.M + m : static_cast<int64_t>(m) * a.ncols + line))
+                           : kOOB;
       }
+  float yv[2][2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        yv[i][j][r] = a.beta != 0.f ? ld_f32(rY, yoff[i][j][r], 0) : 0.f;
+        if (a.scale) acc[i][j][r] *= ld_f32(rS, yoff[i][j][r], 0);
+      }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st_f32(rY, a.beta * yv[i][j][r] + a.alpha * acc[i][j][r], yoff[i][j][r]);
 }
 
-template <bool CONTIG, int BP, int BQ, int WP, int WQ>
+template <bool CONTIG>
 hipError_t launch_s(const ContractArgs& c, hipStream_t s) {
-  constexpr int BOP = CONTIG ? BQ : BP;
-  constexpr int BFL = CONTIG ? BP : BQ;
-  static_assert(BOP <= kRowPad && kRowPad % BOP == 0 && kColPad % BK == 0, "padding");
+  static_assert(BT <= kRowPad && kRowPad % BT == 0 && kColPad % BK == 0, "operator padding must cover tiles");
   SArgs a;
   a.Ahi = static_cast<const uint16_t*>(c.A);
   a.Alo = static_cast<const uint16_t*>(c.A_lo);
@@ -261,20 +315,30 @@ hipError_t launch_s(const ContractArgs& c, hipStream_t s) {
   a.alpha = c.alpha;
   a.beta = c.beta;
   a.scale = static_cast<const float*>(c.scale);
-  a.op_tiles = (c.M + BOP - 1) / BOP;
-  a.fld_tiles = ((c.ncols + BFL - 1) / BFL) * (CONTIG ? 1 : c.batch);
+  a.op_tiles = (c.M + BT - 1) / BT;
+  a.fld_tiles = ((c.ncols + BT - 1) / BT) * (CONTIG ? 1 : c.batch);
   const int64_t blocks = a.fld_tiles * a.op_tiles;
   if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((split_kernel<CONTIG, BP, BQ, WP, WQ>), dim3(static_cast<unsigned>(blocks)), dim3(64 * WP * WQ),
-                     0, s, a);
+  // buffer offsets are 32-bit: every slab must stay below 2 GiB (checked at plan creation too)
+  const int64_t xb = 4 * c.ncols * static_cast<int64_t>(c.K), yb = 4 * c.ncols * static_cast<int64_t>(c.M);
+  const int64_t ob = reinterpret_cast<const char*>(c.A_lo) - reinterpret_cast<const char*>(c.A);
+  if (xb >= (int64_t(1) << 31) || yb >= (int64_t(1) << 31) || ob <= 0 || 2 * ob >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
+  a.lo_off = static_cast<uint32_t>(ob);
+  const dim3 grid(static_cast<unsigned>(blocks));
+  // contiguous rows that start 16-byte aligned take two 16-byte loads per 8 floats
+  const bool vec = CONTIG && c.K % 4 == 0 && (reinterpret_cast<uintptr_t>(c.X) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL((split_kernel<CONTIG, 2>), grid, dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((split_kernel<CONTIG, 0>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_contract_split(const ContractArgs& c, bool contiguous, hipStream_t s) {
-  if (contiguous) return launch_s<true, 128, 128, 2, 2>(c, s);
-  return launch_s<false, 128, 128, 2, 2>(c, s);
+  return contiguous ? launch_s<true>(c, s) : launch_s<false>(c, s);
 }
 
 }  // namespace pstd

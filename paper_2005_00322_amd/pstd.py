@@ -139,6 +139,12 @@ class Plan:
         st.step = cs.step
         return st
 
+    PATHS = {"auto": 0, "per_axis": 1, "fused": 2}
+
+    def set_path(self, path: str) -> None:
+        """Execution path of later steps: "auto", "per_axis" or "fused" (2D FP32: two kernels per step)."""
+        check(load().pstd_plan_set_path(self._h, self.PATHS[path]), "pstd_plan_set_path")
+
     def apply_axis(self, st: State, axis: int, which: int) -> None:
         """One velocity (which=0) or pressure (which=1) update along one axis: a single kernel launch."""
         cs = st._c()

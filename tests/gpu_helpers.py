@@ -17,7 +17,7 @@ def oracle_problem(case):
     return opstd.Problem(case.shape, case.bcs, case.dx, case.dt, case.c0, rho0=case.rho0, c0_map=case.c0_map)
 
 
-def run_gpu(case, precision=None, steps=None, u_mode="centred", chunks=None):
+def run_gpu(case, precision=None, steps=None, u_mode="centred", chunks=None, path=None):
     """Returns (p, [u_a]) as float64 numpy arrays after stepping on the GPU."""
     import torch
     from paper_2005_00322_amd import Plan
@@ -27,6 +27,8 @@ def run_gpu(case, precision=None, steps=None, u_mode="centred", chunks=None):
     c0 = case.c0 if case.c0_map is None else float(np.max(case.c0_map))
     with Plan(case.shape, case.dx, case.dt, c0, case.bcs, rho0=case.rho0, precision=precision,
               c0_map=case.c0_map) as plan:
+        if path is not None:
+            plan.set_path(path)
         st = plan.new_state(case.p0)
         plan.init_state(st, u_mode)
         for n in (chunks or [steps]):
