@@ -38,6 +38,7 @@ WORKLOADS = {
     "pstd2d": ("pstd2d", "fp32", 2000, 200),
     "pstd3d": ("pstd3d", "split_bf16", 100, 10),
     "pstd1d": ("pstd1d", "fp64", 1000, 100),
+    "batched": ("batched", "fp32", 1000, 10),
 }
 
 
@@ -154,6 +155,139 @@ def cpu_baseline_leg(case, gpu_p, total_steps, budget_s=12.0):
     return base, err
 
 
+def batched_solves():
+    import workloads
+    wl = workloads.batched()
+    solves, p0s, pairs, R = [], [], [], []
+    for i, inst in enumerate(wl["instances"]):
+        for bc in (1, 0):                       # Dirichlet then Neumann solve of each instance
+            solves.append({"shape": inst.shape, "bcs": ((bc, bc), (bc, bc)), "dx": wl["dx"], "dt": inst.dt,
+                           "c0": inst.c0})
+            p0s.append(inst.p0)
+        pairs.append((2 * i, 2 * i + 1))
+        R.append(inst.R)
+    return wl, solves, p0s, pairs, R
+
+
+def batch_step_cost(solves):
+    """Algorithmic flops and bytes of one step of every solve (four dense contractions per 2D step)."""
+    flops = bytes_ = 0.0
+    for s in solves:
+        nx, ny = s["shape"]
+        for which in (0, 1):
+            f, b = phase_cost((nx, ny), which, "fp32")
+            flops += f
+            bytes_ += b
+    return flops, bytes_
+
+
+def run_batched(args, K, W):
+    import torch
+
+    from paper_2005_00322_amd import Batch, Plan
+
+    wl, solves, p0s, pairs, R = batched_solves()
+    points = sum(s["shape"][0] * s["shape"][1] for s in solves)
+    b = Batch(solves)
+    cfg = b.autotune(trial_steps=5, cache_path=os.path.join("/tmp", "pstd_batch_tune.json"))
+    st = b.new_states(p0s)
+    b.init_states(st)
+    b.step(st, W)
+    torch.cuda.synchronize()
+    stream = b._stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.step(st, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = e0.elapsed_time(e1)
+    outs = b.combine_R(st, pairs, R)
+    torch.cuda.synchronize()
+    finals = [s.p.double().cpu().numpy() for s in st]
+    combined = [o.double().cpu().numpy() for o in outs]
+    b.close()
+    # the same solves one after another through the single-solve FP32 path (a sample of steps)
+    seq_steps = 10
+    seq = 0.0
+    for s, p0 in zip(solves, p0s):
+        with Plan(s["shape"], s["dx"], s["dt"], s["c0"], s["bcs"], precision="fp32") as pl:
+            ss = pl.new_state(p0)
+            pl.init_state(ss)
+            pl.step(ss, 2)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pl.step(ss, seq_steps)
+            torch.cuda.synchronize()
+            seq += time.perf_counter() - t
+    seq_total = seq * K / seq_steps
+    flops, bytes_ = batch_step_cost(solves)
+    launches = max(1, (K + 1023) // 1024)
+    tfs = flops * K / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s",
+            "frac": round(tfs / PEAK["fp32_TFs"], 4), "traffic": None, "kernel": "batch2d_kernel (persistent)",
+            "avg_ms": round(kernel_ms / launches, 3), "algorithmic_flops": int(flops * K / launches),
+            "algorithmic_bytes": int(bytes_ * K / launches), "arith_intensity": round(flops / bytes_, 2)}
+    cpu = err = None
+    if not args.no_cpu_baseline:
+        cpu, err = batched_cpu_leg(wl, solves, p0s, finals, combined, pairs, R, W + K)
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle; batched speedup",
+        "value": points * K / elapsed, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched2d_128x2_solves_96-512", "solves": len(solves), "points_per_step": points,
+                   "precision": "fp32", "parallelism": "single-gpu", "launch": cfg},
+        "batched_speedup": {"vs_sequential_single_solve_fp32": seq_total / elapsed,
+                            "sequential_estimate_s": seq_total, "batched_s": elapsed,
+                            "sample": "%d steps of each of the %d solves through the single-solve path, scaled to %d"
+                                      % (seq_steps, len(solves), K)},
+        "accuracy": {"rel_l2_vs_fp64_oracle_worst": err, "after_steps": W + K, "tolerance": 1e-5},
+        "roofline": roof, "cpu_baseline": cpu, "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line))
+
+
+def batched_cpu_leg(wl, solves, p0s, finals, combined, pairs, R, total_steps, budget_s=12.0):
+    """Oracle: time stepping of sample solves on the host; check sample solves and combinations."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import pstd as opstd
+
+    # timing sample: the first solves, stepped until the budget is used
+    done_pts = 0
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < budget_s and i < len(solves):
+        s = solves[i]
+        prob = opstd.Problem(s["shape"], s["bcs"], s["dx"], s["dt"], s["c0"])
+        p, u = prob.project(p0s[i]), prob.initial_velocity(p0s[i])
+        n = 0
+        while n < 50 and time.perf_counter() - t0 < budget_s:
+            p, u = prob.step(p, u)
+            n += 1
+        done_pts += n * s["shape"][0] * s["shape"][1]
+        i += 1
+    dt = time.perf_counter() - t0
+    threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
+    # accuracy: every 16th instance, both solves and their combination, against the closed form
+    worst = 0.0
+    for k in range(0, len(pairs), 16):
+        d, n = pairs[k]
+        refs = []
+        for idx in (d, n):
+            s = solves[idx]
+            ref = opstd.Problem(s["shape"], s["bcs"], s["dx"], s["dt"], s["c0"]).modal_solution(p0s[idx], total_steps)
+            refs.append(ref)
+            worst = max(worst, float(np.linalg.norm(finals[idx] - ref) / np.linalg.norm(ref)))
+        cref = opstd.combine_R(refs[0], refs[1], R[k])
+        worst = max(worst, float(np.linalg.norm(combined[k] - cref) / np.linalg.norm(cref)))
+    cpu = {"value": done_pts / dt, "unit": "grid-point updates/s", "cores": int(threads), "kind": "oracle",
+           "sample": "up to 50 time steps of the first %d solves of the batched workload, FP64 NumPy" % i}
+    return cpu, worst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +312,10 @@ def main():
     builder, precision, dsteps, dwarm = WORKLOADS[args.workload]
     K = dsteps if args.steps is None else args.steps
     W = dwarm if args.warmup is None else args.warmup
+    if args.workload == "batched":
+        torch.cuda.set_device(0)
+        run_batched(args, K, W)
+        return
     case = getattr(workloads, builder)()
     torch.cuda.set_device(0)
 

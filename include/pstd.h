@@ -150,6 +150,44 @@ int64_t pstd_plan_numel(pstd_plan plan, int32_t field /* -1 = p, 0..2 = u[axis] 
 
 int pstd_plan_destroy(pstd_plan plan);
 
+/* ---- Batched 2D solves: many independent boxes stepped by one persistent launch ----------------------
+ * A batch holds `count` independent 2D FP32 solves of possibly different sizes, boundary faces,
+ * spacings, time steps and sound speeds (density rho0 shared), all on the batch's stream.  Each solve is
+ * the 2D scheme of §4.3; the paired Neumann/Dirichlet solves of one physical instance are two entries
+ * combined afterwards with pstd_batch_combine_R.  Operators are built in FP64 once per distinct
+ * (n, boundary pair) and shared.  pstd_batch_step runs all requested steps of all solves in one
+ * cooperative kernel launch: per step a velocity phase over every solve's velocity tiles, a grid-wide
+ * barrier, a pressure phase over every pressure tile, a second barrier. */
+typedef struct pstd_batch_s* pstd_batch;
+
+/* n: count x 2 (nx, ny) nodes per solve, each >= 3 and <= 512; bc: count x 4 faces {x-, x+, y-, y+};
+ * dx, dt, c0: count values each.  Returns PSTD_E_UNSTABLE if any solve is above its stability limit. */
+int pstd_batch_create(int32_t count, const int64_t* n, const int32_t* bc, const double* dx, const double* dt,
+                      const double* c0, double rho0, void* hip_stream, pstd_batch* out);
+
+/* Prepare caller-filled states (count of them, FP32 p and u[0], u[1]) as pstd_state_init does. */
+int pstd_batch_state_init(pstd_batch batch, pstd_state* states, int32_t u_mode);
+
+/* Advance every solve by n_steps (one persistent launch per 1024 steps).  Asynchronous. */
+int pstd_batch_step(pstd_batch batch, pstd_state* states, int64_t n_steps);
+
+/* out[i] = (1+R[i])/2 p_neumann + (1-R[i])/2 p_dirichlet for npairs pairs; pairs = npairs x 2 solve
+ * indices (dirichlet, neumann) of equally sized solves; out[i] holds nx*ny floats (may alias either p). */
+int pstd_batch_combine_R(pstd_batch batch, const pstd_state* states, const int32_t* pairs, const double* R,
+                         float* const* out, int32_t npairs);
+
+/* Launch configuration of pstd_batch_step: resident block count (0 = the occupancy maximum) and tile
+ * order within a phase (0 = longest contraction first, 1 = solve by solve). */
+int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order);
+
+/* Autotuner: time every candidate configuration for trial_steps steps on scratch state buffers (the
+ * caller's states are not touched), keep the fastest and, if cache_path is not NULL, store it in a small
+ * JSON file keyed by a signature of the batch; a later call with a matching file skips the timing.
+ * config_out (nullable, 3 ints): blocks, order, 1 if taken from the cache.  Synchronous. */
+int pstd_batch_autotune(pstd_batch batch, int32_t trial_steps, const char* cache_path, int32_t* config_out);
+
+int pstd_batch_destroy(pstd_batch batch);
+
 const char* pstd_status_string(int status);
 const char* pstd_last_error(void);
 

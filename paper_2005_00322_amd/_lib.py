@@ -62,6 +62,16 @@ SIGNATURES = {
                                      C.POINTER(C.c_double)]),
     "pstd_plan_numel": (C.c_int64, [C.c_void_p, C.c_int32]),
     "pstd_plan_destroy": (C.c_int, [C.c_void_p]),
+    "pstd_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "pstd_batch_state_init": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32]),
+    "pstd_batch_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int64]),
+    "pstd_batch_combine_R": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_void_p), C.c_int32]),
+    "pstd_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pstd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]),
+    "pstd_batch_destroy": (C.c_int, [C.c_void_p]),
     "pstd_status_string": (C.c_char_p, [C.c_int]),
     "pstd_last_error": (C.c_char_p, []),
 }

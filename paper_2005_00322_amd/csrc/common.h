@@ -103,6 +103,34 @@ hipError_t launch_phase2d(const DevOperator& Gx, const DevOperator& Gy, const De
 hipError_t launch_phase2d_one(int which, const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx,
                               const DevOperator& Dy, float* p, float* ux, float* uy, const float* c2, int nx, int ny,
                               hipStream_t s);
+// ---- batched 2D solves (kernels_batch2d.hip, capi_batch.hip) --------------------------------------
+struct BatchSolve {
+  float* p;                 // nx x ny
+  float* ux;                // (nx-1) x ny
+  float* uy;                // nx x (ny-1)
+  const float* Gx; const float* Dx; const float* Gy; const float* Dy;   // unscaled (dx = 1) operators
+  int ldgx, lddx, ldgy, lddy;                                          // their row strides
+  int nx, ny;
+  double sG;                // -dt / (rho0 dx)
+  double sD;                // -dt rho0 c0^2 / dx
+};
+struct BatchTask {
+  int solve;
+  int kind;                 // 0 u_x tile, 1 u_y tile, 2 p tile
+  int i0, j0;
+};
+struct BatchArgs {
+  const BatchSolve* solves;
+  const BatchTask* tasksA;  // velocity-phase tiles
+  int nA;
+  const BatchTask* tasksB;  // pressure-phase tiles
+  int nB;
+  unsigned* counters;       // 2 per step, zeroed by the launcher
+  int64_t steps;
+};
+int batch2d_max_blocks(int* out);
+hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s);
+
 hipError_t launch_nonfinite(int prec, const void* x, int64_t count, int* flag, hipStream_t s);
 
 }  // namespace pstd

@@ -1,0 +1,232 @@
+// Batched 2D solver: many independent 2D boxes of different sizes stepped by one persistent launch.
+//
+// Every solve advances with Eq. (dtt_pstd_solution) in its 2D form (§4.3).  The launch is cooperative
+// (all blocks resident) and runs all the steps: each step is a velocity phase over the velocity tiles of
+// every solve, a grid-wide barrier, a pressure phase over the pressure tiles of every solve (each p tile
+// takes both axes' terms), and a second barrier.  Within a phase blocks take tiles from a per-phase
+// atomic counter, largest tiles first, so the uneven sizes balance.
+//
+// Operators are unscaled (dx = 1) FP32 matrices shared by all solves with the same (n, boundary pair);
+// each solve's constants -dt/(rho0 dx) and -dt rho0 c0^2/dx are applied in the FP64 epilogue.  A tile is
+// 32 x 32 outputs; its K extent is streamed through LDS in slices of 32 with a double buffer and a
+// register prefetch; each wave computes a 16 x 16 quarter with MFMA 16x16x4 FP32, four independent
+// chains per slice whose sums are flushed into FP64 registers.
+//
+// MFMA v_mfma_f32_16x16x4: lane l supplies P[l%16][l/16] and Q[l%16][l/16] (both staged as [row][k])
+// and receives C[4*(l/16)+r][l%16] in register r.
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.h"
+
+namespace pstd {
+
+namespace {
+
+namespace cg = cooperative_groups;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+constexpr int TILE = 32;
+constexpr int BK = 32;
+constexpr int LDB = BK + 1;      // LDS row stride (floats)
+constexpr int NT = 256;
+constexpr uint32_t kOOB = 0x80000000u;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+
+// Stage one BK slice of a tile operand into LDS [row][k] (32 rows).
+//   operator rows: A[(r0 + r) * lda + k], zero padded on the host (no checks)
+//   field rows (contiguous):  X[(r0 + r) * ldx + k] for r0 + r < rows, k < K
+//   field columns (strided):  X[k * ldx + c0 + c]   for c0 + c < cols, k < K   (transposed into [c][k])
+// Each thread holds 4 values of the next slice in registers between load and store.
+struct Stager {
+  int kind;          // 0 operator rows, 1 field rows, 2 field columns
+  const float* base;
+  rsrc_t rs;
+  int ld, r0, lim, K;
+  float v[4];
+
+  __device__ void load(int k0) {
+    const int t = threadIdx.x;
+    if (kind == 0) {
+      const int r = t >> 3, kk = (t & 7) * 4;
+      const f32x4 x = *reinterpret_cast<const f32x4*>(base + static_cast<int64_t>(r0 + r) * ld + k0 + kk);
+      v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    } else if (kind == 1) {
+      const int r = t >> 3, kk = (t & 7) * 4;
+      const bool rv = r0 + r < lim;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + kk + j;
+        v[j] = ld_f32(rs, (rv && k < K) ? 4u * static_cast<uint32_t>((r0 + r) * ld + k) : kOOB);
+      }
+    } else {
+      const int k = t >> 3, c = (t & 7) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = r0 + c + j < lim && k0 + k < K;
+        v[j] = ld_f32(rs, ok ? 4u * static_cast<uint32_t>((k0 + k) * ld + r0 + c + j) : kOOB);
+      }
+    }
+  }
+  __device__ void store(float* lds) const {
+    const int t = threadIdx.x;
+    if (kind == 2) {
+      const int k = t >> 3, c = (t & 7) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lds[(c + j) * LDB + k] = v[j];
+    } else {
+      const int r = t >> 3, kk = (t & 7) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lds[r * LDB + kk + j] = v[j];
+    }
+  }
+};
+
+// accd += P . Q^T over K (multiple of BK after zero fill), P and Q described by their stagers.
+__device__ __forceinline__ void tile_contract(Stager& P, Stager& Q, int K, float* lds, double (&accd)[4]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int kl = lane >> 4;
+  float* Pl[2] = {lds, lds + 2 * TILE * LDB};
+  float* Ql[2] = {lds + TILE * LDB, lds + 3 * TILE * LDB};
+  const int nsl = (K + BK - 1) / BK;
+  P.load(0);
+  Q.load(0);
+  lds_barrier();  // the previous user of the LDS buffers is done
+  P.store(Pl[0]);
+  Q.store(Ql[0]);
+  if (nsl > 1) {
+    P.load(BK);
+    Q.load(BK);
+  }
+  lds_barrier();
+  for (int s = 0; s < nsl; ++s) {
+    const float* Pp = Pl[s & 1] + ((wave & 1) * 16 + (lane & 15)) * LDB + kl;
+    const float* Qp = Ql[s & 1] + ((wave >> 1) * 16 + (lane & 15)) * LDB + kl;
+    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, c2 = {0, 0, 0, 0}, c3 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < BK; k += 16) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k], Qp[k], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 4], Qp[k + 4], c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 8], Qp[k + 8], c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 12], Qp[k + 12], c3, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      accd[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
+                 (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
+    if (s + 1 < nsl) {
+      P.store(Pl[(s + 1) & 1]);
+      Q.store(Ql[(s + 1) & 1]);
+      if (s + 2 < nsl) {
+        P.load((s + 2) * BK);
+        Q.load((s + 2) * BK);
+      }
+    }
+    lds_barrier();
+  }
+}
+
+__device__ __forceinline__ int tile_row(int r) { return ((threadIdx.x >> 6) & 1) * 16 + 4 * ((threadIdx.x & 63) >> 4) + r; }
+__device__ __forceinline__ int tile_col() { return (threadIdx.x >> 7) * 16 + (threadIdx.x & 15); }
+
+__device__ void run_task(const BatchSolve& S, const BatchTask& T, float* lds) {
+  double accd[4] = {0, 0, 0, 0};
+  const int nx = S.nx, ny = S.ny;
+  float* Y;
+  int rows, cols;
+  double scale;
+  if (T.kind == 0) {
+    // u_x[i][j] += sG * sum_k Gx[i][k] p[k][j]
+    Stager P{0, S.Gx, make_rsrc(S.Gx, 0u), S.ldgx, T.i0, nx - 1, nx};
+    Stager Q{2, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.j0, ny, nx};
+    tile_contract(P, Q, nx, lds, accd);
+    Y = S.ux; rows = nx - 1; cols = ny; scale = S.sG;
+  } else if (T.kind == 1) {
+    // u_y[i][j] += sG_y * sum_k p[i][k] Gy[j][k]
+    Stager P{1, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.i0, nx, ny};
+    Stager Q{0, S.Gy, make_rsrc(S.Gy, 0u), S.ldgy, T.j0, ny - 1, ny};
+    tile_contract(P, Q, ny, lds, accd);
+    Y = S.uy; rows = nx; cols = ny - 1; scale = S.sG;
+  } else {
+    // p[i][j] += sD * (sum_k Dx[i][k] u_x[k][j] + sum_k u_y[i][k] Dy[j][k])
+    Stager P{0, S.Dx, make_rsrc(S.Dx, 0u), S.lddx, T.i0, nx, nx - 1};
+    Stager Q{2, nullptr, make_rsrc(S.ux, 4u * (nx - 1) * ny), ny, T.j0, ny, nx - 1};
+    tile_contract(P, Q, nx - 1, lds, accd);
+    Stager P2{1, nullptr, make_rsrc(S.uy, 4u * nx * (ny - 1)), ny - 1, T.i0, nx, ny - 1};
+    Stager Q2{0, S.Dy, make_rsrc(S.Dy, 0u), S.lddy, T.j0, ny, ny - 1};
+    tile_contract(P2, Q2, ny - 1, lds, accd);
+    Y = S.p; rows = nx; cols = ny; scale = S.sD;
+  }
+  const int j = T.j0 + tile_col();
+  float yv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = T.i0 + tile_row(r);
+    yv[r] = (i < rows && j < cols) ? Y[static_cast<int64_t>(i) * cols + j] : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = T.i0 + tile_row(r);
+    if (i < rows && j < cols)
+      Y[static_cast<int64_t>(i) * cols + j] = static_cast<float>(static_cast<double>(yv[r]) + scale * accd[r]);
+  }
+}
+
+__global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
+  __shared__ float lds[4 * TILE * LDB];
+  cg::grid_group grid = cg::this_grid();
+  for (int64_t s = 0; s < a.steps; ++s) {
+    for (int phase = 0; phase < 2; ++phase) {
+      const BatchTask* tasks = phase == 0 ? a.tasksA : a.tasksB;
+      const int n = phase == 0 ? a.nA : a.nB;
+      unsigned* ctr = a.counters + 2 * s + phase;
+      __shared__ int t_shared;
+      for (;;) {
+        if (threadIdx.x == 0) t_shared = static_cast<int>(atomicAdd(ctr, 1u));
+        lds_barrier();
+        const int t = t_shared;
+        lds_barrier();
+        if (t >= n) break;
+        const BatchTask T = tasks[t];
+        run_task(a.solves[T.solve], T, lds);
+      }
+      grid.sync();
+    }
+  }
+}
+
+__global__ void zero_u32(unsigned* p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+}  // namespace
+
+int batch2d_max_blocks(int* out) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch2d_kernel, NT, 0) != hipSuccess) return -1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+  *out = per_cu * cus;
+  return 0;
+}
+
+hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s) {
+  // fresh phase counters for every launch (a fill kernel, not a memset, so the launch can be captured)
+  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, 2 * a.steps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BatchArgs args = a;
+  void* params[] = {&args};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch2d_kernel), dim3(blocks), dim3(NT), params, 0, s);
+}
+
+}  // namespace pstd

@@ -51,7 +51,7 @@ struct KArgs {
   const T* X;
   T* Y;
   int64_t ncols, x_bstride, y_bstride;
-  T alpha, beta;
+  double alpha, beta;
   const T* scale;
 };
 
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(64 * WM * WN) void contract_kernel(KArgs<T> a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t idx = out_index(i, j, r);
-        yv[i][j][r] = (idx >= 0 && a.beta != T(0)) ? Y[idx] : T(0);
+        yv[i][j][r] = (idx >= 0 && a.beta != 0.0) ? Y[idx] : T(0);
         sv[i][j][r] = (idx >= 0 && S) ? S[idx] : T(1);
       }
 #pragma unroll
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(64 * WM * WN) void contract_kernel(KArgs<T> a) {
         if (idx < 0) continue;
         // the product, the map factor and the update are formed in FP64 and rounded once
         const double prod = kFlush ? accd[kFlush ? i : 0][kFlush ? j : 0][r] : static_cast<double>(acc[i][j][r]);
-        const double v = static_cast<double>(a.alpha) * prod * static_cast<double>(sv[i][j][r]);
-        Y[idx] = static_cast<T>(static_cast<double>(a.beta) * static_cast<double>(yv[i][j][r]) + v);
+        const double v = a.alpha * prod * static_cast<double>(sv[i][j][r]);
+        Y[idx] = static_cast<T>(a.beta * static_cast<double>(yv[i][j][r]) + v);
       }
 }
 
@@ -204,8 +204,8 @@ hipError_t launch_t(const ContractArgs& c, bool contiguous, hipStream_t s) {
   a.ncols = c.ncols;
   a.x_bstride = c.x_bstride;
   a.y_bstride = c.y_bstride;
-  a.alpha = static_cast<T>(sizeof(T) == 8 ? c.alpha_d : c.alpha);
-  a.beta = static_cast<T>(sizeof(T) == 8 ? c.beta_d : c.beta);
+  a.alpha = c.alpha_d;
+  a.beta = c.beta_d;
   a.scale = static_cast<const T*>(c.scale);
   const int64_t nb = (c.ncols + BN - 1) / BN;
   const int64_t mb = (c.M + BM - 1) / BM;

@@ -217,3 +217,102 @@ def combine_fields(fields, weights, out=None, stream=None):
     check(load().pstd_combine_fields(ptrs, w, n, C.c_void_p(out.data_ptr()), fields[0].numel(),
                                      _stream_handle(stream)), "pstd_combine_fields")
     return out
+
+
+class Batch:
+    """Many independent 2D FP32 solves stepped by one persistent launch (include/pstd.h, pstd_batch_*).
+
+    solves: list of dicts with keys shape (nx, ny), bcs ((l, r), (l, r)), dx, dt, c0.
+    """
+
+    def __init__(self, solves, rho0=1000.0, stream=None):
+        torch = _torch()
+        lib = load()
+        self.solves = [dict(s) for s in solves]
+        self.count = len(self.solves)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        n = (C.c_int64 * (2 * self.count))()
+        bc = (C.c_int32 * (4 * self.count))()
+        dx = (C.c_double * self.count)()
+        dt = (C.c_double * self.count)()
+        c0 = (C.c_double * self.count)()
+        for i, s in enumerate(self.solves):
+            n[2 * i], n[2 * i + 1] = int(s["shape"][0]), int(s["shape"][1])
+            (bl, br), (bd, bu) = s["bcs"]
+            bc[4 * i:4 * i + 4] = [int(bl), int(br), int(bd), int(bu)]
+            dx[i], dt[i], c0[i] = float(s["dx"]), float(s["dt"]), float(s["c0"])
+        h = C.c_void_p()
+        check(lib.pstd_batch_create(self.count, n, bc, dx, dt, c0, float(rho0), _stream_handle(self._stream),
+                                    C.byref(h)), "pstd_batch_create")
+        self._h = h
+
+    def new_states(self, p0s):
+        torch = _torch()
+        out = []
+        for s, p0 in zip(self.solves, p0s):
+            nx, ny = s["shape"]
+            p = torch.as_tensor(np.asarray(p0)).to(device=self.device, dtype=torch.float32).contiguous().clone()
+            if tuple(p.shape) != (nx, ny):
+                raise ValueError("p0 shape mismatch")
+            ux = torch.zeros((nx - 1, ny), device=self.device, dtype=torch.float32)
+            uy = torch.zeros((nx, ny - 1), device=self.device, dtype=torch.float32)
+            out.append(State(p, [ux, uy], 0))
+        return out
+
+    def _c_states(self, states):
+        arr = (_lib.State * self.count)()
+        for i, st in enumerate(states):
+            arr[i] = st._c()
+        return arr
+
+    def init_states(self, states, u_mode="centred"):
+        arr = self._c_states(states)
+        check(load().pstd_batch_state_init(self._h, arr, {"centred": 0, "zero": 1, "keep": 2}[u_mode]),
+              "pstd_batch_state_init")
+        for st in states:
+            st.step = 0
+
+    def step(self, states, n_steps):
+        arr = self._c_states(states)
+        check(load().pstd_batch_step(self._h, arr, int(n_steps)), "pstd_batch_step")
+        for st in states:
+            st.step += int(n_steps)
+
+    def combine_R(self, states, pairs, R, outs=None):
+        """outs[i] = (1+R[i])/2 p_N + (1-R[i])/2 p_D for pairs (dirichlet index, neumann index)."""
+        torch = _torch()
+        npairs = len(pairs)
+        if outs is None:
+            outs = [torch.empty_like(states[d].p) for d, _ in pairs]
+        pr = (C.c_int32 * (2 * npairs))(*[int(x) for pair in pairs for x in pair])
+        rr = (C.c_double * npairs)(*[float(x) for x in R])
+        op = (C.c_void_p * npairs)(*[t.data_ptr() for t in outs])
+        check(load().pstd_batch_combine_R(self._h, self._c_states(states), pr, rr, op, npairs), "pstd_batch_combine_R")
+        return outs
+
+    def set_config(self, blocks=0, order=0):
+        check(load().pstd_batch_set_config(self._h, int(blocks), int(order)), "pstd_batch_set_config")
+
+    def autotune(self, trial_steps=5, cache_path=None):
+        cfg = (C.c_int32 * 3)()
+        check(load().pstd_batch_autotune(self._h, int(trial_steps),
+                                         cache_path.encode() if cache_path else None, cfg), "pstd_batch_autotune")
+        return {"blocks": cfg[0], "order": cfg[1], "from_cache": bool(cfg[2])}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pstd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,148 @@
+"""GPU parity of the batched persistent 2D solver against the FP64 oracle, solve by solve."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import TOL, rel_l2
+from oracle import pstd as opstd
+
+pytestmark = pytest.mark.gpu
+N, D = opstd.NEUMANN, opstd.DIRICHLET
+
+
+def _random_solves(seed, count, lo, hi):
+    rng = np.random.default_rng(seed)
+    solves, p0s = [], []
+    for _ in range(count):
+        shape = tuple(int(v) for v in rng.integers(lo, hi + 1, size=2))
+        faces = rng.integers(0, 2, size=4)
+        c0 = float(rng.uniform(1400, 1600))
+        solves.append({"shape": shape, "bcs": ((int(faces[0]), int(faces[1])), (int(faces[2]), int(faces[3]))),
+                       "dx": 1e-4, "dt": 0.3e-4 / c0, "c0": c0})
+        p0s.append(rng.standard_normal(shape))
+    return solves, p0s
+
+
+def _run(solves, p0s, steps, config=None, chunks=None):
+    import torch
+    from paper_2005_00322_amd import Batch
+    with Batch(solves) as b:
+        if config:
+            b.set_config(**config)
+        st = b.new_states(p0s)
+        b.init_states(st)
+        for n in (chunks or [steps]):
+            b.step(st, n)
+        torch.cuda.synchronize()
+        return [s.p.double().cpu().numpy() for s in st], [[u.double().cpu().numpy() for u in s.u] for s in st]
+
+
+@pytest.mark.parametrize("seed,count,lo,hi", [(1, 5, 5, 40), (2, 7, 30, 140), (3, 3, 3, 12)])
+def test_batch_matches_oracle(seed, count, lo, hi):
+    solves, p0s = _random_solves(seed, count, lo, hi)
+    print("batch", [s["shape"] for s in solves], flush=True)
+    ps, us = _run(solves, p0s, 30)
+    for s, p0, p, u in zip(solves, p0s, ps, us):
+        prob = opstd.Problem(s["shape"], s["bcs"], s["dx"], s["dt"], s["c0"])
+        po, uo = prob.run(p0, 30)
+        assert rel_l2(p, po) < TOL["fp32"]
+        for a in range(2):
+            assert rel_l2(u[a], uo[a]) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("config", [{"blocks": 0, "order": 1}, {"blocks": 256, "order": 0}])
+def test_batch_configs_agree(config):
+    solves, p0s = _random_solves(4, 6, 20, 100)
+    a, _ = _run(solves, p0s, 20)
+    b, _ = _run(solves, p0s, 20, config=config)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)      # same tiles, same arithmetic: order and block count do not matter
+
+
+def test_batch_chunks_bitwise():
+    solves, p0s = _random_solves(5, 4, 20, 70)
+    a, _ = _run(solves, p0s, 23)
+    b, _ = _run(solves, p0s, 23, chunks=[1, 10, 12])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batch_combine_pairs():
+    import torch
+    from paper_2005_00322_amd import Batch
+    rng = np.random.default_rng(11)
+    solves, p0s, R, pairs = [], [], [], []
+    for i in range(3):
+        shape = tuple(int(v) for v in rng.integers(20, 70, size=2))
+        c0 = float(rng.uniform(1400, 1600))
+        g = workloads.gaussian(shape, 1e-4, (shape[0] * 0.5e-4, shape[1] * 0.5e-4), 4e-4)
+        for bc in (D, N):
+            solves.append({"shape": shape, "bcs": ((bc, bc), (bc, bc)), "dx": 1e-4, "dt": 0.3e-4 / c0, "c0": c0})
+            p0s.append(g)
+        pairs.append((2 * i, 2 * i + 1))
+        R.append(float(rng.uniform(-1, 1)))
+    with Batch(solves) as b:
+        st = b.new_states(p0s)
+        b.init_states(st)
+        b.step(st, 40)
+        outs = b.combine_R(st, pairs, R)
+        torch.cuda.synchronize()
+        got = [o.double().cpu().numpy() for o in outs]
+    for (d, n), r, g in zip(pairs, R, got):
+        sd, sn = solves[d], solves[n]
+        pd, _ = opstd.Problem(sd["shape"], sd["bcs"], 1e-4, sd["dt"], sd["c0"]).run(p0s[d], 40)
+        pn, _ = opstd.Problem(sn["shape"], sn["bcs"], 1e-4, sn["dt"], sn["c0"]).run(p0s[n], 40)
+        assert rel_l2(g, opstd.combine_R(pd, pn, r)) < TOL["fp32"]
+
+
+def test_batch_autotune_cache(tmp_path):
+    from paper_2005_00322_amd import Batch
+    solves, p0s = _random_solves(6, 5, 30, 90)
+    cache = os.path.join(str(tmp_path), "tune.json")
+    with Batch(solves) as b:
+        cfg = b.autotune(trial_steps=3, cache_path=cache)
+        assert not cfg["from_cache"] and os.path.exists(cache)
+        cfg2 = b.autotune(trial_steps=3, cache_path=cache)
+        assert cfg2["from_cache"] and cfg2["blocks"] == cfg["blocks"] and cfg2["order"] == cfg["order"]
+    a, _ = _run(solves, p0s, 15)
+    c, _ = _run(solves, p0s, 15, config={"blocks": cfg["blocks"], "order": cfg["order"]})
+    for x, y in zip(a, c):
+        assert np.array_equal(x, y)
+
+
+def test_batched_workload_full():
+    """The 128-instance workload (paired all-Neumann / all-Dirichlet solves, sides 96..512, 1000 steps)
+    against the oracle's closed form for every solve, and the combination for every instance."""
+    import torch
+    from paper_2005_00322_amd import Batch
+    wl = workloads.batched()
+    solves, p0s, pairs, R = [], [], [], []
+    for i, inst in enumerate(wl["instances"]):
+        for bc in (D, N):
+            solves.append({"shape": inst.shape, "bcs": ((bc, bc), (bc, bc)), "dx": wl["dx"], "dt": inst.dt,
+                           "c0": inst.c0})
+            p0s.append(inst.p0)
+        pairs.append((2 * i, 2 * i + 1))
+        R.append(inst.R)
+    steps = wl["steps"]
+    with Batch(solves) as b:
+        st = b.new_states(p0s)
+        b.init_states(st)
+        b.step(st, steps)
+        outs = b.combine_R(st, pairs, R)
+        torch.cuda.synchronize()
+        ps = [s.p.double().cpu().numpy() for s in st]
+        comb = [o.double().cpu().numpy() for o in outs]
+    worst = 0.0
+    for i, inst in enumerate(wl["instances"]):
+        refs = []
+        for k, bc in enumerate((D, N)):
+            prob = opstd.Problem(inst.shape, ((bc, bc), (bc, bc)), wl["dx"], inst.dt, inst.c0)
+            ref = prob.modal_solution(inst.p0, steps)
+            refs.append(ref)
+            worst = max(worst, rel_l2(ps[2 * i + k], ref))
+        worst = max(worst, rel_l2(comb[i], opstd.combine_R(refs[0], refs[1], inst.R)))
+    print("batched workload worst rel L2", worst, flush=True)
+    assert worst < TOL["fp32"]
