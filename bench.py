@@ -1,6 +1,6 @@
 """Benchmark of the PSTD time-step hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d|batched|pstd2d_large]
 
 One bench step is one PSTD time step over the whole grid: every axis's velocity update (forward DTT,
 k-space multiply with the type switch, inverse DTT, leapfrog update; one fused contraction kernel per
@@ -39,6 +39,7 @@ WORKLOADS = {
     "pstd3d": ("pstd3d", "split_bf16", 100, 10),
     "pstd1d": ("pstd1d", "fp64", 1000, 100),
     "batched": ("batched", "fp32", 1000, 10),
+    "pstd2d_large": ("pstd2d_large", "fp32", 200, 20),
 }
 
 
@@ -52,18 +53,43 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def contraction_cost(shape, axis, which, precision):
-    """Algorithmic flops and bytes of one contraction launch (kernel table).
+def fft_factorable(n):
+    L = 2 * (n - 1)
+    if L < 16 or L % 16:
+        return False
+    for f in (2, 3, 5):
+        while L % f == 0:
+            L //= f
+    return L == 1
 
-    Flops: 2*n_in per output point (a dense n_out x n_in operator applied along the axis; three bf16
-    products for split-bf16).  Bytes: the input field read once, the output field read and written once.
+
+def uses_fft(shape, axis, precision):
+    """Mirrors the library's automatic choice: axes above 512 nodes (1D: above 1365) with 2(n-1) =
+    16 x 2^a 3^b 5^c run on the FFT path."""
+    n = shape[axis]
+    lim = 1365 if len(shape) == 1 else 512
+    cap = 8192 if precision == "fp64" else 16384
+    return n > lim and fft_factorable(n) and 2 * (n - 1) <= cap
+
+
+def contraction_cost(shape, axis, which, precision):
+    """Algorithmic flops and bytes of one launch along an axis (kernel table).
+
+    Dense path: 2*n_in flops per output point (a dense n_out x n_in operator applied along the axis;
+    three bf16 products for split-bf16).  FFT path: 2 x 5 L log2(L) / 2 flops per line (a forward and an
+    inverse complex transform of length L = 2(n-1) shared by two lines).  Bytes: the input field read
+    once, the output field read and written once.
     """
     n = shape[axis]
     n_in = n if which == 0 else n - 1
     n_out = n - 1 if which == 0 else n
     lines = int(np.prod(shape)) // n
     esz = 8 if precision == "fp64" else 4
-    flops = 2.0 * n_in * n_out * lines * (3 if precision == "split_bf16" else 1)
+    if uses_fft(shape, axis, precision):
+        L = 2 * (n - 1)
+        flops = 5.0 * L * np.log2(L) * lines
+    else:
+        flops = 2.0 * n_in * n_out * lines * (3 if precision == "split_bf16" else 1)
     bytes_ = esz * lines * (n_in + 2 * n_out)
     return flops, bytes_
 
@@ -345,10 +371,14 @@ def main():
     gbs = bytes_ / (dur_ms * 1e-3) / 1e9
     tfs = flops / (dur_ms * 1e-3) / 1e12
     peak_c = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"], "split_bf16": PEAK["bf16_TFs"]}[precision]
+    if axis >= 0 and uses_fft(case.shape, axis, precision):
+        peak_c = PEAK["fp64_TFs"] if precision == "fp64" else PEAK["fp32_TFs"]   # FFT butterflies: vector ALU
     ai = flops / bytes_
     ridge = peak_c * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     src_hash = kernel_source_hash()
     key = ("fused" if axis < 0 else "axis%d" % axis) + "_" + ("velocity" if which == 0 else "pressure")
+    if axis >= 0 and uses_fft(case.shape, axis, precision):
+        key += "_fft"
     traffic = load_traffic(args.workload, key, src_hash)
     if ai < ridge:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",

@@ -73,8 +73,11 @@ typedef struct pstd_plan_s* pstd_plan;
  * operator G_a = T2^{-1} diag(a1) T1 ((n-1) x n) and the pressure operator D_a = T1^{-1} diag(a2) T2
  * (n x (n-1)), with the DC/Nyquist entries dropped or zero-padded as in the appendix tables
  * "Differentiation with staggered grids", folds -dt/rho0 and -dt rho0 c0^2 into them, rounds them to
- * the plan's precision and copies them to the device.  Returns PSTD_E_UNSTABLE if the time step is
- * above the stability limit. */
+ * the plan's precision and copies them to the device.  Axes that start on the FFT path (see pstd_path)
+ * get FFT tables instead (twiddles and the spectral multipliers, also formed in FP64).  Sizes: n <= 4097
+ * per axis on the dense path; up to 8193 (FP32 state) or 4097 (FP64) where 2(n-1) = 16 x 2^a 3^b 5^c;
+ * 1D plans above 1365 nodes only on the FFT path.  Returns PSTD_E_UNSTABLE if the time step is above the
+ * stability limit, PSTD_E_UNSUPPORTED for sizes outside these limits. */
 int pstd_plan_create(const pstd_grid* grid, double dx, double dt, double c0,
                      const int32_t bc_per_face[6], pstd_plan* out);
 
@@ -98,13 +101,21 @@ int pstd_state_init(pstd_plan plan, pstd_state* state, int32_t u_mode);
  * p^n first, then p^{n+1} from all u_a^{n+1/2}.  Asynchronous on the plan's stream. */
 int pstd_step(pstd_plan plan, pstd_state* state, int64_t n_steps);
 
-/* Execution path of pstd_step.  AUTO picks FUSED for 2D FP32 grids of at most 512 x 512 nodes (two
- * kernels per step: every velocity tile, then every pressure tile with both axes' terms) and PER_AXIS
- * otherwise (one contraction kernel per axis and half step).  Both replay captured HIP graphs and
- * compute the same step; the choice only changes speed and rounding order. */
-typedef enum { PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2 } pstd_path;
+/* Execution path of pstd_step.
+ *   PER_AXIS: one dense contraction kernel per axis and half step (axes up to 4097 nodes).
+ *   FUSED:    2D FP32 grids of at most 512 x 512 nodes: two kernels per step (every velocity tile, then
+ *             every pressure tile with both axes' terms).
+ *   FFT:      every axis whose extended period 2(n-1) is 16 x 2^a 3^b 5^c (up to 16384 for a float state,
+ *             8192 for FP64) applies its operators as LDS-resident FFTs of the field's symmetric
+ *             extension (§3.2: each DTT is a DFT of an evenly or oddly extended sequence), one kernel per
+ *             axis and half step; other axes stay dense.
+ *   AUTO:     FUSED where it applies; otherwise FFT on axes above 512 nodes (1D plans: above 1365) and
+ *             dense contractions elsewhere.
+ * All compute the same step and replay captured HIP graphs; the choice changes speed and rounding only. */
+typedef enum { PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2, PSTD_PATH_FFT = 3 } pstd_path;
 
-/* Select the execution path of later pstd_step calls.  PSTD_E_UNSUPPORTED if the plan cannot use it. */
+/* Select the execution path of later pstd_step calls (builds dense operators on first use when an axis
+ * moves off the FFT path).  PSTD_E_UNSUPPORTED if the plan cannot use it. */
 int pstd_plan_set_path(pstd_plan plan, int32_t path);
 
 /* One term of the step on its own: which = 0 applies the velocity update of axis `axis`,

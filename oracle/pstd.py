@@ -307,6 +307,31 @@ class Problem:
         return 2.0 / (self.dx * np.sqrt(kmax2))
 
 
+def axis_mode(n: int, bc_left: int, bc_right: int, dx: float, m: int) -> tuple[np.ndarray, float]:
+    """Pressure basis function m of one axis on its n nodes, and its wavenumber k_m.
+
+    The basis is the inverse T1 transform of a unit coefficient (Table transform_choices gives T1,
+    Table DTT_wavenumber_groups its wavenumbers): a cosine or sine of k_m x sampled on the nodes, 0 on
+    Dirichlet wall nodes, scaled to a maximum magnitude of 1.  Under the operators of
+    Eq. (dtt_pstd_solution) it is an eigenfunction: div(grad(mode)) = -k_m^2 mode.
+    """
+    ax = Axis(n, bc_left, bc_right, dx)
+    e = np.zeros(len(ax.k1))
+    e[m] = 1.0
+    col = ax.T1inv @ e
+    out = np.zeros(n)
+    out[ax.p_lo:ax.p_hi + 1] = col / np.max(np.abs(col))
+    return out, float(ax.k1[m])
+
+
+def mode_phase(c0: float, dt: float, ksq: float) -> float:
+    """Phase advance per step of a single mode under the leapfrog: sin(theta/2) = c0 dt |k| / 2."""
+    s = c0 * dt * np.sqrt(ksq) / 2.0
+    if s > 1.0:
+        raise ValueError("unstable: c0 dt |k| / 2 > 1")
+    return 2.0 * float(np.arcsin(s))
+
+
 # -- §5: arbitrary real reflection coefficients by weighted sums of the Neumann/Dirichlet fields ------
 
 # Columns: image-source polarities of the four basic 1D cases (R_L, R_R) = (1,1), (1,-1), (-1,1), (-1,-1);

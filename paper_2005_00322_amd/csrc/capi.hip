@@ -1,4 +1,5 @@
 // libpstd C ABI: plan creation (operator tables), state initialisation, stepping, combination.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -98,6 +99,7 @@ void free_plan(pstd_plan_s* P) {
     if (P->G[a].dataT) (void)hipFree(P->G[a].dataT);
     if (P->D[a].data) (void)hipFree(P->D[a].data);
     if (P->D[a].dataT) (void)hipFree(P->D[a].dataT);
+    fft_axis_free(&P->fft[a]);
   }
   if (P->c2map) (void)hipFree(P->c2map);
   if (P->flag) (void)hipFree(P->flag);
@@ -116,6 +118,42 @@ void axis_geometry(const pstd_plan_s* P, int a, int64_t* outer, int64_t* inner) 
   for (int b = a + 1; b < P->ndim; ++b) i *= P->n[b];
   *outer = o;
   *inner = i;
+}
+
+// Constants folded into the operators: velocity -dt/(rho0 dx), pressure -dt rho0 c0^2/dx (c0^2 from the
+// map, applied pointwise, when the plan has one).
+double const_G(const pstd_plan_s* P) { return -P->dt / P->rho0 / P->dx; }
+double const_D(const pstd_plan_s* P) { return -P->dt * P->rho0 * (P->c2map ? 1.0 : P->c0 * P->c0) / P->dx; }
+
+// Dense operators of axis a, built on first use for axes that start on the FFT path.
+int ensure_dense(pstd_plan_s* P, int a) {
+  if (P->G[a].data) return PSTD_OK;
+  const int n = static_cast<int>(P->n[a]);
+  if (n > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: dense operators are limited to 4097 nodes", a);
+  const AxisTables& t = axis_tables(n, axis_case(P->bc[2 * a], P->bc[2 * a + 1]));
+  int st = upload_operator(P, t.G, n - 1, n, const_G(P), &P->G[a]);
+  if (st == PSTD_OK) st = upload_operator(P, t.D, n, n - 1, const_D(P), &P->D[a]);
+  return st;
+}
+
+// Whether axis a runs on the FFT path under the plan's current path setting.  AUTO: axes above 512
+// nodes (1D plans keep the single-workgroup kernel up to 1365 nodes).
+bool axis_fft(const pstd_plan_s* P, int a) {
+  if (!P->fft[a].ok) return false;
+  if (P->path == PSTD_PATH_FFT) return true;
+  if (P->path != PSTD_PATH_AUTO) return false;
+  if (P->ndim == 1) return P->n[0] > 1365;
+  return P->n[a] > 512;
+}
+
+// Make sure every axis has what its path needs (called before any capture).
+int prepare_axes(pstd_plan_s* P) {
+  for (int a = 0; a < P->ndim; ++a)
+    if (!axis_fft(P, a)) {
+      const int st = ensure_dense(P, a);
+      if (st != PSTD_OK) return st;
+    }
+  return PSTD_OK;
 }
 
 hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const void* X, void* Y, double alpha,
@@ -153,8 +191,63 @@ hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const vo
   return launch_contract_split(c, contiguous, s);
 }
 
+// Y = beta Y + alpha scale (op X) along axis a with the velocity (which = 0) or pressure (which = 1)
+// operator, on the axis's FFT or dense path.
+hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void* Y, double alpha, double beta,
+                    const void* scale, hipStream_t s) {
+  if (!axis_fft(P, a)) return contract(P, which == 0 ? P->G[a] : P->D[a], a, X, Y, alpha, beta, scale, s);
+  const FftAxis& f = P->fft[a];
+  FftArgs x{};
+  x.X = X;
+  x.Y = Y;
+  x.scale = scale;
+  x.tw = f.tw;
+  x.om = f.om;
+  x.H = f.H[which];
+  x.alpha = alpha;
+  x.beta = beta;
+  x.N = f.N;
+  x.L = f.L;
+  const int n = static_cast<int>(P->n[a]);
+  x.nin = which == 0 ? n : n - 1;
+  x.nout = which == 0 ? n - 1 : n;
+  x.dir = which;
+  x.sL = f.sL;
+  x.sR = f.sR;
+  x.anti = f.sL * f.sR < 0;
+  x.npass = f.npass;
+  for (int i = 0; i < 8; ++i) x.radix[i] = f.radix[i];
+  int64_t outer, inner;
+  axis_geometry(P, a, &outer, &inner);
+  x.contig = a == P->ndim - 1;
+  const int64_t lines = x.contig ? outer : outer * inner;
+  // transforms per block: enough blocks to fill the chip first (about 1024), then as many lines per
+  // block as LDS holds; at least 64 threads (F L / 16) where LDS allows
+  const int fmax = fft_capacity(P->prec == PSTD_FP64) / f.L;
+  int F = static_cast<int>(std::min<int64_t>(fmax, std::max<int64_t>(1, lines / 2048)));
+  F = std::max(F, std::min(fmax, std::max(1, 1024 / f.L)));
+  F = static_cast<int>(std::min<int64_t>(F, (lines + 1) / 2));
+  F = std::max(F, 1);
+  x.F = F;
+  const int W = 2 * F;
+  if (x.contig) {
+    x.ncols = outer;
+    x.gpb = 0;
+    x.groups = (outer + W - 1) / W;
+    x.x_bstride = x.y_bstride = 0;
+  } else {
+    x.ncols = inner;
+    x.gpb = (inner + W - 1) / W;
+    x.groups = outer * x.gpb;
+    x.x_bstride = static_cast<int64_t>(x.nin) * inner;
+    x.y_bstride = static_cast<int64_t>(x.nout) * inner;
+  }
+  x.xcd_spread = x.groups >= 64;
+  return launch_fft_axis(P->prec == PSTD_FP64, x, s);
+}
+
 bool use_fused2d(const pstd_plan_s* P) {
-  return P->ndim == 2 && P->prec == PSTD_FP32 && P->path != PSTD_PATH_PER_AXIS &&
+  return P->ndim == 2 && P->prec == PSTD_FP32 && (P->path == PSTD_PATH_AUTO || P->path == PSTD_PATH_FUSED) &&
          phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]));
 }
 
@@ -168,11 +261,11 @@ hipError_t enqueue_steps(pstd_plan_s* P, pstd_state* st, int64_t nsteps, hipStre
                           nsteps, s);
   for (int64_t t = 0; t < nsteps; ++t) {
     for (int a = 0; a < P->ndim; ++a) {
-      hipError_t e = contract(P, P->G[a], a, st->p, st->u[a], 1.0, 1.0, nullptr, s);
+      hipError_t e = apply_op(P, a, 0, st->p, st->u[a], 1.0, 1.0, nullptr, s);
       if (e != hipSuccess) return e;
     }
     for (int a = 0; a < P->ndim; ++a) {
-      hipError_t e = contract(P, P->D[a], a, st->u[a], st->p, 1.0, 1.0, P->c2map, s);
+      hipError_t e = apply_op(P, a, 1, st->u[a], st->p, 1.0, 1.0, P->c2map, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -220,14 +313,19 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   if (precision < PSTD_FP64 || precision > PSTD_SPLIT_BF16) return fail(PSTD_E_INVALID_ARG, "bad precision");
   for (int a = 0; a < grid->ndim; ++a) {
     if (grid->n[a] < 3) return fail(PSTD_E_INVALID_ARG, "axis %d has %lld nodes (need >= 3)", a, (long long)grid->n[a]);
-    if (grid->n[a] > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: %lld nodes above 4097", a, (long long)grid->n[a]);
+    if (grid->n[a] > 4097 && !(grid->n[a] <= 16385 && fft_axis_possible(static_cast<int>(grid->n[a]), precision)))
+      return fail(PSTD_E_UNSUPPORTED,
+                  "axis %d: %lld nodes; above 4097 the FFT path needs 2(n-1) = 16 x 2^a 3^b 5^c within %d (%s)", a,
+                  (long long)grid->n[a], fft_capacity(precision == PSTD_FP64),
+                  precision == PSTD_FP64 ? "FP64" : "FP32 state");
     for (int f = 0; f < 2; ++f)
       if (bc_per_face[2 * a + f] != PSTD_NEUMANN && bc_per_face[2 * a + f] != PSTD_DIRICHLET)
         return fail(PSTD_E_INVALID_ARG, "bad boundary condition on face %d", 2 * a + f);
   }
   if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
     return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
-  if (grid->ndim == 1 && grid->n[0] > 1365) return fail(PSTD_E_UNSUPPORTED, "1D grids are limited to 1365 nodes");
+  if (grid->ndim == 1 && grid->n[0] > 1365 && !fft_axis_possible(static_cast<int>(grid->n[0]), precision))
+    return fail(PSTD_E_UNSUPPORTED, "1D grids above 1365 nodes need the FFT path (2(n-1) = 16 x 2^a 3^b 5^c)");
   int64_t total = 1;
   for (int a = 0; a < grid->ndim; ++a) total *= grid->n[a];
   if (total > (int64_t(1) << 31)) return fail(PSTD_E_UNSUPPORTED, "grid above 2^31 points");
@@ -237,8 +335,8 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   // stability: c0 dt |k|_max / 2 <= 1 with |k|_max^2 the sum of the per-axis maxima
   double kmax2 = 0.0;
   for (int a = 0; a < grid->ndim; ++a) {
-    const AxisTables& t = axis_tables(static_cast<int>(grid->n[a]), axis_case(bc_per_face[2 * a], bc_per_face[2 * a + 1]));
-    kmax2 += (t.kmax / dx) * (t.kmax / dx);
+    const double km = axis_kmax(static_cast<int>(grid->n[a]), axis_case(bc_per_face[2 * a], bc_per_face[2 * a + 1]));
+    kmax2 += (km / dx) * (km / dx);
   }
   if (c0 * dt * std::sqrt(kmax2) / 2.0 > 1.0)
     return fail(PSTD_E_UNSTABLE, "c0*dt/dx = %g above the limit %g", c0 * dt / dx, 2.0 / (dx * std::sqrt(kmax2)));
@@ -262,10 +360,7 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   const double sG = -dt / rho0 / dx;
   const double sD = -dt * rho0 * (c0_map_dev ? 1.0 : c0 * c0) / dx;
   for (int a = 0; a < P->ndim; ++a) {
-    const int n = static_cast<int>(P->n[a]);
-    const AxisTables& t = axis_tables(n, axis_case(P->bc[2 * a], P->bc[2 * a + 1]));
-    int st = upload_operator(P, t.G, n - 1, n, sG, &P->G[a]);
-    if (st == PSTD_OK) st = upload_operator(P, t.D, n, n - 1, sD, &P->D[a]);
+    int st = fft_axis_setup(P, a, sG, sD);
     if (st != PSTD_OK) {
       free_plan(P);
       return st;
@@ -284,6 +379,11 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
       free_plan(P);
       return fail(PSTD_E_HIP, "squaring the c0 map failed");
     }
+  }
+  const int st = prepare_axes(P);
+  if (st != PSTD_OK) {
+    free_plan(P);
+    return st;
   }
   *out = P;
   return PSTD_OK;
@@ -309,6 +409,8 @@ int pstd_state_init(pstd_plan P, pstd_state* st, int32_t u_mode) {
   for (int a = 0; a < P->ndim; ++a)
     if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
   if (u_mode < 0 || u_mode > 2) return fail(PSTD_E_INVALID_ARG, "u_mode must be 0, 1 or 2");
+  const int pst = prepare_axes(P);
+  if (pst != PSTD_OK) return pst;
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int a = 0; a < P->ndim; ++a) {
     lo[a] = P->bc[2 * a] == PSTD_DIRICHLET;
@@ -322,7 +424,7 @@ int pstd_state_init(pstd_plan P, pstd_state* st, int32_t u_mode) {
       continue;
     }
     // u^{-1/2} = +(dt/(2 rho0)) G p = -1/2 * (folded operator) p  (beta = 0: u is not read)
-    PSTD_HIP(contract(P, P->G[a], a, st->p, st->u[a], -0.5, 0.0, nullptr, P->stream));
+    PSTD_HIP(apply_op(P, a, 0, st->p, st->u[a], -0.5, 0.0, nullptr, P->stream));
   }
   st->step = 0;
   return PSTD_OK;
@@ -334,7 +436,9 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
     if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
   if (n_steps < 0) return fail(PSTD_E_INVALID_ARG, "n_steps < 0");
   if (n_steps == 0) return PSTD_OK;
-  if (P->ndim == 1) {
+  const int pst = prepare_axes(P);
+  if (pst != PSTD_OK) return pst;
+  if (P->ndim == 1 && !axis_fft(P, 0)) {
     PSTD_HIP(launch_step1d(P->prec, P->G[0], P->D[0], st->p, st->u[0], static_cast<int>(P->n[0]), n_steps,
                            P->c2map, P->stream));
     st->step += n_steps;
@@ -380,12 +484,23 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
 
 int pstd_plan_set_path(pstd_plan P, int32_t path) {
   if (!P) return fail(PSTD_E_INVALID_ARG, "null plan");
-  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_FUSED) return fail(PSTD_E_INVALID_ARG, "bad path");
+  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_FFT) return fail(PSTD_E_INVALID_ARG, "bad path");
+  if (path == PSTD_PATH_FFT) {
+    bool any = false;
+    for (int a = 0; a < P->ndim; ++a) any = any || P->fft[a].ok;
+    if (!any) return fail(PSTD_E_UNSUPPORTED, "no axis has 2(n-1) = 16 x 2^a 3^b 5^c within the FFT capacity");
+  }
   if (path == PSTD_PATH_FUSED &&
       !(P->ndim == 2 && P->prec == PSTD_FP32 &&
         phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]))))
     return fail(PSTD_E_UNSUPPORTED, "the fused path needs a 2D FP32 plan of at most 512 x 512 nodes");
+  const int old = P->path;
   P->path = path;
+  const int pst = prepare_axes(P);
+  if (pst != PSTD_OK) {
+    P->path = old;
+    return pst;
+  }
   if (P->graph_exec) {  // a captured graph may belong to the other path
     (void)hipGraphExecDestroy(P->graph_exec);
     P->graph_exec = nullptr;
@@ -417,8 +532,10 @@ int pstd_apply_axis(pstd_plan P, pstd_state* st, int32_t axis, int32_t which) {
     return PSTD_OK;
   }
   if (!st->u[axis]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", axis);
-  if (which == 0) PSTD_HIP(contract(P, P->G[axis], axis, st->p, st->u[axis], 1.0, 1.0, nullptr, P->stream));
-  else PSTD_HIP(contract(P, P->D[axis], axis, st->u[axis], st->p, 1.0, 1.0, P->c2map, P->stream));
+  const int pst = prepare_axes(P);
+  if (pst != PSTD_OK) return pst;
+  if (which == 0) PSTD_HIP(apply_op(P, axis, 0, st->p, st->u[axis], 1.0, 1.0, nullptr, P->stream));
+  else PSTD_HIP(apply_op(P, axis, 1, st->u[axis], st->p, 1.0, 1.0, P->c2map, P->stream));
   return PSTD_OK;
 }
 
@@ -475,6 +592,8 @@ int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, 
 int pstd_plan_get_operator(pstd_plan P, int32_t axis, int32_t which, double* out) {
   if (!P || !out) return fail(PSTD_E_INVALID_ARG, "null pointer");
   if (axis < 0 || axis >= P->ndim || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  const int est = ensure_dense(P, axis);
+  if (est != PSTD_OK) return est;
   const DevOperator& op = which == 0 ? P->G[axis] : P->D[axis];
   const size_t cnt = static_cast<size_t>(op.Mp) * op.Kp;
   if (P->prec == PSTD_FP64) {

@@ -44,6 +44,10 @@ struct AxisTables {
 // Returns a cached table (built once per (n, case) in the process).
 const AxisTables& axis_tables(int n, AxisCase c);
 
+// Largest |k| of the pressure basis for dx = 1 (the value AxisTables::kmax holds), without building the
+// tables.
+double axis_kmax(int n, AxisCase c);
+
 // ---- device helpers ------------------------------------------------------------------------------
 // Block barrier ordering only LDS accesses.  __syncthreads() also orders global memory, which makes the
 // compiler drain every outstanding global load (s_waitcnt vmcnt(0)) at each barrier and so defeats
@@ -133,6 +137,51 @@ hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s);
 
 hipError_t launch_nonfinite(int prec, const void* x, int64_t count, int* flag, hipStream_t s);
 
+// ---- FFT path of one axis (kernels_fft.hip, fft_plan.cpp) ------------------------------------------
+// Device tables of one axis whose extended period L = 2(n-1) is 16 x 2^a 3^b 5^c (in the state dtype:
+// complex float, or complex double for FP64 plans).
+struct FftAxis {
+  bool ok = false;              // the axis can use the FFT path
+  int N = 0, L = 0;             // N = n - 1, L = 2N
+  int npass = 0;
+  int radix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int sL = 1, sR = 1;           // +1 Neumann wall, -1 Dirichlet wall
+  void* tw = nullptr;           // L entries e^{-2 pi i t / L}
+  void* om = nullptr;           // L entries e^{-i pi j / L} (mixed walls only)
+  void* H[2] = {nullptr, nullptr};   // spectral multipliers of G (0) and D (1), constants and 1/L folded in
+};
+
+struct FftArgs {
+  const void* X;                // input field
+  void* Y;                      // output field (read-modify-write)
+  const void* scale;            // optional per-point factor with Y's layout, may be null
+  const void* tw;
+  const void* om;
+  const void* H;
+  double alpha, beta;           // Y = beta Y + alpha scale (op X)
+  int N, L;
+  int nin, nout;                // extents of X and Y along the axis
+  int dir;                      // 0: G (nodes -> half nodes), 1: D (half nodes -> nodes)
+  int sL, sR, anti;
+  int F;                        // transforms per block (2F lines)
+  int npass;
+  int radix[8];
+  int contig;                   // 1: the axis is the unit-stride one (lines are rows)
+  int xcd_spread;               // launch is padded to a multiple of 8 blocks and line groups spread per XCD
+  int64_t ncols;                // contig: number of rows; strided: extent of the unit-stride block
+  int64_t gpb;                  // strided: line groups per outer block
+  int64_t groups;               // line groups (working blocks)
+  int64_t x_bstride, y_bstride; // strided: elements between outer blocks
+};
+
+// Radix passes for a transform of length L (all 16, 8, 4, 2, 3, 5); false if L is not 16 x 2^a 3^b 5^c or
+// needs more than 8 passes.
+bool fft_factor(int L, int* npass, int* radix);
+int fft_capacity(bool dbl);     // complex entries per block (F L at most)
+bool fft_axis_possible(int n, int prec);
+void fft_axis_free(FftAxis* f);
+hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s);
+
 }  // namespace pstd
 
 // ---- the plan --------------------------------------------------------------------------------------
@@ -144,7 +193,8 @@ struct pstd_plan_s {
   int prec = PSTD_FP32;
   hipStream_t stream = nullptr;
   int device = 0;
-  pstd::DevOperator G[3], D[3];
+  pstd::DevOperator G[3], D[3];  // dense operators (built when an axis runs the dense path)
+  pstd::FftAxis fft[3];
   void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
   int* flag = nullptr;         // device int for reductions (owned)
   int path = 0;                // PSTD_PATH_* (0 = automatic)
@@ -154,3 +204,9 @@ struct pstd_plan_s {
   int64_t graph_steps = 0;
   void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
 };
+
+namespace pstd {
+// Build the FFT tables of axis a (no-op when the axis cannot use the FFT path).  sG, sD: the constants
+// -dt/(rho0 dx) and -dt rho0 c0^2/dx of the velocity and pressure operators.
+int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD);
+}  // namespace pstd

@@ -155,6 +155,15 @@ std::map<std::pair<int, int>, AxisTables> g_cache;
 
 }  // namespace
 
+double axis_kmax(int n, AxisCase c) {
+  const CaseInfo ci = case_info(c);
+  const bool left_d = (c == CASE_DN || c == CASE_DD);
+  const bool right_d = (c == CASE_ND || c == CASE_DD);
+  const int Lp = (right_d ? n - 2 : n - 1) - (left_d ? 1 : 0) + 1;
+  const double shift = antiperiodic(ci.T1) ? 0.5 : 0.0;
+  return 2.0 * M_PI * (wave_index(ci.T1, Lp - 1) + shift) / (2.0 * (n - 1));
+}
+
 const AxisTables& axis_tables(int n, AxisCase c) {
   std::lock_guard<std::mutex> lock(g_cache_mu);
   auto key = std::make_pair(n, static_cast<int>(c));

@@ -106,10 +106,14 @@ class Plan:
         s[a] -= 1
         return tuple(s)
 
-    def new_state(self, p0) -> State:
+    def new_state(self, p0=None) -> State:
+        """Device state with p = p0 (zeros if None) and u = 0."""
         torch = _torch()
-        p = torch.as_tensor(np.asarray(p0) if not isinstance(p0, torch.Tensor) else p0)
-        p = p.to(device=self.device, dtype=self.dtype).contiguous().clone()
+        if p0 is None:
+            p = torch.zeros(self.shape, device=self.device, dtype=self.dtype)
+        else:
+            p = torch.as_tensor(np.asarray(p0) if not isinstance(p0, torch.Tensor) else p0)
+            p = p.to(device=self.device, dtype=self.dtype).contiguous().clone()
         if tuple(p.shape) != self.shape:
             raise ValueError("p0 has shape %s, plan expects %s" % (tuple(p.shape), self.shape))
         u = [torch.zeros(self.u_shape(a), device=self.device, dtype=self.dtype) for a in range(self.ndim)]
@@ -139,10 +143,11 @@ class Plan:
         st.step = cs.step
         return st
 
-    PATHS = {"auto": 0, "per_axis": 1, "fused": 2}
+    PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3}
 
     def set_path(self, path: str) -> None:
-        """Execution path of later steps: "auto", "per_axis" or "fused" (2D FP32: two kernels per step)."""
+        """Execution path of later steps: "auto", "per_axis" (dense contractions), "fused" (2D FP32: two
+        kernels per step) or "fft" (LDS-resident FFTs on every axis whose 2(n-1) is 16 x 2^a 3^b 5^c)."""
         check(load().pstd_plan_set_path(self._h, self.PATHS[path]), "pstd_plan_set_path")
 
     def apply_axis(self, st: State, axis: int, which: int) -> None:

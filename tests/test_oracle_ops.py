@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import dtt, pstd
+from oracle import pstd as opstd
 
 N, D = pstd.NEUMANN, pstd.DIRICHLET
 CASES = [(N, N), (N, D), (D, N), (D, D)]
@@ -106,3 +107,42 @@ def test_waws_forward_transform_reading():
     sample = f[1:]
     wrong = (ax.a1_sign * ax.k1 * (dtt.matrix("S", 4, n - 1) @ sample)) @ ax.T2inv.T
     assert np.max(np.abs(wrong - k * np.cos(k * xh))) > 1e-2 * k
+
+
+@pytest.mark.parametrize("bc", [(N, N), (N, D), (D, N), (D, D)])
+@pytest.mark.parametrize("n", [9, 26])
+def test_axis_mode_closed_form_and_eigen(bc, n):
+    # the pressure basis functions are the cosines/sines of Table DTT_wavenumber_groups on the nodes:
+    # NN cos(pi m j/N), DD sin(pi m j/N), ND cos(pi (m+1/2) j/N), DN sin(pi (m+1/2) j/N)
+    Nn = n - 1
+    j = np.arange(n)
+    dx = 0.5
+    ax = opstd.Axis(n, bc[0], bc[1], dx)
+    for m in range(len(ax.k1)):
+        mode, k = opstd.axis_mode(n, bc[0], bc[1], dx, m)
+        if bc == (N, N):
+            ref, kr = np.cos(np.pi * m * j / Nn), np.pi * m / Nn
+        elif bc == (D, D):
+            ref, kr = np.sin(np.pi * (m + 1) * j / Nn), np.pi * (m + 1) / Nn
+        elif bc == (N, D):
+            ref, kr = np.cos(np.pi * (m + 0.5) * j / Nn), np.pi * (m + 0.5) / Nn
+        else:
+            ref, kr = np.sin(np.pi * (m + 0.5) * j / Nn), np.pi * (m + 0.5) / Nn
+        ref = ref / np.max(np.abs(ref))
+        assert np.allclose(mode, ref, atol=1e-12)
+        assert abs(k - kr / dx) < 1e-12 / dx
+        # eigenfunction of div o grad with eigenvalue -k^2
+        assert np.allclose(ax.div_matrix() @ (ax.grad_matrix() @ mode), -k * k * mode, atol=1e-10 * max(k * k, 1.0 / dx**2))
+
+
+def test_single_mode_evolves_with_the_leapfrog_phase():
+    # 2D, one mode per axis: p^m = cos(m theta) p^0 with sin(theta/2) = c0 dt |k| / 2
+    shape, bcs, dx, c0 = (13, 17), ((D, N), (N, N)), 1e-3, 1500.0
+    dt = 0.3 * dx / c0
+    fx, kx = opstd.axis_mode(shape[0], D, N, dx, 3)
+    fy, ky = opstd.axis_mode(shape[1], N, N, dx, 5)
+    p0 = np.outer(fx, fy)
+    th = opstd.mode_phase(c0, dt, kx * kx + ky * ky)
+    prob = opstd.Problem(shape, bcs, dx, dt, c0)
+    p, _ = prob.run(p0, 37)
+    assert np.max(np.abs(p - np.cos(37 * th) * p0)) < 1e-12

@@ -12,6 +12,12 @@ Workloads (physical set-up of the paper's examples, §4.2: water, c0 = 1500 m/s,
                cosine-tapered disc p0 (flat to 4 dx, zero beyond 8 dx), random centre >= 9 dx from walls.
 * ``pstd3d``   3D 384^3, each face Dirichlet or Neumann with probability 1/2, c0 = 1540 m/s, CFL 0.3,
                500 steps, three Gaussian blobs (sigma = 4 dx, amplitude U[0.5, 1]).
+* ``pstd2d_large``  2D 2049 x 2049 (axes above 512 nodes: the FFT path), x faces Dirichlet, y faces
+               Neumann, CFL 0.3, 200 steps, tapered disc p0 at a random centre >= 9 dx from walls.
+* ``pstd3d_mode``  3D 1025^3, faces drawn like ``pstd3d``, CFL 0.3, one pressure basis function per
+               axis (the mode numbers are drawn here; the function itself is the method's basis).
+* ``fft_small``    random 1D/2D/3D shapes whose sides n have 2(n-1) = 16 x 2^a 3^b 5^c, random faces,
+               white-noise p0 (parity sweeps of the FFT path).
 * ``batched``  128 2D instances, sides uniform in {96..512}, c0 U[1400, 1600], one Gaussian blob,
                R uniform in [-1, 1]; each instance is solved twice (all-Neumann and all-Dirichlet).
 * ``nop``      2D 128 x 128 surrogate pairs: 1-3 blobs (sigma U[3, 6] dx) and a smooth c0 map in
@@ -180,6 +186,44 @@ def nop_pairs(count: int, n: int = 128, index_offset: int = 0):
 NOP_BCS = ((DIRICHLET, DIRICHLET), (NEUMANN, NEUMANN))
 NOP_STEPS = 800
 NOP_DT = 0.3 * DX / 1600.0
+
+
+def pstd2d_large(n: int = 2049, steps: int = 200) -> Case:
+    rng = rng_for(5)
+    shape = (n, n)
+    c0 = 1500.0
+    centre = _centre(rng, shape, 9, DX)
+    p0 = tapered_disc(shape, DX, centre, 4 * DX, 8 * DX)
+    bcs = ((DIRICHLET, DIRICHLET), (NEUMANN, NEUMANN))
+    return Case("pstd2d_%dx%d_xDD_yNN" % shape, shape, bcs, DX, 0.3 * DX / c0, c0, steps, p0,
+                extra={"centre": centre})
+
+
+def pstd3d_mode(n: int = 1025, steps: int = 50) -> Case:
+    """Grid, faces and mode numbers; p0 is left to the caller (one basis function per axis)."""
+    rng = rng_for(6)
+    faces = rng.integers(0, 2, size=6)
+    bcs = tuple((int(faces[2 * a]), int(faces[2 * a + 1])) for a in range(3))
+    modes = tuple(int(m) for m in rng.integers(1, n // 8, size=3))
+    c0 = 1540.0
+    return Case("pstd3d_mode_%d^3" % n, (n, n, n), bcs, DX, 0.3 * DX / c0, c0, steps, None,
+                extra={"modes": modes})
+
+
+FFT_SIDES = (9, 17, 25, 33, 41, 49, 65, 81, 97, 121, 129, 161, 193, 241, 257)
+
+
+def fft_small_case(seed: int, ndim: int, precision: str = "fp32", steps: int = 30, sides=FFT_SIDES) -> Case:
+    """Random sides from ``sides`` (2(n-1) = 16 x 2^a 3^b 5^c), random faces, white-noise p0."""
+    rng = np.random.default_rng(SEED_BASE + 2000 + seed)
+    limit = {1: len(sides), 2: len(sides), 3: 9}[ndim]
+    shape = tuple(int(sides[i]) for i in rng.integers(0, limit, size=ndim))
+    faces = rng.integers(0, 2, size=2 * ndim)
+    bcs = tuple((int(faces[2 * a]), int(faces[2 * a + 1])) for a in range(ndim))
+    c0 = float(rng.uniform(1400.0, 1600.0))
+    cfl = 0.25 if ndim > 1 else 0.4
+    p0 = rng.standard_normal(shape)
+    return Case("fft%dd_%d" % (ndim, seed), shape, bcs, DX, cfl * DX / c0, c0, steps, p0, precision=precision)
 
 
 def random_small_case(seed: int, ndim: int, max_n: int = 40, precision: str = "fp32", steps: int = 20) -> Case:
