@@ -201,9 +201,8 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
   x.X = X;
   x.Y = Y;
   x.scale = scale;
-  x.tw = f.tw;
-  x.om = f.om;
-  x.H = f.H[which];
+  x.tab = f.tab;
+  x.kfac = f.kfac[which];
   x.alpha = alpha;
   x.beta = beta;
   x.N = f.N;
@@ -222,8 +221,8 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
   x.contig = a == P->ndim - 1;
   const int64_t lines = x.contig ? outer : outer * inner;
   // transforms per block: enough blocks to fill the chip first (about 1024), then as many lines per
-  // block as LDS holds; at least 64 threads (F L / 16) where LDS allows
-  const int fmax = fft_capacity(P->prec == PSTD_FP64) / f.L;
+  // block as 64 KB of LDS holds; at least 64 threads (F L / 16) where that allows
+  const int fmax = fft_max_per_block(P->prec == PSTD_FP64, f.L);
   int F = static_cast<int>(std::min<int64_t>(fmax, std::max<int64_t>(1, lines / 2048)));
   F = std::max(F, std::min(fmax, std::max(1, 1024 / f.L)));
   F = static_cast<int>(std::min<int64_t>(F, (lines + 1) / 2));

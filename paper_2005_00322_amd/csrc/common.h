@@ -146,18 +146,16 @@ struct FftAxis {
   int npass = 0;
   int radix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int sL = 1, sR = 1;           // +1 Neumann wall, -1 Dirichlet wall
-  void* tw = nullptr;           // L entries e^{-2 pi i t / L}
-  void* om = nullptr;           // L entries e^{-i pi j / L} (mixed walls only)
-  void* H[2] = {nullptr, nullptr};   // spectral multipliers of G (0) and D (1), constants and 1/L folded in
+  void* tab = nullptr;          // 64 + L/16 entries: w^l (l < 64) then w^{64 h}, w = e^{-2 pi i / 4L}
+  double kfac[2] = {0, 0};      // pi c / (N L) with c the velocity (0) or pressure (1) constant
 };
 
 struct FftArgs {
   const void* X;                // input field
   void* Y;                      // output field (read-modify-write)
   const void* scale;            // optional per-point factor with Y's layout, may be null
-  const void* tw;
-  const void* om;
-  const void* H;
+  const void* tab;              // root table (FftAxis::tab)
+  double kfac;                  // FftAxis::kfac of this direction
   double alpha, beta;           // Y = beta Y + alpha scale (op X)
   int N, L;
   int nin, nout;                // extents of X and Y along the axis
@@ -178,6 +176,7 @@ struct FftArgs {
 // needs more than 8 passes.
 bool fft_factor(int L, int* npass, int* radix);
 int fft_capacity(bool dbl);     // complex entries per block (F L at most)
+int fft_max_per_block(bool dbl, int L);   // transforms per block that keep a block within 64 KB of LDS
 bool fft_axis_possible(int n, int prec);
 void fft_axis_free(FftAxis* f);
 hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s);

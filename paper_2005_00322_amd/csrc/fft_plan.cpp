@@ -1,5 +1,5 @@
-// Host tables of the FFT path (kernels_fft.hip): radix plan, twiddles, the mixed-wall pre-twiddle and
-// the spectral multipliers of G and D, all formed in FP64 and rounded once to the state dtype.
+// Host tables of the FFT path (kernels_fft.hip): the radix plan, the two-level table of roots of unity
+// (formed in FP64, rounded once to the state dtype) and the magnitude factors of the spectral multipliers.
 #include <cmath>
 #include <complex>
 
@@ -64,41 +64,24 @@ int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   fft_factor(L, &f.npass, f.radix);
   f.sL = P->bc[2 * a] == PSTD_DIRICHLET ? -1 : 1;
   f.sR = P->bc[2 * a + 1] == PSTD_DIRICHLET ? -1 : 1;
-  const bool anti = f.sL * f.sR < 0;
+  // roots of unity w^t, w = e^{-2 pi i / 4L}: w^l for l < 64, then w^{64 h} for h < 4L / 64
   const double pi = M_PI;
-  std::vector<std::complex<double>> tw(L), om(L), hg(L), hd(L);
-  for (int t = 0; t < L; ++t) tw[t] = std::polar(1.0, -2.0 * pi * t / L);
-  for (int j = 0; j < L; ++j) om[j] = std::polar(1.0, -pi * j / L);
-  const std::complex<double> I(0.0, 1.0);
-  for (int k = 0; k < L; ++k) {
-    double kap;
-    if (anti) kap = pi * ((k < N ? k : k - L) + 0.5) / N;
-    else kap = pi * (k <= N ? k : k - L) / N;
-    if (!anti && k == N) {
-      // Nyquist: the derivative of the cosine interpolant, real
-      hg[k] = -pi * sG / L;
-      hd[k] = pi * sD / L;
-    } else {
-      hg[k] = I * kap * std::polar(1.0, 0.5 * kap) * (sG / L);
-      hd[k] = I * kap * std::polar(1.0, -0.5 * kap) * (sD / L);
-    }
-  }
+  const int L4 = 4 * L;
+  std::vector<std::complex<double>> tab(64 + L4 / 64);
+  for (int l = 0; l < 64; ++l) tab[l] = std::polar(1.0, -2.0 * pi * l / L4);
+  for (int h = 0; h < L4 / 64; ++h) tab[64 + h] = std::polar(1.0, -2.0 * pi * (64.0 * h) / L4);
+  // |H_k| = |kappa_k| c / L with kappa_k = pi m_k / N: the kernel multiplies m_k by pi c / (N L)
+  f.kfac[0] = pi * sG / (static_cast<double>(N) * L);
+  f.kfac[1] = pi * sD / (static_cast<double>(N) * L);
   const bool dbl = P->prec == PSTD_FP64;
-  int st = dbl ? upload_complex<double>(tw, &f.tw) : upload_complex<float>(tw, &f.tw);
-  if (st == PSTD_OK && anti) st = dbl ? upload_complex<double>(om, &f.om) : upload_complex<float>(om, &f.om);
-  if (st == PSTD_OK) st = dbl ? upload_complex<double>(hg, &f.H[0]) : upload_complex<float>(hg, &f.H[0]);
-  if (st == PSTD_OK) st = dbl ? upload_complex<double>(hd, &f.H[1]) : upload_complex<float>(hd, &f.H[1]);
+  const int st = dbl ? upload_complex<double>(tab, &f.tab) : upload_complex<float>(tab, &f.tab);
   if (st != PSTD_OK) return st;
   f.ok = true;
   return PSTD_OK;
 }
 
 void fft_axis_free(FftAxis* f) {
-  if (f->tw) (void)hipFree(f->tw);
-  if (f->om) (void)hipFree(f->om);
-  for (void* h : f->H)
-    if (h) (void)hipFree(h);
+  if (f->tab) (void)hipFree(f->tab);
   *f = FftAxis();
 }
-
 }  // namespace pstd

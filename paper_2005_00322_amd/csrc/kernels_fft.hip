@@ -13,18 +13,25 @@
 //            s = -1/2 (D: half nodes -> nodes).  The Nyquist entry of the periodic case is the real
 //            -+pi: the derivative of the cosine interpolant, the entry the DTT tables keep;
 //   invert   and keep the n - 1 (G) or n (D) samples of the line.
-// H also carries -dt/(rho0 dx) (G) or -dt rho0 c0^2/dx (D), folded in FP64 on the host.
+// H also carries -dt/(rho0 dx) (G) or -dt rho0 c0^2/dx (D).
 //
 // Two real lines share one complex transform (real and imaginary parts); H_{-k} = conj(H_k), so the two
 // results come back separated in the real and imaginary parts.  The inverse reuses the forward transform
 // through conjugation: IFFT(X) L = conj(FFT(conj(X))).
 //
-// A block holds F transforms of length L in LDS (F L <= 16384 complex floats or 8192 complex doubles,
-// 139 KB with one pad entry per 16) and runs mixed-radix Stockham passes in place: each thread reads its
-// butterflies' inputs into registers, the block synchronises, then each thread writes its outputs.  The
-// first forward pass reads through the extension rule; the last forward pass applies H.  Each block has
-// F L / 16 threads, so a radix-R pass gives every thread 16 / R butterflies.  The field goes from HBM to
-// LDS once and the output is read, updated (formed in FP64, rounded once) and written once.
+// Every root of unity the kernel needs (Stockham twiddles, the pre/post-twiddle, the phase of H) is a
+// power of w = e^{-2 pi i / 4L}, taken from a two-level table in LDS: w^t = Th[t / 64] Tl[t % 64] (both
+// rounded once from FP64 on the host; one complex product).  The block reads the field and the table
+// from HBM at the start and the old output values during the last inverse pass, so its only exposed
+// global latency is the first one.
+//
+// A block holds F transforms of length L in LDS (bank-swizzled; 64 KB or less except for single
+// transforms above that) and runs mixed-radix Stockham passes in place: each thread reads its
+// butterflies' inputs into registers, the block synchronises, then each thread writes its outputs.  Three
+// sweeps over LDS apply the extension and pre-twiddle, conj(H X), and the conjugation and post-twiddle.
+// Each block has F L / 16 threads, so a radix-R pass gives every thread 16 / R butterflies.  The field
+// goes from HBM to LDS once and the output is read, updated (formed in FP64, rounded once) and written
+// once.
 #include <type_traits>
 
 #include "common.h"
@@ -135,90 +142,94 @@ __device__ __forceinline__ void dft(V* v) {
   }
 }
 
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+// LDS position of entry j of a transform: bits 4..8 are XORed into bits 0..4, a permutation of every
+// aligned group of 32 entries.  Stride-16 and stride-256 Stockham writes then spread over all banks
+// without padding.  Each transform occupies a slot of Ls = round_up(L, 32) entries.
+__device__ __forceinline__ int sw(int j) { return j ^ ((j >> 4) & 31); }
 
-// Load entry i of a table at a wave-uniform base with a 32-bit offset (one address register per load).
-template <typename V>
-__device__ __forceinline__ V ldt(const void* base, int i) {
-  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + static_cast<uint32_t>(i) * sizeof(V));
+// q = g / d for 0 <= g < 2^24 through a float reciprocal (one correction step).
+__device__ __forceinline__ int fdiv(int g, int d, float inv) {
+  int q = static_cast<int>(static_cast<float>(g) * inv);
+  const int r = g - q * d;
+  q += (r >= d) - (r < 0);
+  return q;
 }
 
-// v[r] *= w^r for r = 1 .. R-1 with w^r = tw[t r]: powers of two are loaded, the others are products of
-// at most three loaded powers (a few ulp), which keeps live registers low.
+// w^t, w = e^{-2 pi i / 4L}, 0 <= t < 4L, from the LDS table: entries 0..63 hold w^l, entries 64.. hold
+// w^{64 h}.
+template <typename V>
+__device__ __forceinline__ V root(const V* tab, int t) {
+  return cmul(tab[64 + (t >> 6)], tab[t & 63]);
+}
+
+// v[r] *= W_L^{t r} = w^{4 t r} for r = 1 .. R-1: powers of two from the table, the others as products of
+// at most three of them.
 template <typename V, int R, int P = 1>
-__device__ __forceinline__ void twiddle(V* v, const void* tw, int t, V* w) {
+__device__ __forceinline__ void twiddle(V* v, const V* tab, int t, V* w) {
   if constexpr (P < R) {
     if constexpr ((P & (P - 1)) == 0) {
-      w[P] = ldt<V>(tw, t * P);
+      w[P] = root(tab, 4 * t * P);
     } else {
       constexpr int hb = 1 << (31 - __builtin_clz(P));
       w[P] = cmul(w[hb], w[P - hb]);
     }
     v[P] = cmul(v[P], w[P]);
-    twiddle<V, R, P + 1>(v, tw, t, w);
+    twiddle<V, R, P + 1>(v, tab, t, w);
   }
 }
 
-// Value j (0 <= j < L) of the extended, pre-twiddled input sequence of transform f.  The raw samples of
-// the line pair sit at entries 0 .. nin-1 of the transform's LDS slot.
-template <typename T>
-__device__ __forceinline__ typename Cx<T>::type ext_read(const FftArgs& a, const typename Cx<T>::type* z, int f,
-                                                         int j) {
-  typedef typename Cx<T>::type V;
+// Entry j (0 <= j < L) of the extended input sequence is sgn * raw[src] (before the pre-twiddle); the
+// raw samples of a line pair sit at entries 0 .. nin-1 of the transform's slot.  Selects only.
+__device__ __forceinline__ void ext_source(const FftArgs& a, int j, int& src, float& sgn) {
   const int N = a.N;
-  int src = j;
-  T sgn = 1;
   if (a.dir == 0) {
-    if (j > N) {
-      src = 2 * N - j;
-      sgn = static_cast<T>(a.sR);
-    }
+    const bool mirror = j > N;
+    src = mirror ? 2 * N - j : j;
+    sgn = mirror ? static_cast<float>(a.sR) : 1.0f;
     // a Dirichlet wall node is not an unknown: it enters as 0
-    if ((src == 0 && a.sL < 0) || (src == N && a.sR < 0)) sgn = 0;
-  } else if (j >= N) {
-    src = 2 * N - 1 - j;
-    sgn = static_cast<T>(-a.sR);
+    sgn = ((src == 0 && a.sL < 0) || (src == N && a.sR < 0)) ? 0.0f : sgn;
+  } else {
+    const bool mirror = j >= N;
+    src = mirror ? 2 * N - 1 - j : j;
+    sgn = mirror ? static_cast<float>(-a.sR) : 1.0f;
   }
-  const V x = z[pad(f * a.L + src)];
-  V r = sgn == 0 ? V{0, 0} : sgn * x;
-  if (a.anti) r = cmul(r, ldt<V>(a.om, j));
-  return r;
 }
 
-// One in-place Stockham pass of radix R over the F transforms of the block.  first: read through the
-// extension rule (first forward pass); last: store conj(H_k X_k) (last forward pass).
+// Each thread owns transform f of the block and the 16 entries lt + u L/16 (u < 16) of its slot; a
+// radix-R pass gives it the butterflies lt + b L/16, b < ceil(16/R) (guarded only when R does not
+// divide 16).
+struct Lane {
+  int f;       // transform of the block
+  int lt;      // 0 .. L/16 - 1
+  int q;       // L / 16
+  int base;    // f * Ls
+};
+
+// One in-place Stockham pass of radix R: reads of every butterfly input, a block barrier, then writes.
 template <typename T, int R>
-__device__ __forceinline__ void stockham_pass(const FftArgs& a, typename Cx<T>::type* z, int Ns, bool first,
-                                              bool last) {
+__device__ __forceinline__ void stockham_pass(const FftArgs& a, typename Cx<T>::type* z,
+                                              const typename Cx<T>::type* tab, const Lane& ln, int Ns) {
   typedef typename Cx<T>::type V;
   constexpr int NB = (16 + R - 1) / R;
+  constexpr bool EXACT = 16 % R == 0;
   const int L = a.L;
   const int per = L / R;
-  const int total = a.F * per;
-  const int nt = blockDim.x;
+  const float inv_ns = 1.0f / static_cast<float>(Ns);
+  const int tstep = L / (Ns * R);
+  // an opaque copy of the slot index keeps the compiler from hoisting this pass's index arithmetic out
+  // of the pass loop, where it would stay live through every other pass
+  int lt = ln.lt;
+  asm volatile("" : "+v"(lt));
   V v[NB][R];
-  int fo[NB], jo[NB];
-  // An opaque copy of the thread index: keeps the compiler from hoisting this pass's index arithmetic out
-  // of the pass loop, where it would stay live (in registers or spilled) through every other pass.
-  int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int g = tid + b * nt;
-    fo[b] = -1;
-    if (g < total) {
-      const int f = g / per;
-      const int j = g - f * per;
-      fo[b] = f;
-      jo[b] = j;
+    const int j = lt + b * ln.q;
+    if (EXACT || j < per) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (first) v[b][r] = ext_read<T>(a, z, f, j + r * per);
-        else v[b][r] = z[pad(f * L + j + r * per)];
-      }
+      for (int r = 0; r < R; ++r) v[b][r] = z[ln.base + sw(j + r * per)];
       if (Ns > 1) {
         V w[R];
-        twiddle<V, R>(v[b], a.tw, (j % Ns) * (L / (Ns * R)), w);
+        twiddle<V, R>(v[b], tab, (j - fdiv(j, Ns, inv_ns) * Ns) * tstep, w);
       }
       dft<V, R>(v[b]);
     }
@@ -226,41 +237,112 @@ __device__ __forceinline__ void stockham_pass(const FftArgs& a, typename Cx<T>::
   lds_barrier();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    if (fo[b] >= 0) {
-      const int j = jo[b];
-      const int k0 = (j / Ns) * Ns * R + (j % Ns);
+    const int j = lt + b * ln.q;
+    if (EXACT || j < per) {
+      const int jq = fdiv(j, Ns, inv_ns);
+      const int k0 = jq * Ns * R + (j - jq * Ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k = k0 + r * Ns;
-        V x = v[b][r];
-        if (last) x = conj(cmul(ldt<V>(a.H, k), x));
-        z[pad(fo[b] * L + k)] = x;
-      }
+      for (int r = 0; r < R; ++r) z[ln.base + sw(k0 + r * Ns)] = v[b][r];
     }
   }
   lds_barrier();
 }
 
 template <typename T>
-__device__ __forceinline__ void run_pass(const FftArgs& a, typename Cx<T>::type* z, int R, int Ns, bool first,
-                                         bool last) {
+__device__ __forceinline__ void run_pass(const FftArgs& a, typename Cx<T>::type* z, const typename Cx<T>::type* tab,
+                                         const Lane& ln, int R, int Ns) {
   switch (R) {
-    case 16: stockham_pass<T, 16>(a, z, Ns, first, last); break;
-    case 8: stockham_pass<T, 8>(a, z, Ns, first, last); break;
-    case 4: stockham_pass<T, 4>(a, z, Ns, first, last); break;
-    case 2: stockham_pass<T, 2>(a, z, Ns, first, last); break;
-    case 3: stockham_pass<T, 3>(a, z, Ns, first, last); break;
-    default: stockham_pass<T, 5>(a, z, Ns, first, last); break;
+    case 16: stockham_pass<T, 16>(a, z, tab, ln, Ns); break;
+    case 8: stockham_pass<T, 8>(a, z, tab, ln, Ns); break;
+    case 4: stockham_pass<T, 4>(a, z, tab, ln, Ns); break;
+    case 2: stockham_pass<T, 2>(a, z, tab, ln, Ns); break;
+    case 3: stockham_pass<T, 3>(a, z, tab, ln, Ns); break;
+    default: stockham_pass<T, 5>(a, z, tab, ln, Ns); break;
   }
 }
+
+// In-place sweep over the thread's 16 entries j = lt + u L/16: every thread reads E of them (with their
+// table values) before any thread writes.  With E = 16 one batch covers the block, so g may read any
+// entry of the slot.
+template <int E, typename V, typename Fn>
+__device__ __forceinline__ void sweep(V* z, const Lane& ln, Fn g) {
+  int lt = ln.lt;
+  asm volatile("" : "+v"(lt));
+#pragma unroll
+  for (int u0 = 0; u0 < 16; u0 += E) {
+    V v[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = g.read(z, ln.base, lt + (u0 + u) * ln.q);
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < E; ++u) z[ln.base + sw(lt + (u0 + u) * ln.q)] = v[u];
+    lds_barrier();
+  }
+}
+
+// Extension of the raw samples to the full period, times the pre-twiddle e^{-i pi j / L} = w^{2j} for
+// mixed walls.
+template <typename V>
+struct ExtendOp {
+  const FftArgs& a;
+  const V* tab;
+  __device__ V read(const V* z, int base, int j) const {
+    int src;
+    float sgn;
+    ext_source(a, j, src, sgn);
+    V x = z[base + sw(src)];
+    x = V{x.x * sgn, x.y * sgn};
+    if (a.anti) x = cmul(x, root(tab, 2 * j));
+    return x;
+  }
+};
+
+// conj(H_k X_k).  H_k = i kappa_k (c/L) e^{i s kappa_k / 2} with kappa_k = pi m_k / N, m_k = k (+1/2 for
+// mixed walls) folded to the signed frequency; the phase is w^{-2 s m_k} and kfac = pi c / (N L).
+template <typename V>
+struct MultiplyOp {
+  const FftArgs& a;
+  const V* tab;
+  __device__ V read(const V* z, int base, int k) const {
+    typedef elem_t<V> T;
+    const int L = a.L;
+    const bool neg = a.anti ? k >= a.N : k > a.N;
+    const int m2 = 2 * k + a.anti - (neg ? 2 * L : 0);   // 2 m_k
+    const int L4 = 4 * L;
+    int t = a.dir == 0 ? -m2 : m2;                        // w^{-2 s m_k}: s = +1 for G, -1 for D
+    t += t < 0 ? L4 : 0;
+    const V ph = root(tab, t);
+    const T mag = static_cast<T>(0.5) * static_cast<T>(m2) * static_cast<T>(a.kfac);
+    const V h = V{-mag * ph.y, mag * ph.x};                 // i mag ph
+    return conj(cmul(h, z[base + sw(k)]));
+  }
+};
+
+// Result of the inverse: conjugate back, times the post-twiddle e^{i pi j / L} = w^{4L - 2j} for mixed
+// walls.
+template <typename V>
+struct FinishOp {
+  const FftArgs& a;
+  const V* tab;
+  __device__ V read(const V* z, int base, int j) const {
+    const V x = conj(z[base + sw(j)]);
+    if (!a.anti) return x;
+    return cmul(x, root(tab, j == 0 ? 0 : 4 * a.L - 2 * j));
+  }
+};
+
+constexpr size_t kSmallLds = 65536;
 
 template <typename T>
 constexpr int max_threads() {
   return sizeof(T) == 4 ? 1024 : 512;
 }
 
-template <typename T>
-__global__ __launch_bounds__(max_threads<T>()) void fft_axis_kernel(FftArgs a) {
+// BIG: one transform above 64 KB (L > 8192 floats, > 4096 doubles).  Such launches opt in to the larger
+// LDS through a function attribute of their own instance; every other launch stays within the 64 KB a
+// block may take without it, so the attribute never inflates their per-block allocation.
+template <typename T, bool BIG>
+__global__ __launch_bounds__(max_threads<T>(), sizeof(T) == 4 ? 5 : 2) void fft_axis_kernel(FftArgs a) {
   typedef typename Cx<T>::type V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   V* z = reinterpret_cast<V*>(smem);
@@ -272,125 +354,186 @@ __global__ __launch_bounds__(max_threads<T>()) void fft_axis_kernel(FftArgs a) {
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   const int L = a.L;
+  const int Ls = (L + 31) & ~31;
   int64_t b = 0, l0;
-  int nl;
   if (a.contig) {
     l0 = grp * W;
-    nl = static_cast<int>(min<int64_t>(W, a.ncols - l0));
   } else {
     b = grp / a.gpb;
     l0 = (grp - b * a.gpb) * W;
-    nl = static_cast<int>(min<int64_t>(W, a.ncols - l0));
   }
+  const int nl = static_cast<int>(min<int64_t>(W, a.ncols - l0));
   const T* X = static_cast<const T*>(a.X) + b * a.x_bstride;
   T* Y = static_cast<T*>(a.Y) + b * a.y_bstride;
   const T* S = a.scale ? static_cast<const T*>(a.scale) + b * a.y_bstride : nullptr;
+  const int nin = a.nin, nout = a.nout;
+  const float inv_nin = 1.0f / static_cast<float>(nin), inv_nout = 1.0f / static_cast<float>(nout);
+  Lane ln;
+  ln.q = L / 16;
+  ln.f = fdiv(tid, ln.q, 1.0f / static_cast<float>(ln.q));
+  ln.lt = tid - ln.f * ln.q;
+  ln.base = ln.f * Ls;
+  V* tab = z + a.F * Ls;
+  const int ntab = 64 + L / 16;
+  const V* gtab = static_cast<const V*>(a.tab);
 
-  // ---- load: line c of the group -> part (c & 1) of transform c / 2, entries 0 .. nin-1
+  // element e of the group's input (output) lines: line c, position k along the axis; offsets stay below
+  // 2^31 elements (plans hold at most 2^31 points)
+  auto in_pos = [&](int e, int& c, int& k) {
+    if (a.contig) {
+      c = fdiv(e, nin, inv_nin);
+      k = e - c * nin;
+    } else {
+      c = e % W;
+      k = e / W;
+    }
+  };
+  auto out_pos = [&](int e, int& c, int& m) {
+    if (a.contig) {
+      c = fdiv(e, nout, inv_nout);
+      m = e - c * nout;
+    } else {
+      c = e % W;
+      m = e / W;
+    }
+  };
+  auto in_off = [&](int c, int k) -> uint32_t {
+    return a.contig ? static_cast<uint32_t>((l0 + c) * nin + k) : static_cast<uint32_t>(k * a.ncols + l0 + c);
+  };
+  auto out_off = [&](int c, int m) -> uint32_t {
+    return a.contig ? static_cast<uint32_t>((l0 + c) * nout + m) : static_cast<uint32_t>(m * a.ncols + l0 + c);
+  };
+
+  // Every thread takes up to EB input elements of the group per batch (2F lines of at most N + 1 values
+  // over F L / 16 threads: at most 16 + 16/N, so 17 covers every N >= 16; longer is looped) and EO
+  // output elements per batch.
+  constexpr int EB = 17, EO = 8;
+  const int cnt_in = W * nin, cnt_out = W * nout;
+  const bool read_y = a.beta != 0.0;
+
+  // ---- load: line c of the group -> part (c & 1) of transform c / 2, entries 0 .. nin-1; the root table
   {
-    const int nin = a.nin;
-    const int cnt = W * nin;
     T* zs = reinterpret_cast<T*>(z);
-    for (int e0 = 0; e0 < cnt; e0 += 8 * nt) {
-      T v[8];
-      int c[8], k[8];
+    for (int e0 = 0; e0 < cnt_in; e0 += EB * nt) {
+      T v[EB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < EB; ++u) {
         const int e = e0 + tid + u * nt;
-        if (a.contig) {
-          c[u] = e / nin;
-          k[u] = e - c[u] * nin;
-        } else {
-          c[u] = e % W;
-          k[u] = e / W;
-        }
-        const bool ok = e < cnt && c[u] < nl;
-        const int64_t off = a.contig ? (l0 + c[u]) * nin + k[u] : static_cast<int64_t>(k[u]) * a.ncols + l0 + c[u];
-        v[u] = ok ? X[off] : T(0);
+        int c, k;
+        in_pos(e, c, k);
+        v[u] = (e < cnt_in && c < nl) ? X[in_off(c, k)] : T(0);
       }
+      if (e0 == 0)
+        for (int i = tid; i < ntab; i += nt) tab[i] = gtab[i];
+      int tid3 = threadIdx.x;   // positions recomputed, not kept live across the loads
+      asm volatile("" : "+v"(tid3));
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + tid + u * nt;
-        if (e < cnt) zs[2 * pad((c[u] >> 1) * L + k[u]) + (c[u] & 1)] = v[u];
+      for (int u = 0; u < EB; ++u) {
+        const int e = e0 + tid3 + u * nt;
+        int c, k;
+        in_pos(e, c, k);
+        if (e < cnt_in) zs[2 * ((c >> 1) * Ls + sw(k)) + (c & 1)] = v[u];
       }
     }
   }
   lds_barrier();
 
-  // ---- forward transform with the extension on input and H on output, then the inverse
-  // passes 0 .. npass-1: forward transform; npass .. 2 npass-1: the inverse (forward of the conjugate)
+  // ---- extend, forward transform, multiply by H, inverse (the forward transform of the conjugate)
+  sweep<16>(z, ln, ExtendOp<V>{a, tab});   // reads other entries of the slot: one batch
   int Ns = 1;
-  for (int q = 0; q < 2 * a.npass; ++q) {
-    const int p = q < a.npass ? q : q - a.npass;
-    if (p == 0) Ns = 1;
-    const int R = a.radix[p];
-    run_pass<T>(a, z, R, Ns, q == 0, q == a.npass - 1);
-    Ns *= R;
+  for (int p = 0; p < a.npass; ++p) {
+    run_pass<T>(a, z, tab, ln, a.radix[p], Ns);
+    Ns *= a.radix[p];
   }
+  sweep<8>(z, ln, MultiplyOp<V>{a, tab});
+  Ns = 1;
+  for (int p = 0; p + 1 < a.npass; ++p) {
+    run_pass<T>(a, z, tab, ln, a.radix[p], Ns);
+    Ns *= a.radix[p];
+  }
+  // the old output values of the first batch are read while the last pass runs; output positions are
+  // recomputed from an opaque thread index rather than kept live through the transforms
+  int tid2 = threadIdx.x;
+  asm volatile("" : "+v"(tid2));
+  T yv[EO];
+#pragma unroll
+  for (int u = 0; u < EO; ++u) {
+    const int e = tid2 + u * nt;
+    int c, m;
+    out_pos(e, c, m);
+    yv[u] = (read_y && e < cnt_out && c < nl) ? Y[out_off(c, m)] : T(0);
+  }
+  run_pass<T>(a, z, tab, ln, a.radix[a.npass - 1], Ns);
+  sweep<8>(z, ln, FinishOp<V>{a, tab});
 
   // ---- epilogue: Y = beta Y + alpha scale out, formed in FP64
-  {
-    const int nout = a.nout;
-    const int cnt = W * nout;
-    for (int e0 = 0; e0 < cnt; e0 += 4 * nt) {
-      T yv[4], sv[4], ov[4];
-      int64_t off[4];
-      bool ok[4];
+  for (int e0 = 0; e0 < cnt_out; e0 += EO * nt) {
+    T sv[EO];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + tid + u * nt;
-        int c, m;
-        if (a.contig) {
-          c = e / nout;
-          m = e - c * nout;
-        } else {
-          c = e % W;
-          m = e / W;
-        }
-        ok[u] = e < cnt && c < nl;
-        off[u] = a.contig ? (l0 + c) * nout + m : static_cast<int64_t>(m) * a.ncols + l0 + c;
-        yv[u] = ok[u] && a.beta != 0.0 ? Y[off[u]] : T(0);
-        sv[u] = ok[u] && S ? S[off[u]] : T(1);
-        ov[u] = 0;
-        if (e < cnt) {
-          V w = conj(z[pad((c >> 1) * L + m)]);
-          if (a.anti) w = cmul(w, conj(ldt<V>(a.om, m)));
-          ov[u] = (c & 1) ? w.y : w.x;
-          // pressure at a Dirichlet wall node stays 0
-          if (a.dir == 1 && ((m == 0 && a.sL < 0) || (m == a.N && a.sR < 0))) ov[u] = 0;
-        }
+    for (int u = 0; u < EO; ++u) {
+      const int e = e0 + tid2 + u * nt;
+      int c, m;
+      out_pos(e, c, m);
+      const bool ok = e < cnt_out && c < nl;
+      sv[u] = (S && ok) ? S[out_off(c, m)] : T(1);
+      if (e0 != 0) yv[u] = (read_y && ok) ? Y[out_off(c, m)] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < EO; ++u) {
+      const int e = e0 + tid2 + u * nt;
+      int c, m;
+      out_pos(e, c, m);
+      if (e < cnt_out && c < nl) {
+        const V w = z[(c >> 1) * Ls + sw(m)];
+        T ov = (c & 1) ? w.y : w.x;
+        // pressure at a Dirichlet wall node stays 0
+        if (a.dir == 1 && ((m == 0 && a.sL < 0) || (m == a.N && a.sR < 0))) ov = 0;
+        Y[out_off(c, m)] = static_cast<T>(a.beta * static_cast<double>(yv[u]) +
+                                          a.alpha * static_cast<double>(sv[u]) * static_cast<double>(ov));
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (ok[u])
-          Y[off[u]] = static_cast<T>(a.beta * static_cast<double>(yv[u]) +
-                                     a.alpha * static_cast<double>(sv[u]) * static_cast<double>(ov[u]));
     }
   }
 }
 
+// LDS bytes of a launch: F slots of round_up(L, 32) entries and the root table.
+template <typename T>
+size_t lds_bytes(const FftArgs& a) {
+  return static_cast<size_t>(a.F * round_up(a.L, 32) + 64 + a.L / 16) * 2 * sizeof(T);
+}
+
 template <typename T>
 hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
+  const int threads = a.F * a.L / 16;
+  const size_t shm = lds_bytes<T>(a);
+  int64_t blocks = a.groups;
+  if (a.xcd_spread) blocks = round_up(blocks, 8);
+  if (shm <= kSmallLds) {
+    hipLaunchKernelGGL((fft_axis_kernel<T, false>), dim3(static_cast<unsigned>(blocks)), dim3(threads), shm, s, a);
+    return hipGetLastError();
+  }
   static bool configured = false;
-  const int cap = fft_capacity(sizeof(T) == 8);
-  const size_t lds = static_cast<size_t>(cap + cap / 16) * 2 * sizeof(T);
   if (!configured) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fft_axis_kernel<T>),
+    const int cap = fft_capacity(sizeof(T) == 8);
+    const size_t lds = static_cast<size_t>(cap + 64 + cap / 16) * 2 * sizeof(T);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fft_axis_kernel<T, true>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     configured = true;
   }
-  const int threads = a.F * a.L / 16;
-  const size_t shm = static_cast<size_t>(a.F * a.L + (a.F * a.L) / 16) * 2 * sizeof(T);
-  int64_t blocks = a.groups;
-  if (a.xcd_spread) blocks = round_up(blocks, 8);
-  hipLaunchKernelGGL(fft_axis_kernel<T>, dim3(static_cast<unsigned>(blocks)), dim3(threads), shm, s, a);
+  hipLaunchKernelGGL((fft_axis_kernel<T, true>), dim3(static_cast<unsigned>(blocks)), dim3(threads), shm, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
 int fft_capacity(bool dbl) { return dbl ? 8192 : 16384; }
+
+int fft_max_per_block(bool dbl, int L) {
+  const int64_t esz = dbl ? 16 : 8;
+  const int64_t room = static_cast<int64_t>(kSmallLds) / esz - 64 - L / 16;   // entries left for the slots
+  const int64_t f = room / round_up(L, 32);
+  return f < 1 ? 1 : static_cast<int>(f);
+}
 
 hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s) {
   return dbl ? launch_typed<double>(a, s) : launch_typed<float>(a, s);
