@@ -176,6 +176,13 @@ typedef struct pstd_batch_s* pstd_batch;
 int pstd_batch_create(int32_t count, const int64_t* n, const int32_t* bc, const double* dx, const double* dt,
                       const double* c0, double rho0, void* hip_stream, pstd_batch* out);
 
+/* Heterogeneous media (an extension beyond the paper's homogeneous box): c0_maps holds count device
+ * pointers, each null or an nx x ny float map of c0(x) for that solve; the pressure updates of those
+ * solves then use c0(x)^2 pointwise (density stays rho0).  The stability check of pstd_batch_create
+ * used the c0 passed there, so pass each map's maximum as c0.  The maps are squared into buffers the
+ * batch owns; the caller's maps may be freed after the call's work completes.  Asynchronous. */
+int pstd_batch_set_c0_maps(pstd_batch batch, const float* const* c0_maps);
+
 /* Prepare caller-filled states (count of them, FP32 p and u[0], u[1]) as pstd_state_init does. */
 int pstd_batch_state_init(pstd_batch batch, pstd_state* states, int32_t u_mode);
 
@@ -198,6 +205,54 @@ int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order);
 int pstd_batch_autotune(pstd_batch batch, int32_t trial_steps, const char* cache_path, int32_t* config_out);
 
 int pstd_batch_destroy(pstd_batch batch);
+
+/* ---- DCT-basis neural-operator surrogate -------------------------------------------------------------
+ * Not a method of the paper: a learned map from (p0, c0 map) on an H x W grid to the pressure after a
+ * fixed number of PSTD steps, trained on fields the solver produces; the solver remains its fallback and
+ * the judge of its error.  Network (all parameters FP32, contractions on bf16 matrix cores with FP32
+ * accumulation):
+ *   features f = [p0, (c0 - 1500)/100, x, y] with x = i/(H-1), y = j/(W-1)
+ *   lift     v = P f + pb                                   P: C x 4
+ *   layer l  v = GELU(W_l v + b_l + IDCT(R_l . DCT(v)))      W_l: C x C; R_l: (Mm/2) x (Mm/2) x C x C
+ *   project  q = GELU(Q1 v + q1b),  out = Q2 q + q2b         Q1: Hp x C; Q2: Hp
+ * DCT: orthonormal DCT-II along both axes keeping the Mm lowest modes; IDCT: its transpose; R_l mixes
+ * channels per mode, one matrix per 2 x 2 block of modes.  GELU uses the exact erf.  The flat
+ * parameter vector is P, pb, then per layer (R_l, W_l, b_l), then Q1, q1b, Q2, q2b, each row-major.
+ * Loss: batch mean of |out - target|^2 / |target|^2. */
+typedef struct {
+  int32_t H, W;        /* grid */
+  int32_t channels;    /* C */
+  int32_t modes;       /* Mm, even, <= H and <= W */
+  int32_t layers;      /* 1 .. 16 */
+  int32_t hidden;      /* Hp */
+  int32_t max_batch;   /* buffers are sized for this batch */
+  int32_t split;       /* 1: each product as hi*hi + hi*lo + lo*hi bf16 parts (near FP32), 0: one bf16 product */
+} pstd_nop_config;
+
+typedef struct pstd_nop_s* pstd_nop;
+
+/* Create a surrogate with zero parameters on hip_stream (NULL = null stream).  Allocates every buffer
+ * for cfg->max_batch (about (7 + 3 layers) x batch x C x H x W floats plus 4 x batch x Hp x H x W). */
+int pstd_nop_create(const pstd_nop_config* cfg, void* hip_stream, pstd_nop* out);
+/* Length of the flat parameter vector (-1 for a null handle). */
+int64_t pstd_nop_param_count(pstd_nop nop);
+/* Copy host FP32 parameters in (and reset the Adam moments and step count) / out.  n must equal the
+ * parameter count.  Synchronous. */
+int pstd_nop_set_params(pstd_nop nop, const float* host, int64_t n);
+int pstd_nop_get_params(pstd_nop nop, float* host, int64_t n);
+/* Copy the gradient of the last pstd_nop_backward to the host.  Synchronous. */
+int pstd_nop_get_grads(pstd_nop nop, float* host, int64_t n);
+/* out[b] = network(p0[b], c0[b]) for b < batch (device arrays of batch x H x W floats, row-major) and keep
+ * the activations for a following pstd_nop_backward.  Asynchronous on the surrogate's stream. */
+int pstd_nop_forward(pstd_nop nop, const float* p0, const float* c0, float* out, int32_t batch);
+/* Gradient of the loss of the last forward against target (device, batch x H x W) into the surrogate's
+ * gradient buffer; *loss (nullable) receives the loss (synchronises when given). */
+int pstd_nop_backward(pstd_nop nop, const float* target, double* loss);
+/* One Adam step (Kingma & Ba, with bias correction) on the parameters with the current gradient. */
+int pstd_nop_adam_step(pstd_nop nop, double lr, double beta1, double beta2, double eps);
+/* err[b] = |pred[b] - target[b]| / |target[b]| for b < batch (device fields, host err).  Synchronous. */
+int pstd_nop_relative_errors(pstd_nop nop, const float* pred, const float* target, int32_t batch, double* err);
+int pstd_nop_destroy(pstd_nop nop);
 
 const char* pstd_status_string(int status);
 const char* pstd_last_error(void);

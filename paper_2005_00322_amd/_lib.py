@@ -32,6 +32,11 @@ class State(C.Structure):
     _fields_ = [("p", C.c_void_p), ("u", C.c_void_p * 3), ("step", C.c_int64)]
 
 
+class NopConfig(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("channels", C.c_int32), ("modes", C.c_int32),
+                ("layers", C.c_int32), ("hidden", C.c_int32), ("max_batch", C.c_int32), ("split", C.c_int32)]
+
+
 class PstdError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__("%s: %s (%d): %s" % (where, _STATUS.get(status, "?"), status, detail))
@@ -71,7 +76,18 @@ SIGNATURES = {
                                        C.POINTER(C.c_void_p), C.c_int32]),
     "pstd_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pstd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]),
+    "pstd_batch_set_c0_maps": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "pstd_batch_destroy": (C.c_int, [C.c_void_p]),
+    "pstd_nop_create": (C.c_int, [C.POINTER(NopConfig), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pstd_nop_param_count": (C.c_int64, [C.c_void_p]),
+    "pstd_nop_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "pstd_nop_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "pstd_nop_get_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "pstd_nop_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "pstd_nop_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "pstd_nop_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "pstd_nop_relative_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "pstd_nop_destroy": (C.c_int, [C.c_void_p]),
     "pstd_status_string": (C.c_char_p, [C.c_int]),
     "pstd_last_error": (C.c_char_p, []),
 }

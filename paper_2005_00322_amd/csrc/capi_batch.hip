@@ -16,6 +16,7 @@ struct pstd_batch_s {
   std::vector<int> nx, ny;
   std::vector<int> bc;                        // count x 4
   std::vector<double> dx, dt, c0;
+  std::vector<void*> c2maps;                  // owned c0^2 maps (null for homogeneous solves)
   // shared unscaled FP32 operators, one per (n, case): G ((n-1) x n) and D (n x (n-1))
   struct Op {
     pstd::DevOperator G, D;
@@ -53,6 +54,8 @@ int upload_unscaled(const std::vector<double>& m, int M, int K, DevOperator* op)
 
 void free_batch(pstd_batch_s* B) {
   if (!B) return;
+  for (void* p : B->c2maps)
+    if (p) (void)hipFree(p);
   for (auto& kv : B->ops) {
     if (kv.second.G.data) (void)hipFree(kv.second.G.data);
     if (kv.second.D.data) (void)hipFree(kv.second.D.data);
@@ -273,6 +276,22 @@ int pstd_batch_create(int32_t count, const int64_t* n, const int32_t* bc, const 
     return fail(PSTD_E_OOM, "hipMalloc of the phase counters failed");
   }
   *out = B;
+  return PSTD_OK;
+}
+
+int pstd_batch_set_c0_maps(pstd_batch B, const float* const* c0_maps) {
+  if (!B || !c0_maps) return fail(PSTD_E_INVALID_ARG, "null batch or map array");
+  B->c2maps.resize(B->count, nullptr);
+  for (int s = 0; s < B->count; ++s) {
+    if (!c0_maps[s]) continue;
+    const int64_t np = static_cast<int64_t>(B->nx[s]) * B->ny[s];
+    if (!B->c2maps[s] && hipMalloc(&B->c2maps[s], np * sizeof(float)) != hipSuccess)
+      return fail(PSTD_E_OOM, "hipMalloc of a c0^2 map failed");
+    PSTD_HIP(launch_square(PSTD_FP32, c0_maps[s], B->c2maps[s], np, B->stream));
+    B->solves[s].c2 = static_cast<const float*>(B->c2maps[s]);
+    B->solves[s].sD = -B->dt[s] * B->rho0 / B->dx[s];
+  }
+  B->key.clear();   // the device solve table is rebuilt with the maps on the next step
   return PSTD_OK;
 }
 

@@ -116,7 +116,8 @@ struct BatchSolve {
   int ldgx, lddx, ldgy, lddy;                                          // their row strides
   int nx, ny;
   double sG;                // -dt / (rho0 dx)
-  double sD;                // -dt rho0 c0^2 / dx
+  double sD;                // -dt rho0 c0^2 / dx, or -dt rho0 / dx with a c0^2 map
+  const float* c2;          // nx x ny map of c0(x)^2, or null for a homogeneous medium
 };
 struct BatchTask {
   int solve;
@@ -180,6 +181,37 @@ int fft_max_per_block(bool dbl, int L);   // transforms per block that keep a bl
 bool fft_axis_possible(int n, int prec);
 void fft_axis_free(FftAxis* f);
 hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s);
+
+// ---- neural-operator surrogate (kernels_nop.hip, capi_nop.hip) ----------------------------------------
+// C[z] = alpha A[z] B[z] (+ beta C[z]) (+ bias_m[m]) (+ D[z]) (* GELU'(dgelu[z])), then with act set
+// pre[z] = value (if pre is given) and C[z] = GELU(value).  A is M x K, B is K x N, C is M x N, all FP32
+// with element strides; the batch index z = z1 nb2 + z2 adds z1 b*1 + z2 b*2 to each operand.  pre and
+// dgelu use C's strides.
+struct NopGemm {
+  const float* A; const float* B; float* C;
+  int M, N, K;
+  int64_t sAm, sAk, sBk, sBn, sCm, sCn;
+  int nb1, nb2;
+  int64_t bA1, bA2, bB1, bB2, bC1, bC2;
+  float alpha, beta;
+  const float* bias_m;
+  const float* add;
+  int64_t sDm, sDn, bD1, bD2;
+  float* pre;
+  const float* dgelu;
+  int act;              // apply GELU
+  int split;            // 1: hi*hi + hi*lo + lo*hi bf16 products (near FP32); 0: one bf16 product
+};
+hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s);
+hipError_t launch_nop_mode_transpose(const float* in, float* out, int B, int C, int Mm, bool to_block, hipStream_t s);
+hipError_t launch_nop_features(const float* p0, const float* c0, float* f, int B, int H, int W, hipStream_t s);
+hipError_t launch_nop_gelu_bwd(const float* gin, const float* pre, float* d, int64_t n, hipStream_t s);
+hipError_t launch_nop_rowsum(const float* x, float* out, int nb, int rows, int64_t P, hipStream_t s);
+hipError_t launch_nop_partial_sum(const float* part, float* out, int nz, int n, hipStream_t s);
+hipError_t launch_nop_loss(const float* out, const float* tgt, double* terms, float* dout, int B, int64_t P,
+                           hipStream_t s);
+hipError_t launch_nop_adam(float* th, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t s);
 
 }  // namespace pstd
 

@@ -165,17 +165,22 @@ __device__ void run_task(const BatchSolve& S, const BatchTask& T, float* lds) {
     Y = S.p; rows = nx; cols = ny; scale = S.sD;
   }
   const int j = T.j0 + tile_col();
-  float yv[4];
+  // pressure tiles of a heterogeneous solve take c0(x)^2 pointwise
+  const float* c2 = T.kind == 2 ? S.c2 : nullptr;
+  float yv[4], cv[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = T.i0 + tile_row(r);
-    yv[r] = (i < rows && j < cols) ? Y[static_cast<int64_t>(i) * cols + j] : 0.f;
+    const bool ok = i < rows && j < cols;
+    yv[r] = ok ? Y[static_cast<int64_t>(i) * cols + j] : 0.f;
+    cv[r] = (ok && c2) ? c2[static_cast<int64_t>(i) * cols + j] : 1.f;
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = T.i0 + tile_row(r);
     if (i < rows && j < cols)
-      Y[static_cast<int64_t>(i) * cols + j] = static_cast<float>(static_cast<double>(yv[r]) + scale * accd[r]);
+      Y[static_cast<int64_t>(i) * cols + j] =
+          static_cast<float>(static_cast<double>(yv[r]) + scale * static_cast<double>(cv[r]) * accd[r]);
   }
 }
 

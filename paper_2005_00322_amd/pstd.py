@@ -296,6 +296,25 @@ class Batch:
         check(load().pstd_batch_combine_R(self._h, self._c_states(states), pr, rr, op, npairs), "pstd_batch_combine_R")
         return outs
 
+    def set_c0_maps(self, maps):
+        """Per-solve sound-speed maps (float32 device tensors of the solve's shape, or None): the pressure
+        update of those solves uses c0(x)^2 pointwise.  The solve's c0 given at creation must be the
+        map's maximum (it sets the stability check)."""
+        torch = _torch()
+        keep = []
+        ptrs = (C.c_void_p * self.count)()
+        for i, (s, m) in enumerate(zip(self.solves, maps)):
+            if m is None:
+                continue
+            t = torch.as_tensor(m).to(device=self.device, dtype=torch.float32).contiguous()
+            if tuple(t.shape) != tuple(s["shape"]):
+                raise ValueError("c0 map %d has shape %s, solve is %s" % (i, tuple(t.shape), s["shape"]))
+            keep.append(t)
+            ptrs[i] = t.data_ptr()
+        check(load().pstd_batch_set_c0_maps(self._h, ptrs), "pstd_batch_set_c0_maps")
+        self._stream.synchronize()   # the maps are squared into the batch's own buffers
+        del keep
+
     def set_config(self, blocks=0, order=0):
         check(load().pstd_batch_set_config(self._h, int(blocks), int(order)), "pstd_batch_set_config")
 

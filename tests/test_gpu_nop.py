@@ -1,0 +1,128 @@
+"""GPU parity of the neural-operator surrogate against its FP64 reference (oracle.nop).
+
+Forward output and every parameter gradient are compared on a small configuration.  With split bf16
+products (hi*hi + hi*lo + lo*hi) the kernels are close to FP32 and must match to 1e-4 relative; with
+plain bf16 products (the training setting) to 3e-2.  The Adam kernel is compared with the reference
+update applied to the GPU's own gradient.  The batched solver's sound-speed maps (used to generate the
+training targets) are compared with the oracle's heterogeneous stepping.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import rel_l2
+from oracle import nop as onop
+from oracle import pstd as opstd
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(H=16, W=12, channels=4, modes=6, layers=2, hidden=8)
+
+
+def _setup(split, B=3, seed=0):
+    import torch
+    from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig, param_shapes
+
+    scfg = SurrogateConfig(**SMALL)
+    ocfg = onop.Config(H=scfg.H, W=scfg.W, C=scfg.channels, Mm=scfg.modes, layers=scfg.layers, Hp=scfg.hidden)
+    net = Surrogate(scfg, max_batch=4, split=split)
+    assert net.n_params == onop.param_count(ocfg)
+    theta = workloads.nop_init(param_shapes(scfg), seed=seed, gain=1.5).astype(np.float32)
+    rng = np.random.default_rng(10 + seed)
+    p0 = rng.standard_normal((B, scfg.H, scfg.W)).astype(np.float32)
+    c0 = (1400.0 + 200.0 * rng.random((B, scfg.H, scfg.W))).astype(np.float32)
+    tgt = rng.standard_normal((B, scfg.H, scfg.W)).astype(np.float32)
+    net.set_params(theta)
+    return torch, net, ocfg, theta, p0, c0, tgt
+
+
+@pytest.mark.parametrize("split,tol", [(True, 1e-4), (False, 3e-2)])
+def test_forward_and_gradients_match_reference(split, tol):
+    torch, net, ocfg, theta, p0, c0, tgt = _setup(split)
+    print("surrogate parity split", split, flush=True)
+    out = net.forward(p0, c0)
+    loss = net.backward(tgt)
+    torch.cuda.synchronize()
+    g = net.get_grads().astype(np.float64)
+    th = theta.astype(np.float64)
+    ref_out = onop.forward(ocfg, th, p0.astype(np.float64), c0.astype(np.float64))
+    ref_loss, ref_g = onop.backward(ocfg, th, p0.astype(np.float64), c0.astype(np.float64), tgt.astype(np.float64))
+    assert rel_l2(out.double().cpu().numpy(), ref_out) < tol
+    assert abs(loss - ref_loss) < tol * ref_loss
+    o = 0
+    for name, shp in onop.param_shapes(ocfg):
+        n = int(np.prod(shp))
+        e = rel_l2(g[o:o + n], ref_g[o:o + n])
+        assert e < (tol if split else 5 * tol), (name, e)
+        o += n
+    net.close()
+
+
+def test_adam_step_matches_reference():
+    torch, net, ocfg, theta, p0, c0, tgt = _setup(True, seed=1)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, 4):
+        net.forward(p0, c0)
+        net.backward(tgt)
+        g = net.get_grads().astype(np.float64)
+        net.adam_step(1e-3)
+        th, m, v = onop.adam_step(th, g, m, v, t, 1e-3)
+        got = net.get_params().astype(np.float64)
+        assert np.max(np.abs(got - th)) < 1e-6
+        th = got          # continue from the device's parameters (float32 rounding)
+    net.close()
+
+
+def test_batch_sound_speed_maps_match_oracle():
+    import torch
+    from paper_2005_00322_amd import Batch
+
+    rng = np.random.default_rng(3)
+    shapes = [(40, 36), (33, 47)]
+    bcs = [((1, 1), (0, 0)), ((0, 1), (1, 0))]
+    dx = 1e-4
+    solves, p0s, maps = [], [], []
+    for shp, bc in zip(shapes, bcs):
+        cm = workloads.smooth_c0_map(rng, shp, corr_nodes=6.0)
+        dt = 0.25 * dx / cm.max()
+        solves.append({"shape": shp, "bcs": bc, "dx": dx, "dt": dt, "c0": float(cm.max())})
+        p0s.append(workloads.gaussian(shp, dx, (shp[0] * dx / 2, shp[1] * dx / 2.5), 4 * dx))
+        maps.append(cm)
+    b = Batch(solves)
+    b.set_c0_maps([torch.from_numpy(m.astype(np.float32)) for m in maps])
+    st = b.new_states(p0s)
+    b.init_states(st)
+    b.step(st, 120)
+    torch.cuda.synchronize()
+    for i, (s, m) in enumerate(zip(solves, maps)):
+        prob = opstd.Problem(s["shape"], s["bcs"], dx, s["dt"], s["c0"],
+                             c0_map=m.astype(np.float32).astype(np.float64))
+        ref, _ = prob.run(p0s[i], 120)
+        assert rel_l2(st[i].p.double().cpu().numpy(), ref) < 1e-5
+    b.close()
+
+
+def test_training_reduces_loss_on_solver_targets():
+    import torch
+    from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig, param_shapes, solver_targets
+
+    n = 32
+    p0s, c0s = workloads.nop_inputs(48, n=n)
+    dt = 0.3 * workloads.DX / 1600.0
+    tgt = solver_targets(p0s, c0s, workloads.DX, dt, 40, workloads.NOP_BCS)
+    scfg = SurrogateConfig(H=n, W=n, channels=8, modes=8, layers=2, hidden=16)
+    net = Surrogate(scfg, max_batch=16)
+    net.set_params(workloads.nop_init(param_shapes(scfg), seed=2))
+    p = torch.from_numpy(p0s.astype(np.float32)).cuda()
+    c = torch.from_numpy(c0s.astype(np.float32)).cuda()
+    losses = []
+    for it in range(150):
+        i0 = (it * 16) % 48
+        net.forward(p[i0:i0 + 16], c[i0:i0 + 16])
+        losses.append(net.backward(tgt[i0:i0 + 16]))
+        net.adam_step(3e-3)
+    print("loss first/last", losses[0], np.mean(losses[-10:]), flush=True)
+    assert np.mean(losses[-10:]) < 0.5 * losses[0]
+    net.close()

@@ -176,11 +176,35 @@ def nop_pairs(count: int, n: int = 128, index_offset: int = 0):
         p0 = np.zeros((n, n))
         for _ in range(nb):
             sig = float(rng.uniform(3.0, 6.0)) * DX
-            centre = _centre(rng, (n, n), 20, DX)
+            centre = _centre(rng, (n, n), min(20, n // 4), DX)
             p0 += gaussian((n, n), DX, centre, sig, float(rng.uniform(0.5, 1.0)))
         c0m = smooth_c0_map(rng, (n, n))
         out.append((p0, c0m))
     return out
+
+
+def nop_init(shapes, seed: int = 0, gain: float = 1.0) -> np.ndarray:
+    """Initial surrogate parameters: for each (name, shape, fan_in), N(0, gain^2 / fan_in) entries for
+    weight arrays and zeros for biases (fan_in 0); mixing matrices R* and W* get an extra 1/sqrt(2) since
+    their two paths are summed.  Returns the flat float64 vector."""
+    rng = np.random.default_rng(SEED_BASE + 4000 + seed)
+    parts = []
+    for name, shape, fan_in in shapes:
+        n = int(np.prod(shape))
+        if fan_in == 0:
+            parts.append(np.zeros(n))
+            continue
+        g = gain / np.sqrt(fan_in)
+        if name[0] in "RW":
+            g /= np.sqrt(2.0)
+        parts.append(g * rng.standard_normal(n))
+    return np.concatenate(parts)
+
+
+def nop_inputs(count: int, n: int = 128, index_offset: int = 0):
+    """Arrays (p0s, c0s) of shape (count, n, n) for surrogate pairs, as nop_pairs draws them."""
+    pairs = nop_pairs(count, n, index_offset)
+    return np.stack([p for p, _ in pairs]), np.stack([c for _, c in pairs])
 
 
 NOP_BCS = ((DIRICHLET, DIRICHLET), (NEUMANN, NEUMANN))
