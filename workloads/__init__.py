@@ -64,7 +64,8 @@ class Case:
 def rng_for(index: int, stream: int = 0) -> np.random.Generator:
     if stream == 0:
         return np.random.default_rng(SEED_BASE + index)
-    return np.random.default_rng(np.random.SeedSequence(SEED_BASE + index).spawn(stream + 1)[stream])
+    # child `stream` of SeedSequence(SEED_BASE + index), built directly (same stream as .spawn()[stream])
+    return np.random.default_rng(np.random.SeedSequence(SEED_BASE + index, spawn_key=(stream,)))
 
 
 def gaussian(shape, dx, centre, sigma, amp=1.0) -> np.ndarray:
