@@ -252,6 +252,11 @@ int pstd_nop_backward(pstd_nop nop, const float* target, double* loss);
 int pstd_nop_adam_step(pstd_nop nop, double lr, double beta1, double beta2, double eps);
 /* err[b] = |pred[b] - target[b]| / |target[b]| for b < batch (device fields, host err).  Synchronous. */
 int pstd_nop_relative_errors(pstd_nop nop, const float* pred, const float* target, int32_t batch, double* err);
+/* Input statistics for the surrogate's gate, per sample b < batch (device p0, c0; host stats, batch x 4):
+ * min c0, max c0, max |p0| and the share of sum p0^2 on nodes within `margin` of a wall.  A caller
+ * compares them with the training distribution and sends samples outside it (or every sample, when the
+ * surrogate's validated error exceeds the tolerance) to the PSTD solver instead.  Synchronous. */
+int pstd_nop_input_stats(pstd_nop nop, const float* p0, const float* c0, int32_t batch, int32_t margin, double* stats);
 int pstd_nop_destroy(pstd_nop nop);
 
 const char* pstd_status_string(int status);

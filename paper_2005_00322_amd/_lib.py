@@ -87,6 +87,7 @@ SIGNATURES = {
     "pstd_nop_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pstd_nop_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]),
     "pstd_nop_relative_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "pstd_nop_input_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "pstd_nop_destroy": (C.c_int, [C.c_void_p]),
     "pstd_status_string": (C.c_char_p, [C.c_int]),
     "pstd_last_error": (C.c_char_p, []),

@@ -443,6 +443,27 @@ int pstd_nop_relative_errors(pstd_nop N, const float* pred, const float* target,
   return PSTD_OK;
 }
 
+int pstd_nop_input_stats(pstd_nop N, const float* p0, const float* c0, int32_t batch, int32_t margin, double* stats) {
+  if (!N || !p0 || !c0 || !stats) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  if (batch < 1 || batch > N->cfg.max_batch) return fail(PSTD_E_INVALID_ARG, "bad batch");
+  if (margin < 0) return fail(PSTD_E_INVALID_ARG, "margin < 0");
+  if (static_cast<int64_t>(4) * batch > 2LL * N->cfg.max_batch) {
+    // terms holds 2 max_batch doubles; stats of larger batches go through a temporary buffer
+    double* tmp = nullptr;
+    if (hipMalloc(&tmp, 4 * sizeof(double) * batch) != hipSuccess) return fail(PSTD_E_OOM, "hipMalloc failed");
+    hipError_t e = launch_nop_input_stats(p0, c0, tmp, batch, N->cfg.H, N->cfg.W, margin, N->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(stats, tmp, 4 * sizeof(double) * batch, hipMemcpyDeviceToHost, N->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(PSTD_E_HIP, "input statistics failed: %s", hipGetErrorString(e));
+    return PSTD_OK;
+  }
+  NOP_RUN(launch_nop_input_stats(p0, c0, N->terms, batch, N->cfg.H, N->cfg.W, margin, N->stream));
+  PSTD_HIP(hipMemcpyAsync(stats, N->terms, 4 * sizeof(double) * batch, hipMemcpyDeviceToHost, N->stream));
+  PSTD_HIP(hipStreamSynchronize(N->stream));
+  return PSTD_OK;
+}
+
 int pstd_nop_destroy(pstd_nop N) {
   if (!N) return PSTD_OK;
   (void)(N->stream ? hipStreamSynchronize(N->stream) : hipDeviceSynchronize());

@@ -210,6 +210,8 @@ hipError_t launch_nop_rowsum(const float* x, float* out, int nb, int rows, int64
 hipError_t launch_nop_partial_sum(const float* part, float* out, int nz, int n, hipStream_t s);
 hipError_t launch_nop_loss(const float* out, const float* tgt, double* terms, float* dout, int B, int64_t P,
                            hipStream_t s);
+hipError_t launch_nop_input_stats(const float* p0, const float* c0, double* stats, int B, int H, int W, int margin,
+                                  hipStream_t s);
 hipError_t launch_nop_adam(float* th, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                            float eps, float c1, float c2, hipStream_t s);
 

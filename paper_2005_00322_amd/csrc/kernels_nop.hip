@@ -257,6 +257,48 @@ __global__ void nop_adam_kernel(float* th, const float* g, float* m, float* v, i
   th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Per-sample input statistics for the surrogate's gate: c0 min, c0 max, max |p0|, and the share of
+// sum p0^2 within `margin` nodes of a wall.  One block per sample; double sums.
+__global__ void nop_input_stats_kernel(const float* p0, const float* c0, double* stats, int H, int W, int margin) {
+  const int b = blockIdx.x;
+  const int64_t P = static_cast<int64_t>(H) * W;
+  const float* p = p0 + b * P;
+  const float* c = c0 + b * P;
+  double cmin = 1e300, cmax = -1e300, pmax = 0.0, e_all = 0.0, e_wall = 0.0;
+  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
+    const int h = static_cast<int>(i / W), w = static_cast<int>(i % W);
+    const double cv = c[i], pv = p[i];
+    cmin = fmin(cmin, cv);
+    cmax = fmax(cmax, cv);
+    pmax = fmax(pmax, fabs(pv));
+    e_all += pv * pv;
+    if (h < margin || h >= H - margin || w < margin || w >= W - margin) e_wall += pv * pv;
+  }
+  __shared__ double r[5][256];
+  r[0][threadIdx.x] = cmin;
+  r[1][threadIdx.x] = cmax;
+  r[2][threadIdx.x] = pmax;
+  r[3][threadIdx.x] = e_all;
+  r[4][threadIdx.x] = e_wall;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) {
+      r[0][threadIdx.x] = fmin(r[0][threadIdx.x], r[0][threadIdx.x + w]);
+      r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + w]);
+      r[2][threadIdx.x] = fmax(r[2][threadIdx.x], r[2][threadIdx.x + w]);
+      r[3][threadIdx.x] += r[3][threadIdx.x + w];
+      r[4][threadIdx.x] += r[4][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[4 * b] = r[0][0];
+    stats[4 * b + 1] = r[1][0];
+    stats[4 * b + 2] = r[2][0];
+    stats[4 * b + 3] = r[3][0] > 0 ? r[4][0] / r[3][0] : 0.0;
+  }
+}
+
 unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
 
 }  // namespace
@@ -302,6 +344,12 @@ hipError_t launch_nop_loss(const float* out, const float* tgt, double* terms, fl
   if (dout)
     hipLaunchKernelGGL(nop_loss_grad_kernel, dim3(blocks_for(static_cast<int64_t>(B) * P, 256)), dim3(256), 0, s, out,
                        tgt, terms, dout, B, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_nop_input_stats(const float* p0, const float* c0, double* stats, int B, int H, int W, int margin,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(nop_input_stats_kernel, dim3(B), dim3(256), 0, s, p0, c0, stats, H, W, margin);
   return hipGetLastError();
 }
 

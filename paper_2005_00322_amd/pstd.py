@@ -257,7 +257,8 @@ class Batch:
         out = []
         for s, p0 in zip(self.solves, p0s):
             nx, ny = s["shape"]
-            p = torch.as_tensor(np.asarray(p0)).to(device=self.device, dtype=torch.float32).contiguous().clone()
+            p = p0 if isinstance(p0, torch.Tensor) else torch.as_tensor(np.asarray(p0))
+            p = p.to(device=self.device, dtype=torch.float32).contiguous().clone()
             if tuple(p.shape) != (nx, ny):
                 raise ValueError("p0 shape mismatch")
             ux = torch.zeros((nx - 1, ny), device=self.device, dtype=torch.float32)

@@ -152,3 +152,52 @@ def solver_targets(p0s, c0s, dx, dt, steps, bcs, batch=256):
         finally:
             b.close()
     return out
+
+
+def input_stats(net: Surrogate, p0, c0, margin: int = 10) -> np.ndarray:
+    """(batch, 4): min c0, max c0, max |p0|, share of sum p0^2 within `margin` nodes of a wall."""
+    p, cm = net._dev(p0), net._dev(c0)
+    B = int(p.shape[0])
+    out = np.empty((B, 4), np.float64)
+    check(load().pstd_nop_input_stats(net._h, p.data_ptr(), cm.data_ptr(), B, int(margin),
+                                      out.ctypes.data_as(C.c_void_p)), "pstd_nop_input_stats")
+    return out
+
+
+@dataclass(frozen=True)
+class Gate:
+    """When the surrogate may answer instead of the solver.
+
+    validated_error: the surrogate's relative L2 error against the solver on held-out pairs (a high
+    quantile); a request whose tolerance is below it always goes to the solver.  The remaining fields
+    bound the training distribution: c0 range, peak |p0|, and the share of p0's energy near the walls
+    (training sources sit at least 20 nodes inside).
+    """
+    validated_error: float
+    c0_lo: float = 1400.0
+    c0_hi: float = 1600.0
+    p_max: float = 3.0
+    wall_margin: int = 10
+    wall_share_max: float = 1e-3
+
+
+def predict(net: Surrogate, p0, c0, tol: float, gate: Gate, dx, dt, steps, bcs):
+    """Surrogate answer where the gate admits it, the FP32 PSTD solver's answer elsewhere.
+
+    Returns (out, fallback) with fallback a boolean array marking the samples the solver produced."""
+    torch = _torch()
+    p, cm = net._dev(p0), net._dev(c0)
+    B = int(p.shape[0])
+    st = input_stats(net, p, cm, gate.wall_margin)
+    inside = ((st[:, 0] >= gate.c0_lo) & (st[:, 1] <= gate.c0_hi) & (st[:, 2] <= gate.p_max)
+              & (st[:, 3] <= gate.wall_share_max))
+    fallback = ~inside | (gate.validated_error > tol)
+    out = torch.empty_like(p)
+    for s0 in range(0, B, net.max_batch):
+        s1 = min(B, s0 + net.max_batch)
+        net.forward(p[s0:s1], cm[s0:s1], out=out[s0:s1])
+    idx = np.nonzero(fallback)[0]
+    if idx.size:
+        ti = torch.from_numpy(idx).to(p.device)
+        out[ti] = solver_targets(p[ti], cm[ti], dx, dt, steps, bcs)
+    return out, fallback

@@ -126,3 +126,31 @@ def test_training_reduces_loss_on_solver_targets():
     print("loss first/last", losses[0], np.mean(losses[-10:]), flush=True)
     assert np.mean(losses[-10:]) < 0.5 * losses[0]
     net.close()
+
+
+def test_gate_and_solver_fallback():
+    import torch
+    from paper_2005_00322_amd.surrogate import Gate, Surrogate, SurrogateConfig, param_shapes, predict, solver_targets
+
+    n = 32
+    p0s, c0s = workloads.nop_inputs(4, n=n)
+    # sample 2: sound speed outside the training range; sample 3: source at a wall
+    c0s[2] += 300.0
+    p0s[3] = workloads.gaussian((n, n), workloads.DX, (1 * workloads.DX, 16 * workloads.DX), 3 * workloads.DX)
+    dt = 0.3 * workloads.DX / 1900.0
+    scfg = SurrogateConfig(H=n, W=n, channels=4, modes=8, layers=1, hidden=8)
+    net = Surrogate(scfg, max_batch=4)
+    net.set_params(workloads.nop_init(param_shapes(scfg), seed=3))
+    gate = Gate(validated_error=0.4, wall_margin=4, wall_share_max=0.2)
+    p = torch.from_numpy(p0s.astype(np.float32)).cuda()
+    c = torch.from_numpy(c0s.astype(np.float32)).cuda()
+    ref = solver_targets(p, c, workloads.DX, dt, 30, workloads.NOP_BCS)
+    net_out = net.forward(p, c).clone()
+    out, fb = predict(net, p, c, 0.5, gate, workloads.DX, dt, 30, workloads.NOP_BCS)
+    assert fb.tolist() == [False, False, True, True]
+    assert torch.equal(out[:2], net_out[:2])
+    assert torch.equal(out[2:], ref[2:])
+    # a tolerance below the validated error sends everything to the solver
+    out, fb = predict(net, p, c, 0.1, gate, workloads.DX, dt, 30, workloads.NOP_BCS)
+    assert fb.all() and torch.equal(out, ref)
+    net.close()
