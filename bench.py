@@ -1,6 +1,6 @@
 """Benchmark of the PSTD time-step hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d|batched|pstd2d_large]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d|batched|pstd2d_large|nop]
 
 One bench step is one PSTD time step over the whole grid: every axis's velocity update (forward DTT,
 k-space multiply with the type switch, inverse DTT, leapfrog update; one fused contraction kernel per
@@ -40,6 +40,7 @@ WORKLOADS = {
     "pstd1d": ("pstd1d", "fp64", 1000, 100),
     "batched": ("batched", "fp32", 1000, 10),
     "pstd2d_large": ("pstd2d_large", "fp32", 200, 20),
+    "nop": ("nop", "bf16", 20, 3),
 }
 
 
@@ -314,6 +315,109 @@ def batched_cpu_leg(wl, solves, p0s, finals, combined, pairs, R, total_steps, bu
     return cpu, worst
 
 
+def nop_forward_flops(H, W, C, Mm, layers, Hp):
+    """Multiply-add flops (x2) of one surrogate forward pass per sample (the GEMMs of the network)."""
+    P = H * W
+    per_layer = 2 * C * (Mm * H * W + Mm * Mm * W)        # DCT along H, then along W
+    per_layer += 2 * Mm * Mm * C * C                     # per-mode channel mixing
+    per_layer += 2 * C * (Mm * Mm * W + Mm * H * W)      # inverse along W, then along H
+    per_layer += 2 * C * C * P                           # pointwise channel mixing
+    return layers * per_layer + 2 * P * (4 * C + C * Hp + Hp)
+
+
+def run_nop(args, K, W):
+    """Surrogate inference (batch 256) against the batched FP32 solver on the same 256 held-out inputs."""
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import Batch
+    from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig
+
+    wpath = args.weights or os.path.join(ROOT, "paper_2005_00322_amd", "weights", "nop_128x128_c32_m48_l4.npz")
+    cfg = SurrogateConfig()
+    B = 256
+    p0s, c0s = workloads.nop_inputs(B, n=cfg.H, index_offset=2 * 10 ** 6)
+    dev = torch.device("cuda")
+    p = torch.from_numpy(p0s.astype(np.float32)).to(dev)
+    c = torch.from_numpy(c0s.astype(np.float32)).to(dev)
+    # the solver: 256 solves x 800 steps in one batched launch sequence (timed region: the steps only)
+    cmax = c.amax(dim=(1, 2)).double().cpu().numpy()
+    solves = [{"shape": (cfg.H, cfg.W), "bcs": workloads.NOP_BCS, "dx": workloads.DX, "dt": workloads.NOP_DT,
+               "c0": float(cmax[i])} for i in range(B)]
+    b = Batch(solves)
+    b.set_c0_maps([c[i] for i in range(B)])
+    b.autotune(trial_steps=5, cache_path=os.path.join("/tmp", "pstd_batch_tune_nop.json"))
+    st = b.new_states([p[i] for i in range(B)])
+    b.init_states(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(st, workloads.NOP_STEPS)
+    torch.cuda.synchronize()
+    t_pstd = time.perf_counter() - t0
+    ref = torch.stack([s.p for s in st])
+    b.close()
+    # the surrogate
+    net = Surrogate(cfg, max_batch=B)
+    d = np.load(wpath)
+    net.set_params(d["theta"])
+    out = torch.empty_like(p)
+    for _ in range(W):
+        net.forward(p, c, out=out)
+    torch.cuda.synchronize()
+    stream = net._stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(K):
+        net.forward(p, c, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_nop = (time.perf_counter() - t0) / K
+    ev_ms = e0.elapsed_time(e1) / K
+    err = net.relative_errors(out, ref)
+    net.close()
+    pts = cfg.H * cfg.W
+    flops = nop_forward_flops(cfg.H, cfg.W, cfg.channels, cfg.modes, cfg.layers, cfg.hidden) * B
+    tfs = flops / (ev_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import nop as onop
+        ocfg = onop.Config()
+        theta = d["theta"].astype(np.float64)
+        t0 = time.perf_counter()
+        ns = 0
+        while ns < 2:
+            onop.forward(ocfg, theta, p0s[ns:ns + 1], c0s[ns:ns + 1])
+            ns += 1
+        tcpu = time.perf_counter() - t0
+        threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
+        cpu = {"value": ns * pts * workloads.NOP_STEPS / tcpu, "unit": "equivalent grid-point updates/s",
+               "cores": int(threads), "kind": "oracle",
+               "sample": "FP64 NumPy surrogate forward of %d of the 256 samples (einsum contractions)" % ns}
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle; surrogate speedup",
+        "value": B * pts * workloads.NOP_STEPS / t_nop, "unit": "equivalent grid-point updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": t_nop * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": "nop_128x128_batch256_t800", "grid": [cfg.H, cfg.W], "channels": cfg.channels,
+                   "modes": cfg.modes, "layers": cfg.layers, "hidden": cfg.hidden, "batch": B,
+                   "solver_steps": workloads.NOP_STEPS, "weights": os.path.basename(wpath),
+                   "trained_pairs": int(d["train"]), "trained_epochs": int(d["epochs"]), "parallelism": "single-gpu"},
+        "accuracy": {"rel_l2_vs_fp32_pstd": {"mean": float(err.mean()), "median": float(np.median(err)),
+                                             "p95": float(np.quantile(err, 0.95))},
+                     "note": "the FP32 batched solver is the judge; it matches the FP64 oracle to 2e-6"},
+        "surrogate_speedup": {"vs_batched_fp32_pstd": t_pstd / t_nop, "pstd_s": t_pstd, "surrogate_s": t_nop,
+                              "sample": "the same 256 inputs, %d steps each" % workloads.NOP_STEPS},
+        "roofline": {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK["bf16_TFs"], "unit": "TFLOP/s",
+                     "frac": round(tfs / PEAK["bf16_TFs"], 5), "traffic": None, "kernel": "whole forward (nop_gemm)",
+                     "avg_ms": round(ev_ms, 4), "algorithmic_flops": int(flops)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +425,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="pstd2d", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=None, help="surrogate parameters (npz with 'theta') for --workload nop")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known HBM traffic, for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -341,6 +446,10 @@ def main():
     if args.workload == "batched":
         torch.cuda.set_device(0)
         run_batched(args, K, W)
+        return
+    if args.workload == "nop":
+        torch.cuda.set_device(0)
+        run_nop(args, K, W)
         return
     case = getattr(workloads, builder)()
     torch.cuda.set_device(0)
