@@ -167,8 +167,9 @@ int pstd_plan_destroy(pstd_plan plan);
  * the 2D scheme of §4.3; the paired Neumann/Dirichlet solves of one physical instance are two entries
  * combined afterwards with pstd_batch_combine_R.  Operators are built in FP64 once per distinct
  * (n, boundary pair) and shared.  pstd_batch_step runs all requested steps of all solves in one
- * cooperative kernel launch: per step a velocity phase over every solve's velocity tiles, a grid-wide
- * barrier, a pressure phase over every pressure tile, a second barrier. */
+ * persistent kernel launch of at most as many blocks as the GPU holds: per step a velocity phase over
+ * every solve's velocity tiles, a grid-wide barrier, a pressure phase over every pressure tile, a second
+ * barrier. */
 typedef struct pstd_batch_s* pstd_batch;
 
 /* n: count x 2 (nx, ny) nodes per solve, each >= 3 and <= 512; bc: count x 4 faces {x-, x+, y-, y+};
@@ -186,7 +187,8 @@ int pstd_batch_set_c0_maps(pstd_batch batch, const float* const* c0_maps);
 /* Prepare caller-filled states (count of them, FP32 p and u[0], u[1]) as pstd_state_init does. */
 int pstd_batch_state_init(pstd_batch batch, pstd_state* states, int32_t u_mode);
 
-/* Advance every solve by n_steps (one persistent launch per 1024 steps).  Asynchronous. */
+/* Advance every solve by n_steps: per 1024 steps one persistent launch (with the kernel that zeroes its
+ * tile tickets and barrier counters) replayed from a captured HIP graph.  Asynchronous. */
 int pstd_batch_step(pstd_batch batch, pstd_state* states, int64_t n_steps);
 
 /* out[i] = (1+R[i])/2 p_neumann + (1-R[i])/2 p_dirichlet for npairs pairs; pairs = npairs x 2 solve
@@ -203,6 +205,11 @@ int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order);
  * JSON file keyed by a signature of the batch; a later call with a matching file skips the timing.
  * config_out (nullable, 3 ints): blocks, order, 1 if taken from the cache.  Synchronous. */
 int pstd_batch_autotune(pstd_batch batch, int32_t trial_steps, const char* cache_path, int32_t* config_out);
+
+/* Wait for the batch's stream and report whether every grid barrier of the launches since the last
+ * call completed: PSTD_E_HIP if one gave up waiting (its blocks were not all resident, e.g. because other
+ * work held the GPU), in which case the states are not valid. */
+int pstd_batch_synchronize(pstd_batch batch);
 
 int pstd_batch_destroy(pstd_batch batch);
 

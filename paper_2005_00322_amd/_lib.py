@@ -77,6 +77,7 @@ SIGNATURES = {
     "pstd_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pstd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]),
     "pstd_batch_set_c0_maps": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pstd_batch_synchronize": (C.c_int, [C.c_void_p]),
     "pstd_batch_destroy": (C.c_int, [C.c_void_p]),
     "pstd_nop_create": (C.c_int, [C.POINTER(NopConfig), C.c_void_p, C.POINTER(C.c_void_p)]),
     "pstd_nop_param_count": (C.c_int64, [C.c_void_p]),

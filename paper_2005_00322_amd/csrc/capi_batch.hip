@@ -28,16 +28,18 @@ struct pstd_batch_s {
   std::vector<pstd::BatchTask> tasksA, tasksB;
   pstd::BatchTask* d_tasks = nullptr;         // A then B
   int order_built = -1;
-  unsigned* d_counters = nullptr;
+  unsigned* d_counters = nullptr;             // 4 per step of a launch, then the barrier timeout flag
   int blocks = 0;                             // 0 = occupancy maximum
   int order = 0;
+  hipStream_t capture = nullptr;              // private stream the launch graphs are captured on
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;   // (steps, blocks) -> instantiated graph
 };
 
 namespace pstd {
 namespace {
 
 constexpr int kTile = 32;
-constexpr int64_t kChunk = 1024;   // steps per persistent launch (2 counters each)
+constexpr int64_t kChunk = 1024;   // steps per persistent launch (4 counters each)
 
 int upload_unscaled(const std::vector<double>& m, int M, int K, DevOperator* op) {
   op->M = M;
@@ -63,6 +65,8 @@ void free_batch(pstd_batch_s* B) {
   if (B->d_solves) (void)hipFree(B->d_solves);
   if (B->d_tasks) (void)hipFree(B->d_tasks);
   if (B->d_counters) (void)hipFree(B->d_counters);
+  for (auto& kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (B->capture) (void)hipStreamDestroy(B->capture);
   delete B;
 }
 
@@ -132,10 +136,17 @@ int resident_blocks(const pstd_batch_s* B, int* out) {
   return PSTD_OK;
 }
 
-int launch_steps(pstd_batch_s* B, int64_t n_steps, hipStream_t s) {
-  int blocks = 0;
-  int st = resident_blocks(B, &blocks);
-  if (st != PSTD_OK) return st;
+// The instantiated graph (counter fill + persistent launch) for `steps` steps on `blocks` blocks.  The
+// device tables it reads (solves, tasks, counters) keep their addresses for the batch's lifetime; their
+// contents are refreshed in place.
+int graph_for(pstd_batch_s* B, int64_t steps, int blocks, hipGraphExec_t* out) {
+  const auto key = std::make_pair(steps, blocks);
+  auto it = B->graphs.find(key);
+  if (it != B->graphs.end()) {
+    *out = it->second;
+    return PSTD_OK;
+  }
+  if (!B->capture) PSTD_HIP(hipStreamCreateWithFlags(&B->capture, hipStreamNonBlocking));
   BatchArgs a;
   a.solves = B->d_solves;
   a.tasksA = B->d_tasks;
@@ -143,9 +154,31 @@ int launch_steps(pstd_batch_s* B, int64_t n_steps, hipStream_t s) {
   a.tasksB = B->d_tasks + B->tasksA.size();
   a.nB = static_cast<int>(B->tasksB.size());
   a.counters = B->d_counters;
+  a.timeout = B->d_counters + 4 * kChunk;
+  a.steps = steps;
+  hipGraph_t g = nullptr;
+  PSTD_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
+  const hipError_t le = launch_batch2d(a, blocks, B->capture);
+  hipError_t e = hipStreamEndCapture(B->capture, &g);
+  if (le != hipSuccess) e = le;
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(PSTD_E_HIP, "capture of the persistent launch failed: %s", hipGetErrorString(e));
+  B->graphs[key] = ex;
+  *out = ex;
+  return PSTD_OK;
+}
+
+int launch_steps(pstd_batch_s* B, int64_t n_steps, hipStream_t s) {
+  int blocks = 0;
+  int st = resident_blocks(B, &blocks);
+  if (st != PSTD_OK) return st;
   for (int64_t left = n_steps; left > 0; left -= kChunk) {
-    a.steps = std::min(left, kChunk);
-    PSTD_HIP(launch_batch2d(a, blocks, s));
+    hipGraphExec_t ex = nullptr;
+    st = graph_for(B, std::min(left, kChunk), blocks, &ex);
+    if (st != PSTD_OK) return st;
+    PSTD_HIP(hipGraphLaunch(ex, s));
   }
   return PSTD_OK;
 }
@@ -271,9 +304,13 @@ int pstd_batch_create(int32_t count, const int64_t* n, const int32_t* bc, const 
     S.sD = -B->dt[s] * rho0 * B->c0[s] * B->c0[s] / B->dx[s];
     B->solves.push_back(S);
   }
-  if (hipMalloc(&B->d_counters, sizeof(unsigned) * 2 * kChunk) != hipSuccess) {
+  if (hipMalloc(&B->d_counters, sizeof(unsigned) * (4 * kChunk + 1)) != hipSuccess) {
     free_batch(B);
     return fail(PSTD_E_OOM, "hipMalloc of the phase counters failed");
+  }
+  if (hipMemset(B->d_counters, 0, sizeof(unsigned) * (4 * kChunk + 1)) != hipSuccess) {
+    free_batch(B);
+    return fail(PSTD_E_HIP, "hipMemset of the phase counters failed");
   }
   *out = B;
   return PSTD_OK;
@@ -292,6 +329,19 @@ int pstd_batch_set_c0_maps(pstd_batch B, const float* const* c0_maps) {
     B->solves[s].sD = -B->dt[s] * B->rho0 / B->dx[s];
   }
   B->key.clear();   // the device solve table is rebuilt with the maps on the next step
+  return PSTD_OK;
+}
+
+int pstd_batch_synchronize(pstd_batch B) {
+  if (!B) return fail(PSTD_E_INVALID_ARG, "null batch");
+  PSTD_HIP(B->stream ? hipStreamSynchronize(B->stream) : hipDeviceSynchronize());
+  unsigned flag = 0;
+  PSTD_HIP(hipMemcpy(&flag, B->d_counters + 4 * kChunk, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (flag) {
+    PSTD_HIP(hipMemset(B->d_counters + 4 * kChunk, 0, sizeof(unsigned)));
+    return fail(PSTD_E_HIP, "a grid barrier of the persistent launch timed out (blocks not all resident); "
+                            "the state is not valid");
+  }
   return PSTD_OK;
 }
 
@@ -445,7 +495,7 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
         B->order = order;
         st = ensure_solves(B, scratch.data());
         if (st == PSTD_OK) st = ensure_tasks(B);
-        if (st == PSTD_OK) st = launch_steps(B, 1, B->stream);   // warm
+        if (st == PSTD_OK) st = launch_steps(B, trial_steps, B->stream);   // warm (and capture the graph)
         if (st != PSTD_OK) break;
         if (hipEventRecord(e0, B->stream) != hipSuccess) { st = fail(PSTD_E_HIP, "event record failed"); break; }
         st = launch_steps(B, trial_steps, B->stream);

@@ -130,7 +130,8 @@ struct BatchArgs {
   int nA;
   const BatchTask* tasksB;  // pressure-phase tiles
   int nB;
-  unsigned* counters;       // 2 per step, zeroed by the launcher
+  unsigned* counters;       // 4 per step (two tile tickets, two barrier arrivals), zeroed by the launcher
+  unsigned* timeout;        // set to 1 when a grid barrier gives up waiting (sticky; cleared by the host)
   int64_t steps;
 };
 int batch2d_max_blocks(int* out);

@@ -1,10 +1,14 @@
 // Batched 2D solver: many independent 2D boxes of different sizes stepped by one persistent launch.
 //
-// Every solve advances with Eq. (dtt_pstd_solution) in its 2D form (§4.3).  The launch is cooperative
-// (all blocks resident) and runs all the steps: each step is a velocity phase over the velocity tiles of
-// every solve, a grid-wide barrier, a pressure phase over the pressure tiles of every solve (each p tile
-// takes both axes' terms), and a second barrier.  Within a phase blocks take tiles from a per-phase
-// atomic counter, largest tiles first, so the uneven sizes balance.
+// Every solve advances with Eq. (dtt_pstd_solution) in its 2D form (§4.3).  One launch of at most as many
+// blocks as the GPU holds at once runs all the steps: each step is a velocity phase over the velocity
+// tiles of every solve, a grid-wide barrier, a pressure phase over the pressure tiles of every solve
+// (each p tile takes both axes' terms), and a second barrier.  Within a phase blocks take tiles from a
+// per-phase atomic ticket, largest tiles first, so the uneven sizes balance.  The grid barrier is an
+// arrival counter per (step, phase) with agent-scope release/acquire ordering (the L2 of every XCD is
+// written back and invalidated around it); it gives up after a bounded wait and flags the launch, so a
+// launch whose blocks were not all resident ends instead of hanging.  An ordinary launch, it can be
+// captured in a HIP graph with the kernel that zeroes the counters.
 //
 // Operators are unscaled (dx = 1) FP32 matrices shared by all solves with the same (n, boundary pair);
 // each solve's constants -dt/(rho0 dx) and -dt rho0 c0^2/dx are applied in the FP64 epilogue.  A tile is
@@ -14,15 +18,12 @@
 //
 // MFMA v_mfma_f32_16x16x4: lane l supplies P[l%16][l/16] and Q[l%16][l/16] (both staged as [row][k])
 // and receives C[4*(l/16)+r][l%16] in register r.
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.h"
 
 namespace pstd {
 
 namespace {
 
-namespace cg = cooperative_groups;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
@@ -184,14 +185,33 @@ __device__ void run_task(const BatchSolve& S, const BatchTask& T, float* lds) {
   }
 }
 
+// All blocks of the grid meet here.  Bounded wait: about 2^22 polls (well over a second) before the
+// launch is flagged and the block moves on.
+__device__ void grid_barrier(unsigned* arrivals, unsigned* timeout) {
+  __syncthreads();   // the block's stores are complete
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned polls = 0;
+    // relaxed polls (they read the counter past the caches without invalidating them), one acquire after
+    while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+      __builtin_amdgcn_s_sleep(4);
+      if (++polls > (1u << 22)) {
+        __hip_atomic_store(timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
   __shared__ float lds[4 * TILE * LDB];
-  cg::grid_group grid = cg::this_grid();
   for (int64_t s = 0; s < a.steps; ++s) {
     for (int phase = 0; phase < 2; ++phase) {
       const BatchTask* tasks = phase == 0 ? a.tasksA : a.tasksB;
       const int n = phase == 0 ? a.nA : a.nB;
-      unsigned* ctr = a.counters + 2 * s + phase;
+      unsigned* ctr = a.counters + 4 * s + phase;
       __shared__ int t_shared;
       for (;;) {
         if (threadIdx.x == 0) t_shared = static_cast<int>(atomicAdd(ctr, 1u));
@@ -202,7 +222,7 @@ __global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
         const BatchTask T = tasks[t];
         run_task(a.solves[T.solve], T, lds);
       }
-      grid.sync();
+      grid_barrier(a.counters + 4 * s + 2 + phase, a.timeout);
     }
   }
 }
@@ -225,13 +245,13 @@ int batch2d_max_blocks(int* out) {
 }
 
 hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s) {
-  // fresh phase counters for every launch (a fill kernel, not a memset, so the launch can be captured)
-  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, 2 * a.steps);
+  // fresh tickets and barrier counters for every launch (a fill kernel, not a memset, so the pair of
+  // launches can be captured in a graph)
+  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, 4 * a.steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  BatchArgs args = a;
-  void* params[] = {&args};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch2d_kernel), dim3(blocks), dim3(NT), params, 0, s);
+  hipLaunchKernelGGL(batch2d_kernel, dim3(blocks), dim3(NT), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace pstd

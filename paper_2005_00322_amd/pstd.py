@@ -316,6 +316,10 @@ class Batch:
         self._stream.synchronize()   # the maps are squared into the batch's own buffers
         del keep
 
+    def synchronize(self):
+        """Wait for the batch's work; raises if a grid barrier of the persistent launch timed out."""
+        check(load().pstd_batch_synchronize(self._h), "pstd_batch_synchronize")
+
     def set_config(self, blocks=0, order=0):
         check(load().pstd_batch_set_config(self._h, int(blocks), int(order)), "pstd_batch_set_config")
 

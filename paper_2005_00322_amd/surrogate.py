@@ -146,6 +146,7 @@ def solver_targets(p0s, c0s, dx, dt, steps, bcs, batch=256):
             st = b.new_states([p0s[i] for i in range(s0, s1)])
             b.init_states(st)
             b.step(st, steps)
+            b.synchronize()
             for i in range(s1 - s0):
                 out[s0 + i].copy_(st[i].p)
             torch.cuda.synchronize()

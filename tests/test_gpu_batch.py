@@ -35,7 +35,7 @@ def _run(solves, p0s, steps, config=None, chunks=None):
         b.init_states(st)
         for n in (chunks or [steps]):
             b.step(st, n)
-        torch.cuda.synchronize()
+        b.synchronize()   # raises if a grid barrier timed out
         return [s.p.double().cpu().numpy() for s in st], [[u.double().cpu().numpy() for u in s.u] for s in st]
 
 
@@ -88,7 +88,7 @@ def test_batch_combine_pairs():
         b.init_states(st)
         b.step(st, 40)
         outs = b.combine_R(st, pairs, R)
-        torch.cuda.synchronize()
+        b.synchronize()
         got = [o.double().cpu().numpy() for o in outs]
     for (d, n), r, g in zip(pairs, R, got):
         sd, sn = solves[d], solves[n]
@@ -132,7 +132,7 @@ def test_batched_workload_full():
         b.init_states(st)
         b.step(st, steps)
         outs = b.combine_R(st, pairs, R)
-        torch.cuda.synchronize()
+        b.synchronize()
         ps = [s.p.double().cpu().numpy() for s in st]
         comb = [o.double().cpu().numpy() for o in outs]
     worst = 0.0
