@@ -362,14 +362,14 @@ def run_nop(args, K, W):
     net.set_params(d["theta"])
     out = torch.empty_like(p)
     for _ in range(W):
-        net.forward(p, c, out=out)
+        net.infer(p, c, out=out)
     torch.cuda.synchronize()
     stream = net._stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(K):
-        net.forward(p, c, out=out)
+        net.infer(p, c, out=out)
     e1.record(stream)
     torch.cuda.synchronize()
     t_nop = (time.perf_counter() - t0) / K

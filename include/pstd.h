@@ -228,7 +228,7 @@ int pstd_batch_destroy(pstd_batch batch);
  * Loss: batch mean of |out - target|^2 / |target|^2. */
 typedef struct {
   int32_t H, W;        /* grid */
-  int32_t channels;    /* C */
+  int32_t channels;    /* C, 1 .. 32 */
   int32_t modes;       /* Mm, even, <= H and <= W */
   int32_t layers;      /* 1 .. 16 */
   int32_t hidden;      /* Hp */
@@ -252,6 +252,8 @@ int pstd_nop_get_grads(pstd_nop nop, float* host, int64_t n);
 /* out[b] = network(p0[b], c0[b]) for b < batch (device arrays of batch x H x W floats, row-major) and keep
  * the activations for a following pstd_nop_backward.  Asynchronous on the surrogate's stream. */
 int pstd_nop_forward(pstd_nop nop, const float* p0, const float* c0, float* out, int32_t batch);
+/* The same map for inference: stores no activations (a following pstd_nop_backward is refused). */
+int pstd_nop_infer(pstd_nop nop, const float* p0, const float* c0, float* out, int32_t batch);
 /* Gradient of the loss of the last forward against target (device, batch x H x W) into the surrogate's
  * gradient buffer; *loss (nullable) receives the loss (synchronises when given). */
 int pstd_nop_backward(pstd_nop nop, const float* target, double* loss);

@@ -85,6 +85,7 @@ SIGNATURES = {
     "pstd_nop_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pstd_nop_get_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pstd_nop_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "pstd_nop_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "pstd_nop_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pstd_nop_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]),
     "pstd_nop_relative_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),

@@ -157,7 +157,8 @@ int pstd_nop_create(const pstd_nop_config* cfg, void* hip_stream, pstd_nop* out)
   *out = nullptr;
   if (!cfg) return fail(PSTD_E_INVALID_ARG, "cfg is null");
   const pstd_nop_config c = *cfg;
-  if (c.H < 2 || c.W < 2 || c.channels < 1 || c.modes < 2 || c.modes % 2 || c.modes > c.H || c.modes > c.W ||
+  if (c.H < 2 || c.W < 2 || c.channels < 1 || c.channels > 32 || c.modes < 2 || c.modes % 2 || c.modes > c.H ||
+      c.modes > c.W ||
       c.layers < 1 || c.layers > 16 || c.hidden < 1 || c.max_batch < 1 || (c.split != 0 && c.split != 1))
     return fail(PSTD_E_INVALID_ARG, "bad surrogate configuration");
   const int64_t P = static_cast<int64_t>(c.H) * c.W;
@@ -272,7 +273,14 @@ int pstd_nop_get_grads(pstd_nop N, float* host, int64_t n) {
   return PSTD_OK;
 }
 
-int pstd_nop_forward(pstd_nop N, const float* p0, const float* c0, float* out, int32_t batch) {
+}  // extern "C"
+
+namespace pstd {
+namespace {
+
+// Forward pass; with keep every activation the backward pass needs is stored, otherwise the layers
+// ping-pong between two buffers and nothing else is written.
+int forward_impl(pstd_nop N, const float* p0, const float* c0, float* out, int32_t batch, bool keep) {
   if (!N || !p0 || !c0 || !out) return fail(PSTD_E_INVALID_ARG, "null pointer");
   if (batch < 1 || batch > N->cfg.max_batch) return fail(PSTD_E_INVALID_ARG, "batch must be 1..%d", N->cfg.max_batch);
   const pstd_nop_config& c = N->cfg;
@@ -282,49 +290,38 @@ int pstd_nop_forward(pstd_nop N, const float* p0, const float* c0, float* out, i
   const float* th = N->theta;
   NOP_RUN(launch_nop_features(p0, c0, N->F, B, c.H, c.W, s));
   // lift: V0[b] (C x P) = Pw (C x 4) F[b] (4 x P) + pb
-  NopGemm g = gemm(N, th + N->oP, 4, 1, N->F, P, 1, N->V[0], P, 1, C, static_cast<int>(P), 4);
-  g.nb1 = B;
-  g.bB1 = 4 * P;
-  g.bC1 = C * P;
-  g.bias_m = th + N->opb;
-  NOP_RUN(launch_nop_gemm(g, s));
+  NOP_RUN(launch_nop_mix(th + N->oP, false, N->F, N->V[0], th + N->opb, nullptr, nullptr, C, 4, P, B, false, s));
+  float* vin = N->V[0];
   for (int l = 0; l < c.layers; ++l) {
-    const int st = spectral_fwd(N, N->V[l], th + N->oR[l], N->AT[l], B);
+    float* vout = keep ? N->V[l + 1] : N->V[(l + 1) & 1];
+    const int st = spectral_fwd(N, vin, th + N->oR[l], keep ? N->AT[l] : N->At2, B);
     if (st != PSTD_OK) return st;
-    // V[l+1] = GELU(W V[l] + b + S), pre-activation kept for the backward pass
-    g = gemm(N, th + N->oW[l], C, 1, N->V[l], P, 1, N->V[l + 1], P, 1, C, static_cast<int>(P), C);
-    g.nb1 = B;
-    g.bB1 = C * P;
-    g.bC1 = C * P;
-    g.bias_m = th + N->ob[l];
-    g.add = N->S;
-    g.sDm = P;
-    g.sDn = 1;
-    g.bD1 = C * P;
-    g.pre = N->PRE[l];
-    g.act = 1;
-    NOP_RUN(launch_nop_gemm(g, s));
+    // vout = GELU(W vin + b + S), pre-activation kept for the backward pass
+    NOP_RUN(launch_nop_mix(th + N->oW[l], false, vin, vout, th + N->ob[l], N->S, keep ? N->PRE[l] : nullptr, C, C, P,
+                           B, true, s));
+    vin = vout;
   }
-  // projection: q = GELU(Q1 v + q1b), out = Q2 q + q2b
-  g = gemm(N, th + N->oQ1, C, 1, N->V[c.layers], P, 1, N->q, P, 1, Hp, static_cast<int>(P), C);
-  g.nb1 = B;
-  g.bB1 = C * P;
-  g.bC1 = Hp * P;
-  g.bias_m = th + N->oq1b;
-  g.pre = N->qpre;
-  g.act = 1;
-  NOP_RUN(launch_nop_gemm(g, s));
-  g = gemm(N, th + N->oQ2, Hp, 1, N->q, P, 1, N->out, P, 1, 1, static_cast<int>(P), Hp);
-  g.nb1 = B;
-  g.bB1 = Hp * P;
-  g.bC1 = P;
-  g.bias_m = th + N->oq2b;
-  NOP_RUN(launch_nop_gemm(g, s));
+  // projection: out = Q2 GELU(Q1 v + q1b) + q2b
+  NOP_RUN(launch_nop_project(th + N->oQ1, th + N->oq1b, th + N->oQ2, th + N->oq2b, vin, N->out,
+                             keep ? N->qpre : nullptr, keep ? N->q : nullptr, C, Hp, P, B, s));
   if (out != N->out)
     PSTD_HIP(hipMemcpyAsync(out, N->out, static_cast<size_t>(B) * P * sizeof(float), hipMemcpyDeviceToDevice, s));
   N->last_batch = B;
-  N->have_fwd = true;
+  N->have_fwd = keep;
   return PSTD_OK;
+}
+
+}  // namespace
+}  // namespace pstd
+
+extern "C" {
+
+int pstd_nop_forward(pstd_nop N, const float* p0, const float* c0, float* out, int32_t batch) {
+  return forward_impl(N, p0, c0, out, batch, true);
+}
+
+int pstd_nop_infer(pstd_nop N, const float* p0, const float* c0, float* out, int32_t batch) {
+  return forward_impl(N, p0, c0, out, batch, false);
 }
 
 int pstd_nop_backward(pstd_nop N, const float* target, double* loss) {
@@ -352,22 +349,14 @@ int pstd_nop_backward(pstd_nop N, const float* target, double* loss) {
   st = weight_grad(N, N->dq, Hp, N->V[c.layers], C, gr + N->oQ1, B);
   if (st != PSTD_OK) return st;
   // dv = Q1^T dq
-  g = gemm(N, th + N->oQ1, 1, C, N->dq, P, 1, N->dv, P, 1, C, static_cast<int>(P), Hp);
-  g.nb1 = B;
-  g.bB1 = Hp * P;
-  g.bC1 = C * P;
-  NOP_RUN(launch_nop_gemm(g, s));
+  NOP_RUN(launch_nop_mix(th + N->oQ1, true, N->dq, N->dv, nullptr, nullptr, nullptr, C, Hp, P, B, false, s));
   for (int l = c.layers - 1; l >= 0; --l) {
     NOP_RUN(launch_nop_gelu_bwd(N->dv, N->PRE[l], N->dpre, static_cast<int64_t>(B) * C * P, s));
     NOP_RUN(launch_nop_rowsum(N->dpre, gr + N->ob[l], B, C, P, s));
     st = weight_grad(N, N->dpre, C, N->V[l], C, gr + N->oW[l], B);
     if (st != PSTD_OK) return st;
     // dvn = W^T dpre
-    g = gemm(N, th + N->oW[l], 1, C, N->dpre, P, 1, N->dvn, P, 1, C, static_cast<int>(P), C);
-    g.nb1 = B;
-    g.bB1 = C * P;
-    g.bC1 = C * P;
-    NOP_RUN(launch_nop_gemm(g, s));
+    NOP_RUN(launch_nop_mix(th + N->oW[l], true, N->dpre, N->dvn, nullptr, nullptr, nullptr, C, C, P, B, false, s));
     // spectral path: dZ = DCT(dpre) (the inverse's adjoint), blocked
     g = gemm(N, N->Ch, H, 1, N->dpre, W, 1, N->Y1, W, 1, Mm, W, H);
     g.nb1 = B * C;

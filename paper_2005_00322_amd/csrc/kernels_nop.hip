@@ -21,32 +21,41 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int BK = 32;
 constexpr int LDK = BK + 8;     // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
-constexpr int NT = 256;         // 4 waves, 2 x 2, each 32 x 32
-constexpr int PER = BM * BK / NT;   // elements of each operand tile per thread (8)
+constexpr int NT = 256;         // 4 waves
 
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-// Element e (0 .. BM*BK-1) of an operand tile: row r (m for A, n for B) and column k.  Lanes run along
+// Element e (0 .. ROWS*BK-1) of an operand tile: row r (m for A, n for B) and column k.  Lanes run along
 // k when the operand is contiguous in k, along the rows otherwise, so the loads coalesce either way.
+template <int ROWS>
 __device__ __forceinline__ void tile_pos(int e, bool kcontig, int& r, int& k) {
   if (kcontig) {
     k = e & (BK - 1);
     r = e >> 5;
   } else {
-    r = e & (BM - 1);
-    k = e >> 6;
+    r = e % ROWS;
+    k = e / ROWS;
   }
 }
 
+// Tile of WMW x WNW waves, each computing FM x FN blocks of 32 x 32 outputs:
+// BM = 32 WMW FM rows, BN = 32 WNW FN columns.
+template <int WMW, int WNW, int FM, int FN>
 __global__ __launch_bounds__(NT) void nop_gemm_kernel(NopGemm g) {
-  __shared__ __attribute__((aligned(16))) __bf16 lds[4][BM * LDK];   // A hi, A lo, B hi, B lo ([row][k])
+  constexpr int BM = 32 * WMW * FM, BN = 32 * WNW * FN;
+  constexpr int PA = BM * BK / NT, PB = BN * BK / NT;   // operand elements staged per thread
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * (BM + BN) * LDK];   // A hi, A lo, B hi, B lo
+  __bf16* Ah = lds;
+  __bf16* Al = lds + BM * LDK;
+  __bf16* Bh = lds + 2 * BM * LDK;
+  __bf16* Bl = Bh + BN * LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WMW, wn = wave / WMW;
   const int tiles_m = (g.M + BM - 1) / BM;
   const int m0 = (blockIdx.x % tiles_m) * BM, n0 = (blockIdx.x / tiles_m) * BN;
   const int z = blockIdx.y;
@@ -55,57 +64,88 @@ __global__ __launch_bounds__(NT) void nop_gemm_kernel(NopGemm g) {
   const float* B = g.B + z1 * g.bB1 + z2 * g.bB2;
   const bool akc = g.sAk == 1, bkc = g.sBk == 1;
   const bool split = g.split != 0;
+  // element offsets within one batch entry fit in 32 bits (the host checks every operand's extent)
+  const uint32_t sAm = static_cast<uint32_t>(g.sAm), sAk = static_cast<uint32_t>(g.sAk);
+  const uint32_t sBk = static_cast<uint32_t>(g.sBk), sBn = static_cast<uint32_t>(g.sBn);
 
-  float ra[PER], rb[PER];
+  float ra[PA], rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < PA; ++i) {
       int r, k;
-      tile_pos(tid + i * NT, akc, r, k);
+      tile_pos<BM>(tid + i * NT, akc, r, k);
       const int m = m0 + r, kk = k0 + k;
-      ra[i] = (m < g.M && kk < g.K) ? A[m * g.sAm + kk * g.sAk] : 0.f;
-      tile_pos(tid + i * NT, bkc, r, k);
-      const int n = n0 + r;
-      const int kb = k0 + k;
-      rb[i] = (n < g.N && kb < g.K) ? B[kb * g.sBk + n * g.sBn] : 0.f;
+      ra[i] = (m < g.M && kk < g.K) ? A[static_cast<uint32_t>(m) * sAm + static_cast<uint32_t>(kk) * sAk] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      int r, k;
+      tile_pos<BN>(tid + i * NT, bkc, r, k);
+      const int n = n0 + r, kb = k0 + k;
+      rb[i] = (n < g.N && kb < g.K) ? B[static_cast<uint32_t>(kb) * sBk + static_cast<uint32_t>(n) * sBn] : 0.f;
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < PA; ++i) {
       int r, k;
-      tile_pos(tid + i * NT, akc, r, k);
+      tile_pos<BM>(tid + i * NT, akc, r, k);
       const __bf16 h = static_cast<__bf16>(ra[i]);
-      lds[0][r * LDK + k] = h;
-      if (split) lds[1][r * LDK + k] = static_cast<__bf16>(ra[i] - static_cast<float>(h));
-      tile_pos(tid + i * NT, bkc, r, k);
-      const __bf16 hb = static_cast<__bf16>(rb[i]);
-      lds[2][r * LDK + k] = hb;
-      if (split) lds[3][r * LDK + k] = static_cast<__bf16>(rb[i] - static_cast<float>(hb));
+      Ah[r * LDK + k] = h;
+      if (split) Al[r * LDK + k] = static_cast<__bf16>(ra[i] - static_cast<float>(h));
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      int r, k;
+      tile_pos<BN>(tid + i * NT, bkc, r, k);
+      const __bf16 h = static_cast<__bf16>(rb[i]);
+      Bh[r * LDK + k] = h;
+      if (split) Bl[r * LDK + k] = static_cast<__bf16>(rb[i] - static_cast<float>(h));
     }
   };
 
-  f32x16 acc;
+  f32x16 acc[FM][FN];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   const int nsl = (g.K + BK - 1) / BK;
   load(0);
   store();
   lds_barrier();
-  const int arow = wm * 32 + (lane & 31), brow = wn * 32 + (lane & 31);
   const int koff = 8 * (lane >> 5);
   for (int s = 0; s < nsl; ++s) {
     if (s + 1 < nsl) load((s + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
-      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&lds[0][arow * LDK + kk + koff]);
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&lds[2][brow * LDK + kk + koff]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+      bf16x8 ah[FM], bh[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[((wm * FM + i) * 32 + (lane & 31)) * LDK + kk + koff]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[((wn * FN + j) * 32 + (lane & 31)) * LDK + kk + koff]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       if (split) {
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&lds[1][arow * LDK + kk + koff]);
-        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&lds[3][brow * LDK + kk + koff]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+        bf16x8 al[FM], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          al[i] = *reinterpret_cast<const bf16x8*>(&Al[((wm * FM + i) * 32 + (lane & 31)) * LDK + kk + koff]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[((wn * FN + j) * 32 + (lane & 31)) * LDK + kk + koff]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          }
       }
     }
     lds_barrier();
@@ -120,24 +160,52 @@ __global__ __launch_bounds__(NT) void nop_gemm_kernel(NopGemm g) {
   const float* Dp = g.add ? g.add + z1 * g.bD1 + z2 * g.bD2 : nullptr;
   float* Pp = g.pre ? g.pre + z1 * g.bC1 + z2 * g.bC2 : nullptr;
   const float* Gp = g.dgelu ? g.dgelu + z1 * g.bC1 + z2 * g.bC2 : nullptr;
-  const int n = n0 + wn * 32 + (lane & 31);
+  const uint32_t sCm = static_cast<uint32_t>(g.sCm), sCn = static_cast<uint32_t>(g.sCn);
+  const uint32_t sDm = static_cast<uint32_t>(g.sDm), sDn = static_cast<uint32_t>(g.sDn);
+  // All reads of a 32 x 32 block (old C, the added tensor, the GELU argument, the bias) are issued before
+  // its first store: the stores may alias nothing the loads touch, but the compiler cannot know that,
+  // and interleaving would serialise every element on a memory round trip.
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    if (m < g.M && n < g.N) {
-      const int64_t co = m * g.sCm + n * g.sCn;
-      float v = g.alpha * acc[r];
-      if (g.beta != 0.f) v += g.beta * C[co];
-      if (g.bias_m) v += g.bias_m[m];
-      if (Dp) v += Dp[m * g.sDm + n * g.sDn];
-      if (Gp) v *= gelu_grad_f(Gp[co]);
-      if (g.act) {
-        if (Pp) Pp[co] = v;
-        v = gelu_f(v);
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + (wn * FN + j) * 32 + (lane & 31);
+      float ext[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + (wm * FM + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const bool ok = m < g.M && n < g.N;
+        const uint32_t co = static_cast<uint32_t>(m) * sCm + static_cast<uint32_t>(n) * sCn;
+        float e = 0.f;
+        if (ok) {
+          if (g.beta != 0.f) e += g.beta * C[co];
+          if (g.bias_m) e += g.bias_m[m];
+          if (Dp) e += Dp[static_cast<uint32_t>(m) * sDm + static_cast<uint32_t>(n) * sDn];
+        }
+        ext[r] = e;
       }
-      C[co] = v;
+      float gg[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + (wm * FM + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const uint32_t co = static_cast<uint32_t>(m) * sCm + static_cast<uint32_t>(n) * sCn;
+        gg[r] = (Gp && m < g.M && n < g.N) ? Gp[co] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + (wm * FM + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m < g.M && n < g.N) {
+          const uint32_t co = static_cast<uint32_t>(m) * sCm + static_cast<uint32_t>(n) * sCn;
+          float v = g.alpha * acc[i][j][r] + ext[r];
+          if (Gp) v *= gelu_grad_f(gg[r]);
+          if (g.act) {
+            if (Pp) Pp[co] = v;
+            v = gelu_f(v);
+          }
+          C[co] = v;
+        }
+      }
     }
-  }
 }
 
 // Natural spectral layout [b][c][kh][kw] <-> block layout [blk][q][b][c] (blk = (kh/2)(Mm/2) + kw/2,
@@ -299,14 +367,139 @@ __global__ void nop_input_stats_kernel(const float* p0, const float* c0, double*
   }
 }
 
+// Pointwise channel mixing on the FP32 matrix cores: Y[b][o][p] = sum_i A[o][i] X[b][i][p] (+ bias[o])
+// (+ D[b][o][p]), then optionally pre = value and Y = GELU(value), for O <= 32 output channels.  Each
+// wave computes all O outputs of 32 consecutive positions with v_mfma_f32_32x32x2f32: lane l supplies
+// A[l%32][k0 + l/32] and X[k0 + l/32][l%32] (read straight from HBM, coalesced along the positions) and
+// receives Y[8(r/4) + 4(l/32) + r%4][l%32] in register r.  A is O x I row-major, or I x O with tA.
+__global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ A, const float* __restrict__ X,
+                                                      float* __restrict__ Y, const float* __restrict__ bias,
+                                                      const float* __restrict__ D, float* __restrict__ pre, int O, int I,
+                                                      int64_t P, int act, int tA) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b = blockIdx.y;
+  const int64_t n = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32 + (lane & 31);
+  const int kk = lane >> 5, o = lane & 31;
+  const bool nok = n < P;
+  const float* xb = X + b * I * P + (nok ? n : 0);
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int k0 = 0; k0 < I; k0 += 32) {
+    float av[16], xv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = k0 + 2 * j + kk;
+      const bool kok = k < I;
+      av[j] = (o < O && kok) ? (tA ? A[static_cast<int64_t>(k) * O + o] : A[static_cast<int64_t>(o) * I + k]) : 0.f;
+      xv[j] = (nok && kok) ? xb[static_cast<int64_t>(k) * P] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], xv[j], acc, 0, 0, 0);
+  }
+  float e[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int oo = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    e[r] = (oo < O && nok) ? ((D ? D[(b * O + oo) * P + n] : 0.f) + (bias ? bias[oo] : 0.f)) : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int oo = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (oo < O && nok) {
+      const int64_t off = (b * O + oo) * P + n;
+      float v = acc[r] + e[r];
+      if (act) {
+        if (pre) pre[off] = v;
+        v = gelu_f(v);
+      }
+      Y[off] = v;
+    }
+  }
+}
+
+// Fused projection on the FP32 matrix cores: out[b][p] = sum_j Q2[j] GELU(sum_c Q1[j][c] v[b][c][p] + q1b[j])
+// + q2b (C <= 32 channels), 32 hidden rows per pass; each lane sums its rows, the two halves of the wave
+// are added with a lane exchange.  With keep (qpre non-null), qpre and q ([b][Hp][P]) are stored.
+__global__ __launch_bounds__(256) void nop_project_kernel(const float* __restrict__ Q1, const float* __restrict__ q1b,
+                                                          const float* __restrict__ Q2, const float* __restrict__ q2b,
+                                                          const float* __restrict__ v, float* __restrict__ out,
+                                                          float* __restrict__ qpre, float* __restrict__ q, int C,
+                                                          int Hp, int64_t P) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b = blockIdx.y;
+  const int64_t n = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32 + (lane & 31);
+  const int kk = lane >> 5, o = lane & 31;
+  const bool nok = n < P;
+  const float* vb = v + b * C * P + (nok ? n : 0);
+  float xv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = 2 * j + kk;
+    xv[j] = (nok && k < C) ? vb[static_cast<int64_t>(k) * P] : 0.f;
+  }
+  float part = 0.f;
+  for (int t0 = 0; t0 < Hp; t0 += 32) {
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    float av[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = 2 * j + kk;
+      av[j] = (t0 + o < Hp && k < C) ? Q1[static_cast<int64_t>(t0 + o) * C + k] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], xv[j], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int jj = t0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (jj < Hp) {
+        const float h = acc[r] + q1b[jj];
+        const float g = gelu_f(h);
+        if (qpre && nok) {
+          const int64_t off = (b * Hp + jj) * P + n;
+          qpre[off] = h;
+          q[off] = g;
+        }
+        part = fmaf(Q2[jj], g, part);
+      }
+    }
+  }
+  part += __shfl_xor(part, 32);
+  if (lane < 32 && nok) out[b * P + n] = part + q2b[0];
+}
+
 unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
 
 }  // namespace
 
+// Tile shape by operand shape: few output rows (channel mixing, K = 32) take 32 x 256 tiles so each
+// block streams a long run of positions; the rest 64 x 64.
 hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nb1 * g.nb2 <= 0) return hipSuccess;
-  const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  hipLaunchKernelGGL(nop_gemm_kernel, dim3(tiles, g.nb1 * g.nb2), dim3(NT), 0, s, g);
+  const dim3 grid_z(1, g.nb1 * g.nb2);
+  auto tiles = [&](int bm, int bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn); };
+  if (g.M <= 32 && g.N >= 256) {
+    hipLaunchKernelGGL((nop_gemm_kernel<1, 4, 1, 2>), dim3(tiles(32, 256), g.nb1 * g.nb2), dim3(NT), 0, s, g);
+  } else {
+    hipLaunchKernelGGL((nop_gemm_kernel<2, 2, 1, 1>), dim3(tiles(64, 64), g.nb1 * g.nb2), dim3(NT), 0, s, g);
+  }
+  (void)grid_z;
+  return hipGetLastError();
+}
+
+hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y, const float* bias, const float* D,
+                          float* pre, int O, int I, int64_t P, int B, bool act, hipStream_t s) {
+  hipLaunchKernelGGL(nop_mix_kernel, dim3(blocks_for(P, 128), B), dim3(256), 0, s, A, X, Y, bias, D, pre, O, I, P,
+                     act ? 1 : 0, transA ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
+                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, hipStream_t s) {
+  hipLaunchKernelGGL(nop_project_kernel, dim3(blocks_for(P, 128), B), dim3(256), 0, s, Q1, q1b, Q2, q2b, v, out, qpre,
+                     q, C, Hp, P);
   return hipGetLastError();
 }
 

@@ -89,6 +89,18 @@ class Surrogate:
         self._keep = (p, cm)
         return out
 
+    def infer(self, p0, c0, out=None):
+        """out = network(p0, c0) without keeping activations (the inference form)."""
+        torch = _torch()
+        p, cm = self._dev(p0), self._dev(c0)
+        if p.shape != cm.shape:
+            raise ValueError("p0 and c0 shapes differ")
+        B = int(p.shape[0])
+        if out is None:
+            out = torch.empty_like(p)
+        check(load().pstd_nop_infer(self._h, p.data_ptr(), cm.data_ptr(), out.data_ptr(), B), "pstd_nop_infer")
+        return out
+
     def backward(self, target) -> float:
         t = self._dev(target)
         loss = C.c_double()
@@ -196,7 +208,7 @@ def predict(net: Surrogate, p0, c0, tol: float, gate: Gate, dx, dt, steps, bcs):
     out = torch.empty_like(p)
     for s0 in range(0, B, net.max_batch):
         s1 = min(B, s0 + net.max_batch)
-        net.forward(p[s0:s1], cm[s0:s1], out=out[s0:s1])
+        net.infer(p[s0:s1], cm[s0:s1], out=out[s0:s1])
     idx = np.nonzero(fallback)[0]
     if idx.size:
         ti = torch.from_numpy(idx).to(p.device)

@@ -80,7 +80,7 @@ def evaluate(net, p, c, t, batch):
     out = torch.empty_like(t[:batch])
     for s in range(0, int(p.shape[0]), batch):
         e = min(int(p.shape[0]), s + batch)
-        o = net.forward(p[s:e], c[s:e], out=out[:e - s])
+        o = net.infer(p[s:e], c[s:e], out=out[:e - s])
         errs.append(net.relative_errors(o, t[s:e]))
     return np.concatenate(errs)
 

@@ -17,13 +17,15 @@ from oracle import pstd as opstd
 pytestmark = pytest.mark.gpu
 
 SMALL = dict(H=16, W=12, channels=4, modes=6, layers=2, hidden=8)
+# 256 positions: both GEMM tile shapes of the library (32 x 256 and 64 x 64) are used
+MEDIUM = dict(H=16, W=16, channels=8, modes=8, layers=1, hidden=128)
 
 
-def _setup(split, B=3, seed=0):
+def _setup(split, B=3, seed=0, shape=SMALL):
     import torch
     from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig, param_shapes
 
-    scfg = SurrogateConfig(**SMALL)
+    scfg = SurrogateConfig(**shape)
     ocfg = onop.Config(H=scfg.H, W=scfg.W, C=scfg.channels, Mm=scfg.modes, layers=scfg.layers, Hp=scfg.hidden)
     net = Surrogate(scfg, max_batch=4, split=split)
     assert net.n_params == onop.param_count(ocfg)
@@ -36,13 +38,15 @@ def _setup(split, B=3, seed=0):
     return torch, net, ocfg, theta, p0, c0, tgt
 
 
+@pytest.mark.parametrize("shape", ["small", "medium"])
 @pytest.mark.parametrize("split,tol", [(True, 1e-4), (False, 3e-2)])
-def test_forward_and_gradients_match_reference(split, tol):
-    torch, net, ocfg, theta, p0, c0, tgt = _setup(split)
-    print("surrogate parity split", split, flush=True)
+def test_forward_and_gradients_match_reference(split, tol, shape):
+    torch, net, ocfg, theta, p0, c0, tgt = _setup(split, shape=SMALL if shape == "small" else MEDIUM)
+    print("surrogate parity split", split, shape, flush=True)
     out = net.forward(p0, c0)
     loss = net.backward(tgt)
     torch.cuda.synchronize()
+    assert torch.equal(net.infer(p0, c0), out)   # the inference form computes the same map
     g = net.get_grads().astype(np.float64)
     th = theta.astype(np.float64)
     ref_out = onop.forward(ocfg, th, p0.astype(np.float64), c0.astype(np.float64))
