@@ -196,14 +196,16 @@ int pstd_batch_step(pstd_batch batch, pstd_state* states, int64_t n_steps);
 int pstd_batch_combine_R(pstd_batch batch, const pstd_state* states, const int32_t* pairs, const double* R,
                          float* const* out, int32_t npairs);
 
-/* Launch configuration of pstd_batch_step: resident block count (0 = the occupancy maximum) and tile
- * order within a phase (0 = longest contraction first, 1 = solve by solve). */
-int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order);
+/* Launch configuration of pstd_batch_step: resident block count (0 = the occupancy maximum), tile
+ * order within a phase (0 = longest contraction first, 1 = solve by solve) and output tile edge (32:
+ * 32 x 32 tiles on FP32 MFMA 16x16x4; 64: 64 x 64 tiles on FP32 MFMA 32x32x2). */
+int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order, int32_t tile);
 
-/* Autotuner: time every candidate configuration for trial_steps steps on scratch state buffers (the
- * caller's states are not touched), keep the fastest and, if cache_path is not NULL, store it in a small
- * JSON file keyed by a signature of the batch; a later call with a matching file skips the timing.
- * config_out (nullable, 3 ints): blocks, order, 1 if taken from the cache.  Synchronous. */
+/* Autotuner: time every candidate configuration (tile edge x block count x order) for trial_steps steps
+ * on scratch state buffers (the caller's states are not touched), keep the fastest and, if cache_path is
+ * not NULL, store it in a small JSON file keyed by a signature of the batch; a later call with a matching
+ * file skips the timing.  config_out (nullable, 4 ints): blocks, order, tile, 1 if taken from the cache.
+ * Synchronous. */
 int pstd_batch_autotune(pstd_batch batch, int32_t trial_steps, const char* cache_path, int32_t* config_out);
 
 /* Wait for the batch's stream and report whether every grid barrier of the launches since the last

@@ -74,7 +74,7 @@ SIGNATURES = {
     "pstd_batch_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int64]),
     "pstd_batch_combine_R": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                        C.POINTER(C.c_void_p), C.c_int32]),
-    "pstd_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pstd_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "pstd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]),
     "pstd_batch_set_c0_maps": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "pstd_batch_synchronize": (C.c_int, [C.c_void_p]),

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 
 #include "common.h"
 
@@ -28,17 +29,18 @@ struct pstd_batch_s {
   std::vector<pstd::BatchTask> tasksA, tasksB;
   pstd::BatchTask* d_tasks = nullptr;         // A then B
   int order_built = -1;
+  int tile_built = -1;
   unsigned* d_counters = nullptr;             // 4 per step of a launch, then the barrier timeout flag
   int blocks = 0;                             // 0 = occupancy maximum
   int order = 0;
+  int tile = 32;                              // output tile edge of the persistent kernel (32 or 64)
   hipStream_t capture = nullptr;              // private stream the launch graphs are captured on
-  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;   // (steps, blocks) -> instantiated graph
+  std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;   // (steps, blocks, tile) -> graph
 };
 
 namespace pstd {
 namespace {
 
-constexpr int kTile = 32;
 constexpr int64_t kChunk = 1024;   // steps per persistent launch (4 counters each)
 
 int upload_unscaled(const std::vector<double>& m, int M, int K, DevOperator* op) {
@@ -70,19 +72,19 @@ void free_batch(pstd_batch_s* B) {
   delete B;
 }
 
-// Tile lists of both phases in the requested order.
-void build_tasks(pstd_batch_s* B, int order) {
+// Tile lists of both phases for output tiles of edge T, in the requested order.
+void build_tasks(pstd_batch_s* B, int order, int T) {
   B->tasksA.clear();
   B->tasksB.clear();
   std::vector<std::pair<int, BatchTask>> a, b;   // (contracted length, task)
   for (int s = 0; s < B->count; ++s) {
     const int nx = B->nx[s], ny = B->ny[s];
-    for (int i0 = 0; i0 < nx - 1; i0 += kTile)
-      for (int j0 = 0; j0 < ny; j0 += kTile) a.push_back({nx, BatchTask{s, 0, i0, j0}});
-    for (int i0 = 0; i0 < nx; i0 += kTile)
-      for (int j0 = 0; j0 < ny - 1; j0 += kTile) a.push_back({ny, BatchTask{s, 1, i0, j0}});
-    for (int i0 = 0; i0 < nx; i0 += kTile)
-      for (int j0 = 0; j0 < ny; j0 += kTile) b.push_back({nx + ny - 2, BatchTask{s, 2, i0, j0}});
+    for (int i0 = 0; i0 < nx - 1; i0 += T)
+      for (int j0 = 0; j0 < ny; j0 += T) a.push_back({nx, BatchTask{s, 0, i0, j0}});
+    for (int i0 = 0; i0 < nx; i0 += T)
+      for (int j0 = 0; j0 < ny - 1; j0 += T) a.push_back({ny, BatchTask{s, 1, i0, j0}});
+    for (int i0 = 0; i0 < nx; i0 += T)
+      for (int j0 = 0; j0 < ny; j0 += T) b.push_back({nx + ny - 2, BatchTask{s, 2, i0, j0}});
   }
   if (order == 0) {
     auto longest_first = [](const std::pair<int, BatchTask>& x, const std::pair<int, BatchTask>& y) { return x.first > y.first; };
@@ -94,15 +96,22 @@ void build_tasks(pstd_batch_s* B, int order) {
 }
 
 int ensure_tasks(pstd_batch_s* B) {
-  if (B->order_built == B->order && B->d_tasks) return PSTD_OK;
-  build_tasks(B, B->order);
-  const size_t n = B->tasksA.size() + B->tasksB.size();
-  if (!B->d_tasks && hipMalloc(&B->d_tasks, n * sizeof(BatchTask)) != hipSuccess)
-    return fail(PSTD_E_OOM, "hipMalloc of the task lists failed");
+  if (B->order_built == B->order && B->tile_built == B->tile && B->d_tasks) return PSTD_OK;
+  if (!B->d_tasks) {
+    // sized for the smallest tile (the longest lists); the address stays fixed for captured graphs
+    build_tasks(B, 0, 32);
+    const size_t n = B->tasksA.size() + B->tasksB.size();
+    if (hipMalloc(&B->d_tasks, n * sizeof(BatchTask)) != hipSuccess)
+      return fail(PSTD_E_OOM, "hipMalloc of the task lists failed");
+  }
+  build_tasks(B, B->order, B->tile);
+  // the stream may still run a launch reading the previous lists
+  PSTD_HIP(B->stream ? hipStreamSynchronize(B->stream) : hipDeviceSynchronize());
   PSTD_HIP(hipMemcpy(B->d_tasks, B->tasksA.data(), B->tasksA.size() * sizeof(BatchTask), hipMemcpyHostToDevice));
   PSTD_HIP(hipMemcpy(B->d_tasks + B->tasksA.size(), B->tasksB.data(), B->tasksB.size() * sizeof(BatchTask),
                      hipMemcpyHostToDevice));
   B->order_built = B->order;
+  B->tile_built = B->tile;
   return PSTD_OK;
 }
 
@@ -131,7 +140,7 @@ int ensure_solves(pstd_batch_s* B, const pstd_state* st) {
 
 int resident_blocks(const pstd_batch_s* B, int* out) {
   int maxb = 0;
-  if (batch2d_max_blocks(&maxb) != 0 || maxb < 1) return fail(PSTD_E_HIP, "occupancy query failed");
+  if (batch2d_max_blocks(B->tile, &maxb) != 0 || maxb < 1) return fail(PSTD_E_HIP, "occupancy query failed");
   *out = (B->blocks > 0 && B->blocks < maxb) ? B->blocks : maxb;
   return PSTD_OK;
 }
@@ -140,7 +149,7 @@ int resident_blocks(const pstd_batch_s* B, int* out) {
 // device tables it reads (solves, tasks, counters) keep their addresses for the batch's lifetime; their
 // contents are refreshed in place.
 int graph_for(pstd_batch_s* B, int64_t steps, int blocks, hipGraphExec_t* out) {
-  const auto key = std::make_pair(steps, blocks);
+  const auto key = std::make_tuple(steps, blocks, B->tile);
   auto it = B->graphs.find(key);
   if (it != B->graphs.end()) {
     *out = it->second;
@@ -158,7 +167,7 @@ int graph_for(pstd_batch_s* B, int64_t steps, int blocks, hipGraphExec_t* out) {
   a.steps = steps;
   hipGraph_t g = nullptr;
   PSTD_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
-  const hipError_t le = launch_batch2d(a, blocks, B->capture);
+  const hipError_t le = launch_batch2d(a, B->tile, blocks, B->capture);
   hipError_t e = hipStreamEndCapture(B->capture, &g);
   if (le != hipSuccess) e = le;
   hipGraphExec_t ex = nullptr;
@@ -204,7 +213,7 @@ std::string signature(const pstd_batch_s* B) {
   return buf;
 }
 
-bool read_cache(const char* path, const std::string& sig, int* blocks, int* order) {
+bool read_cache(const char* path, const std::string& sig, int* blocks, int* order, int* tile) {
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char buf[512] = {0};
@@ -212,15 +221,19 @@ bool read_cache(const char* path, const std::string& sig, int* blocks, int* orde
   fclose(f);
   buf[n] = 0;
   char s[64] = {0};
-  int b = 0, o = 0;
+  int b = 0, o = 0, t = 0;
   const char* p = strstr(buf, "\"signature\"");
   if (!p || sscanf(p, "\"signature\": \"%63[0-9a-f]\"", s) != 1) return false;
   const char* pb = strstr(buf, "\"blocks\"");
   const char* po = strstr(buf, "\"order\"");
-  if (!pb || !po || sscanf(pb, "\"blocks\": %d", &b) != 1 || sscanf(po, "\"order\": %d", &o) != 1) return false;
+  const char* pt = strstr(buf, "\"tile\"");
+  if (!pb || !po || !pt || sscanf(pb, "\"blocks\": %d", &b) != 1 || sscanf(po, "\"order\": %d", &o) != 1 ||
+      sscanf(pt, "\"tile\": %d", &t) != 1 || (t != 32 && t != 64))
+    return false;
   if (sig != s) return false;
   *blocks = b;
   *order = o;
+  *tile = t;
   return true;
 }
 
@@ -427,24 +440,28 @@ int pstd_batch_combine_R(pstd_batch B, const pstd_state* st, const int32_t* pair
   return PSTD_OK;
 }
 
-int pstd_batch_set_config(pstd_batch B, int32_t blocks, int32_t order) {
-  if (!B || blocks < 0 || order < 0 || order > 1) return fail(PSTD_E_INVALID_ARG, "bad batch configuration");
+int pstd_batch_set_config(pstd_batch B, int32_t blocks, int32_t order, int32_t tile) {
+  if (!B || blocks < 0 || order < 0 || order > 1 || (tile != 32 && tile != 64))
+    return fail(PSTD_E_INVALID_ARG, "bad batch configuration");
   B->blocks = blocks;
   B->order = order;
+  B->tile = tile;
   return PSTD_OK;
 }
 
 int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_path, int32_t* config_out) {
   if (!B || trial_steps < 1) return fail(PSTD_E_INVALID_ARG, "bad batch or trial_steps");
   const std::string sig = signature(B);
-  int cb = 0, co = 0;
-  if (cache_path && read_cache(cache_path, sig, &cb, &co)) {
+  int cb = 0, co = 0, ct = 32;
+  if (cache_path && read_cache(cache_path, sig, &cb, &co, &ct)) {
     B->blocks = cb;
     B->order = co;
+    B->tile = ct;
     if (config_out) {
       config_out[0] = cb;
       config_out[1] = co;
-      config_out[2] = 1;
+      config_out[2] = ct;
+      config_out[3] = 1;
     }
     return PSTD_OK;
   }
@@ -473,26 +490,31 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
     scratch[s].u[2] = nullptr;
     scratch[s].step = 0;
   }
-  int maxb = 0;
-  if (st == PSTD_OK && batch2d_max_blocks(&maxb) != 0) st = fail(PSTD_E_HIP, "occupancy query failed");
   int cus = 0, dev = 0;
   if (st == PSTD_OK && (hipGetDevice(&dev) != hipSuccess ||
                         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess))
     st = fail(PSTD_E_HIP, "device query failed");
   const std::vector<void*> saved_key = B->key;
   double best = 1e300;
-  int best_b = maxb, best_o = 0;
+  int best_b = 0, best_o = 0, best_t = 32;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (st == PSTD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     st = fail(PSTD_E_HIP, "event creation failed");
-  if (st == PSTD_OK) {
+  for (int tile : {32, 64}) {
+    if (st != PSTD_OK) break;
+    int maxb = 0;
+    if (batch2d_max_blocks(tile, &maxb) != 0 || maxb < 1) {
+      st = fail(PSTD_E_HIP, "occupancy query failed");
+      break;
+    }
     std::vector<int> cand;
     for (int m = 1; m * cus <= maxb; ++m) cand.push_back(m * cus);
     if (cand.empty() || cand.back() != maxb) cand.push_back(maxb);
     for (int order = 0; order < 2 && st == PSTD_OK; ++order)
       for (int b : cand) {
-        B->blocks = b;
+        B->blocks = b == maxb ? 0 : b;
         B->order = order;
+        B->tile = tile;
         st = ensure_solves(B, scratch.data());
         if (st == PSTD_OK) st = ensure_tasks(B);
         if (st == PSTD_OK) st = launch_steps(B, trial_steps, B->stream);   // warm (and capture the graph)
@@ -508,8 +530,9 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
           best = ms;
-          best_b = b;
+          best_b = B->blocks;
           best_o = order;
+          best_t = tile;
         }
       }
   }
@@ -520,20 +543,22 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
   B->key.clear();   // the device solve table points at the freed scratch states
   (void)saved_key;
   if (st != PSTD_OK) return st;
-  B->blocks = best_b == maxb ? 0 : best_b;
+  B->blocks = best_b;
   B->order = best_o;
+  B->tile = best_t;
   if (cache_path) {
     FILE* f = fopen(cache_path, "w");
     if (f) {
-      fprintf(f, "{\"signature\": \"%s\", \"blocks\": %d, \"order\": %d, \"ms_per_step\": %.6f}\n", sig.c_str(),
-              B->blocks, B->order, best / trial_steps);
+      fprintf(f, "{\"signature\": \"%s\", \"blocks\": %d, \"order\": %d, \"tile\": %d, \"ms_per_step\": %.6f}\n",
+              sig.c_str(), B->blocks, B->order, B->tile, best / trial_steps);
       fclose(f);
     }
   }
   if (config_out) {
     config_out[0] = B->blocks;
     config_out[1] = B->order;
-    config_out[2] = 0;
+    config_out[2] = B->tile;
+    config_out[3] = 0;
   }
   return PSTD_OK;
 }

@@ -134,8 +134,8 @@ struct BatchArgs {
   unsigned* timeout;        // set to 1 when a grid barrier gives up waiting (sticky; cleared by the host)
   int64_t steps;
 };
-int batch2d_max_blocks(int* out);
-hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s);
+int batch2d_max_blocks(int tile, int* out);   // tile: 32 or 64 (output tile edge)
+hipError_t launch_batch2d(const BatchArgs& a, int tile, int blocks, hipStream_t s);
 
 hipError_t launch_nonfinite(int prec, const void* x, int64_t count, int* flag, hipStream_t s);
 

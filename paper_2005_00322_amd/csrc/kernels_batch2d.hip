@@ -4,7 +4,8 @@
 // blocks as the GPU holds at once runs all the steps: each step is a velocity phase over the velocity
 // tiles of every solve, a grid-wide barrier, a pressure phase over the pressure tiles of every solve
 // (each p tile takes both axes' terms), and a second barrier.  Within a phase blocks take tiles from a
-// per-phase atomic ticket, largest tiles first, so the uneven sizes balance.  The grid barrier is an
+// per-phase atomic ticket, largest tiles first, so the uneven sizes balance.  Output tiles are 32 x 32
+// (FP32 MFMA 16x16x4) or 64 x 64 (FP32 MFMA 32x32x2), chosen per batch by the autotuner.  The grid barrier is an
 // arrival counter per (step, phase) with agent-scope release/acquire ordering (the L2 of every XCD is
 // written back and invalidated around it); it gives up after a bounded wait and flags the launch, so a
 // launch whose blocks were not all resident ends instead of hanging.  An ordinary launch, it can be
@@ -27,11 +28,11 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-constexpr int TILE = 32;
 constexpr int BK = 32;
 constexpr int LDB = BK + 1;      // LDS row stride (floats)
 constexpr int NT = 256;
 constexpr uint32_t kOOB = 0x80000000u;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
@@ -40,36 +41,44 @@ __device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
-// Stage one BK slice of a tile operand into LDS [row][k] (32 rows).
+// Stage one BK slice of a TILE-row tile operand into LDS [row][k].
 //   operator rows: A[(r0 + r) * lda + k], zero padded on the host (no checks)
 //   field rows (contiguous):  X[(r0 + r) * ldx + k] for r0 + r < rows, k < K
 //   field columns (strided):  X[k * ldx + c0 + c]   for c0 + c < cols, k < K   (transposed into [c][k])
-// Each thread holds 4 values of the next slice in registers between load and store.
+// Each thread holds TILE/8 values of the next slice in registers between load and store.
+template <int TILE>
 struct Stager {
+  static constexpr int V = TILE / 8;
   int kind;          // 0 operator rows, 1 field rows, 2 field columns
   const float* base;
   rsrc_t rs;
   int ld, r0, lim, K;
-  float v[4];
+  float v[V];
 
   __device__ void load(int k0) {
     const int t = threadIdx.x;
     if (kind == 0) {
-      const int r = t >> 3, kk = (t & 7) * 4;
-      const f32x4 x = *reinterpret_cast<const f32x4*>(base + static_cast<int64_t>(r0 + r) * ld + k0 + kk);
-      v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
-    } else if (kind == 1) {
-      const int r = t >> 3, kk = (t & 7) * 4;
-      const bool rv = r0 + r < lim;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = k0 + kk + j;
-        v[j] = ld_f32(rs, (rv && k < K) ? 4u * static_cast<uint32_t>((r0 + r) * ld + k) : kOOB);
+      for (int h = 0; h < V / 4; ++h) {
+        const int r = (t >> 3) + 32 * h, kk = (t & 7) * 4;
+        const f32x4 x = *reinterpret_cast<const f32x4*>(base + static_cast<int64_t>(r0 + r) * ld + k0 + kk);
+        v[4 * h] = x[0]; v[4 * h + 1] = x[1]; v[4 * h + 2] = x[2]; v[4 * h + 3] = x[3];
+      }
+    } else if (kind == 1) {
+#pragma unroll
+      for (int h = 0; h < V / 4; ++h) {
+        const int r = (t >> 3) + 32 * h, kk = (t & 7) * 4;
+        const bool rv = r0 + r < lim;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + kk + j;
+          v[4 * h + j] = ld_f32(rs, (rv && k < K) ? 4u * static_cast<uint32_t>((r0 + r) * ld + k) : kOOB);
+        }
       }
     } else {
-      const int k = t >> 3, c = (t & 7) * 4;
+      const int k = t >> 3, c = (t & 7) * V;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < V; ++j) {
         const bool ok = r0 + c + j < lim && k0 + k < K;
         v[j] = ld_f32(rs, ok ? 4u * static_cast<uint32_t>((k0 + k) * ld + r0 + c + j) : kOOB);
       }
@@ -78,22 +87,78 @@ struct Stager {
   __device__ void store(float* lds) const {
     const int t = threadIdx.x;
     if (kind == 2) {
-      const int k = t >> 3, c = (t & 7) * 4;
+      const int k = t >> 3, c = (t & 7) * V;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) lds[(c + j) * LDB + k] = v[j];
+      for (int j = 0; j < V; ++j) lds[(c + j) * LDB + k] = v[j];
     } else {
-      const int r = t >> 3, kk = (t & 7) * 4;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) lds[r * LDB + kk + j] = v[j];
+      for (int h = 0; h < V / 4; ++h) {
+        const int r = (t >> 3) + 32 * h, kk = (t & 7) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[r * LDB + kk + j] = v[4 * h + j];
+      }
     }
   }
 };
 
+// FP32 MFMA per slice, summed into FP64: TILE 32 = four waves of 16 x 16 (v_mfma_f32_16x16x4f32, four
+// chains); TILE 64 = four waves of 32 x 32 (v_mfma_f32_32x32x2f32, two chains).
+template <int TILE>
+struct Acc;
+template <>
+struct Acc<32> {
+  static constexpr int R = 4;
+  __device__ static void slice(const float* Pl, const float* Ql, double (&accd)[R]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
+    const float* Pp = Pl + ((wave & 1) * 16 + (lane & 15)) * LDB + kl;
+    const float* Qp = Ql + ((wave >> 1) * 16 + (lane & 15)) * LDB + kl;
+    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, c2 = {0, 0, 0, 0}, c3 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < BK; k += 16) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k], Qp[k], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 4], Qp[k + 4], c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 8], Qp[k + 8], c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 12], Qp[k + 12], c3, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      accd[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
+                 (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
+  }
+  // tile-local output coordinates of register r (lane l receives C[4 (l/16) + r][l%16])
+  __device__ static int row(int r) { return ((threadIdx.x >> 6) & 1) * 16 + 4 * ((threadIdx.x & 63) >> 4) + r; }
+  __device__ static int col() { return (threadIdx.x >> 7) * 16 + (threadIdx.x & 15); }
+};
+template <>
+struct Acc<64> {
+  static constexpr int R = 16;
+  __device__ static void slice(const float* Pl, const float* Ql, double (&accd)[R]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 5;
+    // lane l supplies P[l%32][k + l/32] and Q[l%32][k + l/32]
+    const float* Pp = Pl + ((wave & 1) * 32 + (lane & 31)) * LDB + kl;
+    const float* Qp = Ql + ((wave >> 1) * 32 + (lane & 31)) * LDB + kl;
+    f32x16 c0, c1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c0[r] = c1[r] = 0.f;
+#pragma unroll
+    for (int k = 0; k < BK; k += 4) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k], Qp[k], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k + 2], Qp[k + 2], c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) accd[r] += static_cast<double>(c0[r]) + static_cast<double>(c1[r]);
+  }
+  // lane l receives C[8 (r/4) + 4 (l/32) + r%4][l%32]
+  __device__ static int row(int r) {
+    return ((threadIdx.x >> 6) & 1) * 32 + 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3);
+  }
+  __device__ static int col() { return (threadIdx.x >> 7) * 32 + (threadIdx.x & 31); }
+};
+
 // accd += P . Q^T over K (multiple of BK after zero fill), P and Q described by their stagers.
-__device__ __forceinline__ void tile_contract(Stager& P, Stager& Q, int K, float* lds, double (&accd)[4]) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int kl = lane >> 4;
+template <int TILE>
+__device__ __forceinline__ void tile_contract(Stager<TILE>& P, Stager<TILE>& Q, int K, float* lds,
+                                              double (&accd)[Acc<TILE>::R]) {
   float* Pl[2] = {lds, lds + 2 * TILE * LDB};
   float* Ql[2] = {lds + TILE * LDB, lds + 3 * TILE * LDB};
   const int nsl = (K + BK - 1) / BK;
@@ -108,20 +173,7 @@ __device__ __forceinline__ void tile_contract(Stager& P, Stager& Q, int K, float
   }
   lds_barrier();
   for (int s = 0; s < nsl; ++s) {
-    const float* Pp = Pl[s & 1] + ((wave & 1) * 16 + (lane & 15)) * LDB + kl;
-    const float* Qp = Ql[s & 1] + ((wave >> 1) * 16 + (lane & 15)) * LDB + kl;
-    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, c2 = {0, 0, 0, 0}, c3 = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < BK; k += 16) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k], Qp[k], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 4], Qp[k + 4], c1, 0, 0, 0);
-      c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 8], Qp[k + 8], c2, 0, 0, 0);
-      c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 12], Qp[k + 12], c3, 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      accd[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
-                 (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
+    Acc<TILE>::slice(Pl[s & 1], Ql[s & 1], accd);
     if (s + 1 < nsl) {
       P.store(Pl[(s + 1) & 1]);
       Q.store(Ql[(s + 1) & 1]);
@@ -134,51 +186,52 @@ __device__ __forceinline__ void tile_contract(Stager& P, Stager& Q, int K, float
   }
 }
 
-__device__ __forceinline__ int tile_row(int r) { return ((threadIdx.x >> 6) & 1) * 16 + 4 * ((threadIdx.x & 63) >> 4) + r; }
-__device__ __forceinline__ int tile_col() { return (threadIdx.x >> 7) * 16 + (threadIdx.x & 15); }
-
+template <int TILE>
 __device__ void run_task(const BatchSolve& S, const BatchTask& T, float* lds) {
-  double accd[4] = {0, 0, 0, 0};
+  constexpr int R = Acc<TILE>::R;
+  double accd[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) accd[r] = 0.0;
   const int nx = S.nx, ny = S.ny;
   float* Y;
   int rows, cols;
   double scale;
   if (T.kind == 0) {
     // u_x[i][j] += sG * sum_k Gx[i][k] p[k][j]
-    Stager P{0, S.Gx, make_rsrc(S.Gx, 0u), S.ldgx, T.i0, nx - 1, nx};
-    Stager Q{2, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.j0, ny, nx};
-    tile_contract(P, Q, nx, lds, accd);
+    Stager<TILE> P{0, S.Gx, make_rsrc(S.Gx, 0u), S.ldgx, T.i0, nx - 1, nx};
+    Stager<TILE> Q{2, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.j0, ny, nx};
+    tile_contract<TILE>(P, Q, nx, lds, accd);
     Y = S.ux; rows = nx - 1; cols = ny; scale = S.sG;
   } else if (T.kind == 1) {
     // u_y[i][j] += sG_y * sum_k p[i][k] Gy[j][k]
-    Stager P{1, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.i0, nx, ny};
-    Stager Q{0, S.Gy, make_rsrc(S.Gy, 0u), S.ldgy, T.j0, ny - 1, ny};
-    tile_contract(P, Q, ny, lds, accd);
+    Stager<TILE> P{1, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.i0, nx, ny};
+    Stager<TILE> Q{0, S.Gy, make_rsrc(S.Gy, 0u), S.ldgy, T.j0, ny - 1, ny};
+    tile_contract<TILE>(P, Q, ny, lds, accd);
     Y = S.uy; rows = nx; cols = ny - 1; scale = S.sG;
   } else {
     // p[i][j] += sD * (sum_k Dx[i][k] u_x[k][j] + sum_k u_y[i][k] Dy[j][k])
-    Stager P{0, S.Dx, make_rsrc(S.Dx, 0u), S.lddx, T.i0, nx, nx - 1};
-    Stager Q{2, nullptr, make_rsrc(S.ux, 4u * (nx - 1) * ny), ny, T.j0, ny, nx - 1};
-    tile_contract(P, Q, nx - 1, lds, accd);
-    Stager P2{1, nullptr, make_rsrc(S.uy, 4u * nx * (ny - 1)), ny - 1, T.i0, nx, ny - 1};
-    Stager Q2{0, S.Dy, make_rsrc(S.Dy, 0u), S.lddy, T.j0, ny, ny - 1};
-    tile_contract(P2, Q2, ny - 1, lds, accd);
+    Stager<TILE> P{0, S.Dx, make_rsrc(S.Dx, 0u), S.lddx, T.i0, nx, nx - 1};
+    Stager<TILE> Q{2, nullptr, make_rsrc(S.ux, 4u * (nx - 1) * ny), ny, T.j0, ny, nx - 1};
+    tile_contract<TILE>(P, Q, nx - 1, lds, accd);
+    Stager<TILE> P2{1, nullptr, make_rsrc(S.uy, 4u * nx * (ny - 1)), ny - 1, T.i0, nx, ny - 1};
+    Stager<TILE> Q2{0, S.Dy, make_rsrc(S.Dy, 0u), S.lddy, T.j0, ny, ny - 1};
+    tile_contract<TILE>(P2, Q2, ny - 1, lds, accd);
     Y = S.p; rows = nx; cols = ny; scale = S.sD;
   }
-  const int j = T.j0 + tile_col();
+  const int j = T.j0 + Acc<TILE>::col();
   // pressure tiles of a heterogeneous solve take c0(x)^2 pointwise
   const float* c2 = T.kind == 2 ? S.c2 : nullptr;
-  float yv[4], cv[4];
+  float yv[R], cv[R];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = T.i0 + tile_row(r);
+  for (int r = 0; r < R; ++r) {
+    const int i = T.i0 + Acc<TILE>::row(r);
     const bool ok = i < rows && j < cols;
     yv[r] = ok ? Y[static_cast<int64_t>(i) * cols + j] : 0.f;
     cv[r] = (ok && c2) ? c2[static_cast<int64_t>(i) * cols + j] : 1.f;
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = T.i0 + tile_row(r);
+  for (int r = 0; r < R; ++r) {
+    const int i = T.i0 + Acc<TILE>::row(r);
     if (i < rows && j < cols)
       Y[static_cast<int64_t>(i) * cols + j] =
           static_cast<float>(static_cast<double>(yv[r]) + scale * static_cast<double>(cv[r]) * accd[r]);
@@ -205,6 +258,7 @@ __device__ void grid_barrier(unsigned* arrivals, unsigned* timeout) {
   __syncthreads();
 }
 
+template <int TILE>
 __global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
   __shared__ float lds[4 * TILE * LDB];
   for (int64_t s = 0; s < a.steps; ++s) {
@@ -220,7 +274,7 @@ __global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
         lds_barrier();
         if (t >= n) break;
         const BatchTask T = tasks[t];
-        run_task(a.solves[T.solve], T, lds);
+        run_task<TILE>(a.solves[T.solve], T, lds);
       }
       grid_barrier(a.counters + 4 * s + 2 + phase, a.timeout);
     }
@@ -235,22 +289,25 @@ __global__ void zero_u32(unsigned* p, int64_t n) {
 
 }  // namespace
 
-int batch2d_max_blocks(int* out) {
+int batch2d_max_blocks(int tile, int* out) {
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch2d_kernel, NT, 0) != hipSuccess) return -1;
+  const hipError_t e = tile == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch2d_kernel<64>, NT, 0)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch2d_kernel<32>, NT, 0);
+  if (e != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
   *out = per_cu * cus;
   return 0;
 }
 
-hipError_t launch_batch2d(const BatchArgs& a, int blocks, hipStream_t s) {
+hipError_t launch_batch2d(const BatchArgs& a, int tile, int blocks, hipStream_t s) {
   // fresh tickets and barrier counters for every launch (a fill kernel, not a memset, so the pair of
   // launches can be captured in a graph)
   hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, 4 * a.steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batch2d_kernel, dim3(blocks), dim3(NT), 0, s, a);
+  if (tile == 64) hipLaunchKernelGGL(batch2d_kernel<64>, dim3(blocks), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL(batch2d_kernel<32>, dim3(blocks), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

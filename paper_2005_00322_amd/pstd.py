@@ -320,14 +320,14 @@ class Batch:
         """Wait for the batch's work; raises if a grid barrier of the persistent launch timed out."""
         check(load().pstd_batch_synchronize(self._h), "pstd_batch_synchronize")
 
-    def set_config(self, blocks=0, order=0):
-        check(load().pstd_batch_set_config(self._h, int(blocks), int(order)), "pstd_batch_set_config")
+    def set_config(self, blocks=0, order=0, tile=32):
+        check(load().pstd_batch_set_config(self._h, int(blocks), int(order), int(tile)), "pstd_batch_set_config")
 
     def autotune(self, trial_steps=5, cache_path=None):
-        cfg = (C.c_int32 * 3)()
+        cfg = (C.c_int32 * 4)()
         check(load().pstd_batch_autotune(self._h, int(trial_steps),
                                          cache_path.encode() if cache_path else None, cfg), "pstd_batch_autotune")
-        return {"blocks": cfg[0], "order": cfg[1], "from_cache": bool(cfg[2])}
+        return {"blocks": cfg[0], "order": cfg[1], "tile": cfg[2], "from_cache": bool(cfg[3])}
 
     def close(self):
         if getattr(self, "_h", None):

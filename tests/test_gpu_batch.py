@@ -52,13 +52,19 @@ def test_batch_matches_oracle(seed, count, lo, hi):
             assert rel_l2(u[a], uo[a]) < TOL["fp32"]
 
 
-@pytest.mark.parametrize("config", [{"blocks": 0, "order": 1}, {"blocks": 256, "order": 0}])
+@pytest.mark.parametrize("config", [{"blocks": 0, "order": 1}, {"blocks": 256, "order": 0},
+                                    {"blocks": 0, "order": 0, "tile": 64}, {"blocks": 300, "order": 1, "tile": 64}])
 def test_batch_configs_agree(config):
     solves, p0s = _random_solves(4, 6, 20, 100)
-    a, _ = _run(solves, p0s, 20)
+    a, _ = _run(solves, p0s, 20, config={"tile": config.get("tile", 32)})
     b, _ = _run(solves, p0s, 20, config=config)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)      # same tiles, same arithmetic: order and block count do not matter
+    if config.get("tile", 32) != 32:
+        # another tile edge sums in another order: equal to rounding
+        c, _ = _run(solves, p0s, 20)
+        for x, y in zip(b, c):
+            assert np.max(np.abs(x - y)) <= 1e-6 * np.max(np.abs(y))
 
 
 def test_batch_chunks_bitwise():
@@ -107,7 +113,7 @@ def test_batch_autotune_cache(tmp_path):
         cfg2 = b.autotune(trial_steps=3, cache_path=cache)
         assert cfg2["from_cache"] and cfg2["blocks"] == cfg["blocks"] and cfg2["order"] == cfg["order"]
     a, _ = _run(solves, p0s, 15)
-    c, _ = _run(solves, p0s, 15, config={"blocks": cfg["blocks"], "order": cfg["order"]})
+    c, _ = _run(solves, p0s, 15, config={"blocks": cfg["blocks"], "order": cfg["order"], "tile": cfg["tile"]})
     for x, y in zip(a, c):
         assert np.array_equal(x, y)
 
