@@ -1,274 +1,345 @@
 // Two fused phase kernels per step for 2D FP32 plans with at most 512 nodes per axis.
 //
 // Eq. (dtt_pstd_solution) in its 2D form (§4.3) splits into a velocity phase and a pressure phase:
-//   velocity  u_x += G~x p   and   u_y += p G~y^T           (one launch, every u_x and u_y tile)
-//   pressure  p += c2 .* (D~x u_x + u_y D~y^T)               (one launch; each p tile takes both axes'
-//                                                             terms, so p is read and written once)
-// A small box is bound by latency, so each block computes one 32 x 32 output tile from full-K operand
-// slices staged into LDS in one pass (no K loop of dependent loads).  The kernel boundary between the
-// phases is the grid-wide dependency of the scheme; graph replay keeps the launch gaps short.
-// Each wave computes one 16 x 16 quarter with four independent MFMA accumulator chains whose sums
-// are flushed into FP64 registers every 16 k; the update is formed in FP64 and rounded once.
+//   velocity  u_x += G~x p   and   u_y += p G~y^T           (one launch)
+//   pressure  p += c2 .* (D~x u_x + u_y D~y^T)               (one launch)
+// Each block owns one 16 x 16 output tile of the phase: in the velocity phase the u_x and the u_y tile at
+// the same (i, j) position, in the pressure phase one p tile with both axes' terms.  Both phases are thus
+// two contractions of the same shape,
+//   contraction 0:  out0[i][j] = sum_k A0[i][k] X0[k][j]   (operator rows, columns of a field)
+//   contraction 1:  out1[i][j] = sum_k X1[i][k] A1[j][k]   (rows of a field, operator rows)
+// and the four waves of a block split them as (contraction, half of k).  A box of a few hundred nodes a
+// side is bound by latency, not by bandwidth or MFMA rate, so a block issues every load it needs (four
+// full-k operand slices and the old output values of its epilogue) before the first LDS store: one
+// round trip to memory per phase.  Small tiles give enough blocks to spread the MFMA work over the
+// whole GPU (256 blocks for 256 x 256).  The kernel boundary between the phases is the grid-wide
+// dependency of the scheme; graph replay keeps the launch gaps short.
 //
-// MFMA v_mfma_f32_16x16x4: lane l supplies P[l%16][l/16] and Q[l%16][l/16] (both staged as [row][k])
-// and receives C[4*(l/16)+r][l%16] in register r.  The operand whose rows run along the output's
-// unit-stride axis goes to the Q port, so lanes 0..15 write 16 consecutive floats.
+// MFMA v_mfma_f32_16x16x4: lane l supplies P[l%16][kslot l/16] and Q[l%16][kslot l/16] and receives
+// C[4*(l/16)+r][l%16] in register r.  A lane reads four consecutive k of each operand with one LDS
+// read and feeds component e to the e-th of four independent MFMAs, so MFMA e contracts the k set
+// {k0 + 4s + e}; the four together cover k0 .. k0+15 once.  FP32 chain sums are flushed into FP64
+// registers every 32 k, the halves and contractions are added in FP64, and the update is rounded once.
 #include "common.h"
 
 namespace pstd {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-constexpr int TILE = 32;        // output tile edge
-constexpr int KMAX = 512;       // largest contracted extent handled
-constexpr int LDT = KMAX + 1;   // LDS row stride (floats), odd: conflict-free reads down a column
-constexpr int NT = 256;         // 4 waves
+constexpr int T = 16;                   // output tile edge
+constexpr int NT = 256;                 // four waves
+constexpr uint32_t kOOB = 0x80000000u;  // buffer offset past every range: the load returns zero
 
 struct Phase2DArgs {
-  const float* Gx; int ldgx;    // (nx-1) x nx, zero padded to row stride ldgx
-  const float* Gy; int ldgy;    // (ny-1) x ny
-  const float* Dx; int lddx;    // nx x (nx-1)
-  const float* Dy; int lddy;    // ny x (ny-1)
-  float* p;                     // nx x ny
-  float* ux;                    // (nx-1) x ny
-  float* uy;                    // nx x (ny-1)
-  const float* c2;              // nx x ny or null
+  const float* Gx; int ldgx, mgx;   // (nx-1) x nx operator, row stride ldgx, mgx rows allocated (zero padded)
+  const float* Gy; int ldgy, mgy;   // (ny-1) x ny
+  const float* Dx; int lddx, mdx;   // nx x (nx-1)
+  const float* Dy; int lddy, mdy;   // ny x (ny-1)
+  float* p;                         // nx x ny
+  float* ux;                        // (nx-1) x ny
+  float* uy;                        // nx x (ny-1)
+  const float* c2;                  // nx x ny or null
   int nx, ny;
 };
 
-// Rows [r0, r0+TILE) x k [0, Kpad) of a row-major matrix (row stride ld) into LDS as [row][k]: wave w
-// takes rows w, w+4, ...; lanes stride along k.  Reads only rows < `rows` and k < K; the rest is zero.
-// Loads are issued in batches of four rows before their LDS stores, so a batch costs one round trip.
-__device__ __forceinline__ void stage_rows(float* dst, const float* __restrict__ src, int64_t ld, int r0, int rows,
-                                           int K, int Kpad) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int RPW = TILE / (NT / 64);   // rows per wave
-  constexpr int KCH = KMAX / 64;          // k chunks per row
+__device__ __forceinline__ rsrc_t make_rsrc(const void* ptr, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(ptr), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+__device__ __forceinline__ f32x4 ld_f32x4(rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+}
+
+__host__ __device__ __forceinline__ int pad64(int k) { return (k + 63) & ~63; }
+
+// One phase's operands in registers between the loads and the LDS stores.
+//   op0, op1: operator rows r0 .. r0+15, k < Kpad, thread t holds k = 4 (t%16) + 64 j of row t/16
+//   col0:     X0[k][c0 + c], thread t holds c = t%16, k = t/16 + 16 u
+//   row1:     X1[r0 + r][k], thread t holds r = t/64 + 4 q, k = t%64 + 64 j
+template <int KMAX>
+struct Slices {
+  static constexpr int KC = KMAX / 64;
+  f32x4 op0[KC], op1[KC];
+  float col0[KMAX / 16];
+  float row1[4 * KC];
+};
+
+template <int KMAX>
+__device__ __forceinline__ void load_op(f32x4 (&v)[KMAX / 64], rsrc_t rs, int ld, int r0, int Kpad) {
+  const int t = threadIdx.x;
+  const uint32_t base = 4u * static_cast<uint32_t>((r0 + (t >> 4)) * ld + 4 * (t & 15));
 #pragma unroll
-  for (int g = 0; g < RPW; g += 4) {
-    float v[4][KCH];
+  for (int j = 0; j < KMAX / 64; ++j)
+    if (64 * j < Kpad) v[j] = ld_f32x4(rs, base + 256u * j);
+}
+
+template <int KMAX>
+__device__ __forceinline__ void store_op(float* dst, const f32x4 (&v)[KMAX / 64], int Kpad) {
+  constexpr int LD = KMAX + 4;
+  const int t = threadIdx.x;
+  float* d = dst + (t >> 4) * LD + 4 * (t & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wave + (NT / 64) * (g + i);
-      const bool rv = r0 + r < rows;
-      const float* s = src + static_cast<int64_t>(rv ? r0 + r : 0) * ld;
+  for (int j = 0; j < KMAX / 64; ++j)
+    if (64 * j < Kpad) *reinterpret_cast<f32x4*>(d + 64 * j) = v[j];
+}
+
+// columns c0 .. c0+15 of X (row stride ld; valid c < cols, k < K)
+template <int KMAX>
+__device__ __forceinline__ void load_cols(float (&v)[KMAX / 16], rsrc_t rs, int ld, int c0, int cols, int K, int Kpad) {
+  const int t = threadIdx.x;
+  const int c = c0 + (t & 15);
 #pragma unroll
-      for (int j = 0; j < KCH; ++j) {
-        const int k = lane + 64 * j;
-        v[i][j] = (rv && k < K) ? s[k] : 0.f;
-      }
-    }
+  for (int u = 0; u < KMAX / 16; ++u) {
+    const int k = (t >> 4) + 16 * u;
+    if (16 * u < Kpad) v[u] = ld_f32(rs, (c < cols && k < K) ? 4u * static_cast<uint32_t>(k * ld + c) : kOOB);
+  }
+}
+
+template <int KMAX>
+__device__ __forceinline__ void store_cols(float* dst, const float (&v)[KMAX / 16], int Kpad) {
+  constexpr int LD = KMAX + 4;
+  const int t = threadIdx.x;
+  float* d = dst + (t & 15) * LD + (t >> 4);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wave + (NT / 64) * (g + i);
+  for (int u = 0; u < KMAX / 16; ++u)
+    if (16 * u < Kpad) d[16 * u] = v[u];
+}
+
+// rows r0 .. r0+15 of X (row stride ld; valid r < rows, k < K)
+template <int KMAX>
+__device__ __forceinline__ void load_rows(float (&v)[4 * (KMAX / 64)], rsrc_t rs, int ld, int r0, int rows, int K,
+                                          int Kpad) {
+  const int t = threadIdx.x;
 #pragma unroll
-      for (int j = 0; j < KCH; ++j) {
-        const int k = lane + 64 * j;
-        if (k < Kpad) dst[r * LDT + k] = v[i][j];
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + (t >> 6) + 4 * q;
+#pragma unroll
+    for (int j = 0; j < KMAX / 64; ++j) {
+      const int k = (t & 63) + 64 * j;
+      if (64 * j < Kpad)
+        v[q * (KMAX / 64) + j] = ld_f32(rs, (r < rows && k < K) ? 4u * static_cast<uint32_t>(r * ld + k) : kOOB);
     }
   }
 }
 
-// Columns [c0, c0+TILE) x k [0, Kpad) of a row-major matrix X[k][c] (row stride ld) transposed into LDS
-// as [c][k]: each wave instruction reads two 32-float row segments.  Reads only c < `cols`, k < K.
-// Loads are issued 16 at a time before their LDS stores.
-__device__ __forceinline__ void stage_cols(float* dst, const float* __restrict__ src, int64_t ld, int c0, int cols,
-                                           int K, int Kpad) {
-  const int c = threadIdx.x & 31;
-  const int kb = threadIdx.x >> 5;
-  const bool cv = c0 + c < cols;
-  constexpr int KS = NT / 32;             // k stride between a thread's elements
-  for (int k0 = 0; k0 < Kpad; k0 += 16 * KS) {
-    float v[16];
+template <int KMAX>
+__device__ __forceinline__ void store_rows(float* dst, const float (&v)[4 * (KMAX / 64)], int Kpad) {
+  constexpr int LD = KMAX + 4;
+  const int t = threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int k = k0 + kb + KS * u;
-      v[u] = (cv && k < K) ? src[static_cast<int64_t>(k) * ld + c0 + c] : 0.f;
-    }
+  for (int q = 0; q < 4; ++q) {
+    float* d = dst + ((t >> 6) + 4 * q) * LD + (t & 63);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int k = k0 + kb + KS * u;
-      if (k < Kpad) dst[c * LDT + k] = v[u];
-    }
+    for (int j = 0; j < KMAX / 64; ++j)
+      if (64 * j < Kpad) d[64 * j] = v[q * (KMAX / 64) + j];
   }
 }
 
-// accd (this wave's 16 x 16 quarter) += P[rows][0..K) . Q[cols][0..K)^T; K a multiple of 16, zero padded.
-__device__ __forceinline__ void mma_tile(const float* P, const float* Q, int K, double (&accd)[4]) {
+// acc (this lane's four outputs of the 16 x 16 tile) += sum over k in [kb, ke) of P[row][k] Q[col][k];
+// kb and ke multiples of 32.
+template <int KMAX>
+__device__ __forceinline__ void mma_range(const float* P, const float* Q, int kb, int ke, double (&acc)[4]) {
+  constexpr int LD = KMAX + 4;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int kl = lane >> 4;
-  const float* Pp = P + ((wave & 1) * 16 + (lane & 15)) * LDT + kl;
-  const float* Qp = Q + ((wave >> 1) * 16 + (lane & 15)) * LDT + kl;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, c2 = {0, 0, 0, 0}, c3 = {0, 0, 0, 0};
-    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k0], Qp[k0], c0, 0, 0, 0);
-    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k0 + 4], Qp[k0 + 4], c1, 0, 0, 0);
-    c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k0 + 8], Qp[k0 + 8], c2, 0, 0, 0);
-    c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k0 + 12], Qp[k0 + 12], c3, 0, 0, 0);
+  const float* Pp = P + (lane & 15) * LD + 4 * (lane >> 4);
+  const float* Qp = Q + (lane & 15) * LD + 4 * (lane >> 4);
+  for (int k = kb; k < ke; k += 32) {
+    const f32x4 a0 = *reinterpret_cast<const f32x4*>(Pp + k);
+    const f32x4 b0 = *reinterpret_cast<const f32x4*>(Qp + k);
+    const f32x4 a1 = *reinterpret_cast<const f32x4*>(Pp + k + 16);
+    const f32x4 b1 = *reinterpret_cast<const f32x4*>(Qp + k + 16);
+    const f32x4 z = {0, 0, 0, 0};
+    f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b0[0], z, 0, 0, 0);
+    f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b0[1], z, 0, 0, 0);
+    f32x4 c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b0[2], z, 0, 0, 0);
+    f32x4 c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b0[3], z, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b1[0], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b1[1], c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b1[2], c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b1[3], c3, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      accd[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
-                 (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
+      acc[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
+                (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
   }
 }
 
-// Tile-local output coordinates of this lane's register r.
-__device__ __forceinline__ int tile_row(int r) { return ((threadIdx.x >> 6) & 1) * 16 + 4 * ((threadIdx.x & 63) >> 4) + r; }
-__device__ __forceinline__ int tile_col() { return (threadIdx.x >> 7) * 16 + (threadIdx.x & 15); }
+template <int KMAX>
+constexpr size_t lds_bytes() {
+  return sizeof(float) * 4 * T * (KMAX + 4) + sizeof(double) * 4 * 4 * 64;
+}
 
-__device__ __forceinline__ int pad16(int k) { return (k + 15) & ~15; }
-
-__global__ __launch_bounds__(NT) void velocity2d_kernel(Phase2DArgs a) {
+// PH 0: velocity phase, PH 1: pressure phase.
+template <int KMAX, int PH>
+__global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
+  constexpr int SL = T * (KMAX + 4);
   extern __shared__ float lds[];
-  float* P = lds;
-  float* Q = lds + TILE * LDT;
+  double* red = reinterpret_cast<double*>(lds + 4 * SL);   // [wave][reg][lane]
   const int nx = a.nx, ny = a.ny;
-  const int tux_n = (ny + TILE - 1) / TILE;
-  const int n_ux = ((nx - 1 + TILE - 1) / TILE) * tux_n;
-  const int t = blockIdx.x;
-  double accd[4] = {0, 0, 0, 0};
-  int i0, j0, rows, cols;
-  int64_t ldy;
-  float* Y;
-  if (t < n_ux) {
-    // u_x[i][j] += sum_k Gx[i][k] p[k][j]: P = Gx rows i, Q = p columns j
-    i0 = (t / tux_n) * TILE;
-    j0 = (t % tux_n) * TILE;
-    stage_rows(P, a.Gx, a.ldgx, i0, nx - 1, nx, pad16(nx));
-    stage_cols(Q, a.p, ny, j0, ny, nx, pad16(nx));
-    lds_barrier();
-    mma_tile(P, Q, pad16(nx), accd);
-    Y = a.ux;
-    ldy = ny;
-    rows = nx - 1;
-    cols = ny;
+  const int tiles_y = (ny + T - 1) / T;
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);   // consecutive tiles on one XCD
+  const int i0 = (b / tiles_y) * T, j0 = (b % tiles_y) * T;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+
+  // the two contractions of this phase
+  const float* A0 = PH == 0 ? a.Gx : a.Dx;
+  const int lda0 = PH == 0 ? a.ldgx : a.lddx, ma0 = PH == 0 ? a.mgx : a.mdx;
+  const float* A1 = PH == 0 ? a.Gy : a.Dy;
+  const int lda1 = PH == 0 ? a.ldgy : a.lddy, ma1 = PH == 0 ? a.mgy : a.mdy;
+  const float* X0 = PH == 0 ? a.p : a.ux;                   // ld ny, K0 rows
+  const float* X1 = PH == 0 ? a.p : a.uy;                   // nx rows of K1
+  const int K0 = PH == 0 ? nx : nx - 1, K1 = PH == 0 ? ny : ny - 1;
+  const int ld1 = PH == 0 ? ny : ny - 1;
+  const int Kp0 = pad64(K0), Kp1 = pad64(K1);
+
+  const rsrc_t rA0 = make_rsrc(A0, 4u * static_cast<uint32_t>(ma0 * lda0));
+  const rsrc_t rA1 = make_rsrc(A1, 4u * static_cast<uint32_t>(ma1 * lda1));
+  const rsrc_t rX0 = make_rsrc(X0, 4u * static_cast<uint32_t>(K0 * ny));
+  const rsrc_t rX1 = make_rsrc(X1, 4u * static_cast<uint32_t>(nx * ld1));
+
+  // old output values of this wave's share of the epilogue, loaded with the operands
+  //   velocity: wave w finishes registers 2 (w%2), 2 (w%2) + 1 of the u_x (w < 2) or u_y (w >= 2) tile
+  //   pressure: wave w finishes register w of the p tile
+  float old[2];
+  float cfac[2] = {1.f, 1.f};
+  const int oj = j0 + (lane & 15);
+  if (PH == 0) {
+    float* Y = wave < 2 ? a.ux : a.uy;
+    const int rows = wave < 2 ? nx - 1 : nx, cols = wave < 2 ? ny : ny - 1;
+    const rsrc_t rY = make_rsrc(Y, 4u * static_cast<uint32_t>(rows * cols));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int oi = i0 + 4 * (lane >> 4) + 2 * (wave & 1) + h;
+      old[h] = ld_f32(rY, (oi < rows && oj < cols) ? 4u * static_cast<uint32_t>(oi * cols + oj) : kOOB);
+    }
   } else {
-    // u_y[i][j] += sum_k p[i][k] Gy[j][k]: P = p rows i, Q = Gy rows j
-    const int tuy_n = (ny - 1 + TILE - 1) / TILE;
-    const int tt = t - n_ux;
-    i0 = (tt / tuy_n) * TILE;
-    j0 = (tt % tuy_n) * TILE;
-    stage_rows(P, a.p, ny, i0, nx, ny, pad16(ny));
-    stage_rows(Q, a.Gy, a.ldgy, j0, ny - 1, ny, pad16(ny));
-    lds_barrier();
-    mma_tile(P, Q, pad16(ny), accd);
-    Y = a.uy;
-    ldy = ny - 1;
-    rows = nx;
-    cols = ny - 1;
+    const rsrc_t rP = make_rsrc(a.p, 4u * static_cast<uint32_t>(nx * ny));
+    const int oi = i0 + 4 * (lane >> 4) + wave;
+    const bool ok = oi < nx && oj < ny;
+    old[0] = ld_f32(rP, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
+    if (a.c2) {
+      const rsrc_t rC = make_rsrc(a.c2, 4u * static_cast<uint32_t>(nx * ny));
+      cfac[0] = ld_f32(rC, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
+    }
   }
-  // read all four outputs, then write them (one round trip)
-  const int j = j0 + tile_col();
-  float yv[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tile_row(r);
-    yv[r] = (i < rows && j < cols) ? Y[static_cast<int64_t>(i) * ldy + j] : 0.f;
+
+  Slices<KMAX> s;
+  load_op<KMAX>(s.op0, rA0, lda0, i0, Kp0);
+  load_cols<KMAX>(s.col0, rX0, ny, j0, ny, K0, Kp0);
+  load_rows<KMAX>(s.row1, rX1, ld1, i0, nx, K1, Kp1);
+  load_op<KMAX>(s.op1, rA1, lda1, j0, Kp1);
+  float* S0 = lds;            // A0 rows       [i][k]
+  float* S1 = lds + SL;       // X0 columns    [j][k]
+  float* S2 = lds + 2 * SL;   // X1 rows       [i][k]
+  float* S3 = lds + 3 * SL;   // A1 rows       [j][k]
+  store_op<KMAX>(S0, s.op0, Kp0);
+  store_cols<KMAX>(S1, s.col0, Kp0);
+  store_rows<KMAX>(S2, s.row1, Kp1);
+  store_op<KMAX>(S3, s.op1, Kp1);
+  __syncthreads();
+
+  double acc[4] = {0, 0, 0, 0};
+  {
+    const int c = wave >> 1, h = wave & 1;
+    const int Kp = c == 0 ? Kp0 : Kp1;
+    const int half = Kp >> 1;   // a multiple of 32
+    mma_range<KMAX>(c == 0 ? S0 : S2, c == 0 ? S1 : S3, h * half, (h + 1) * half, acc);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tile_row(r);
-    if (i < rows && j < cols)
-      Y[static_cast<int64_t>(i) * ldy + j] = static_cast<float>(static_cast<double>(yv[r]) + accd[r]);
+  for (int r = 0; r < 4; ++r) red[(wave * 4 + r) * 64 + lane] = acc[r];
+  __syncthreads();
+
+  if (PH == 0) {
+    const int c = wave >> 1;
+    float* Y = c == 0 ? a.ux : a.uy;
+    const int rows = c == 0 ? nx - 1 : nx, cols = c == 0 ? ny : ny - 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = 2 * (wave & 1) + h;
+      const double v = red[((2 * c) * 4 + r) * 64 + lane] + red[((2 * c + 1) * 4 + r) * 64 + lane];
+      const int oi = i0 + 4 * (lane >> 4) + r;
+      if (oi < rows && oj < cols)
+        Y[static_cast<int64_t>(oi) * cols + oj] = static_cast<float>(static_cast<double>(old[h]) + v);
+    }
+  } else {
+    const int r = wave;
+    const double v = (red[(0 * 4 + r) * 64 + lane] + red[(1 * 4 + r) * 64 + lane]) +
+                     (red[(2 * 4 + r) * 64 + lane] + red[(3 * 4 + r) * 64 + lane]);
+    const int oi = i0 + 4 * (lane >> 4) + r;
+    if (oi < nx && oj < ny)
+      a.p[static_cast<int64_t>(oi) * ny + oj] =
+          static_cast<float>(static_cast<double>(old[0]) + v * static_cast<double>(cfac[0]));
   }
 }
 
-__global__ __launch_bounds__(NT) void pressure2d_kernel(Phase2DArgs a) {
-  extern __shared__ float lds[];
-  float* P = lds;
-  float* Q = lds + TILE * LDT;
-  const int nx = a.nx, ny = a.ny;
-  const int tp_n = (ny + TILE - 1) / TILE;
-  const int i0 = (blockIdx.x / tp_n) * TILE, j0 = (blockIdx.x % tp_n) * TILE;
-  double accd[4] = {0, 0, 0, 0};
-  // p[i][j] += sum_k Dx[i][k] u_x[k][j]
-  stage_rows(P, a.Dx, a.lddx, i0, nx, nx - 1, pad16(nx - 1));
-  stage_cols(Q, a.ux, ny, j0, ny, nx - 1, pad16(nx - 1));
-  lds_barrier();
-  mma_tile(P, Q, pad16(nx - 1), accd);
-  lds_barrier();
-  // + sum_k u_y[i][k] Dy[j][k]
-  stage_rows(P, a.uy, ny - 1, i0, nx, ny - 1, pad16(ny - 1));
-  stage_rows(Q, a.Dy, a.lddy, j0, ny, ny - 1, pad16(ny - 1));
-  lds_barrier();
-  mma_tile(P, Q, pad16(ny - 1), accd);
-  // read all four outputs (and map factors), then write them (one round trip)
-  const int j = j0 + tile_col();
-  float pv[4], cv[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tile_row(r);
-    const bool ok = i < nx && j < ny;
-    const int64_t idx = static_cast<int64_t>(i) * ny + j;
-    pv[r] = ok ? a.p[idx] : 0.f;
-    cv[r] = (ok && a.c2) ? a.c2[idx] : 1.f;
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tile_row(r);
-    if (i < nx && j < ny)
-      a.p[static_cast<int64_t>(i) * ny + j] =
-          static_cast<float>(static_cast<double>(pv[r]) + accd[r] * static_cast<double>(cv[r]));
-  }
-}
-
-constexpr size_t kLds = sizeof(float) * 2 * TILE * LDT;
-
-hipError_t configure(const void* fn) {
-  static int configured[2] = {-1, -1};
+template <int KMAX, int PH>
+hipError_t configure() {
+  static int configured = -1;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const int slot = fn == reinterpret_cast<const void*>(velocity2d_kernel) ? 0 : 1;
-  if (configured[slot] == dev) return hipSuccess;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLds));
-  if (e == hipSuccess) configured[slot] = dev;
+  if (configured == dev) return hipSuccess;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(phase2d_kernel<KMAX, PH>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes<KMAX>()));
+  if (e == hipSuccess) configured = dev;
   return e;
+}
+
+template <int KMAX>
+hipError_t launch_one(int which, const Phase2DArgs& a, hipStream_t s) {
+  const int nb = ((a.nx + T - 1) / T) * ((a.ny + T - 1) / T);
+  hipError_t e = which == 0 ? configure<KMAX, 0>() : configure<KMAX, 1>();
+  if (e != hipSuccess) return e;
+  if (which == 0) hipLaunchKernelGGL((phase2d_kernel<KMAX, 0>), dim3(nb), dim3(NT), lds_bytes<KMAX>(), s, a);
+  else hipLaunchKernelGGL((phase2d_kernel<KMAX, 1>), dim3(nb), dim3(NT), lds_bytes<KMAX>(), s, a);
+  return hipGetLastError();
+}
+
+Phase2DArgs make_args(const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx, const DevOperator& Dy,
+                      float* p, float* ux, float* uy, const float* c2, int nx, int ny) {
+  return Phase2DArgs{static_cast<const float*>(Gx.data), Gx.Kp, Gx.Mp, static_cast<const float*>(Gy.data), Gy.Kp,
+                     Gy.Mp, static_cast<const float*>(Dx.data), Dx.Kp, Dx.Mp, static_cast<const float*>(Dy.data), Dy.Kp,
+                     Dy.Mp, p, ux, uy, c2, nx, ny};
+}
+
+// The operator slices are read as 16-byte rows of the zero-padded device matrices: every k < pad64(K)
+// lies inside a row, and rows past the allocation read as zero.
+bool operators_fit(const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx, const DevOperator& Dy,
+                   int nx, int ny) {
+  return Gx.Kp >= pad64(nx) && Gy.Kp >= pad64(ny) && Dx.Kp >= pad64(nx - 1) && Dy.Kp >= pad64(ny - 1) &&
+         Gx.Kp % 4 == 0 && Gy.Kp % 4 == 0 && Dx.Kp % 4 == 0 && Dy.Kp % 4 == 0;
 }
 
 }  // namespace
 
-bool phase2d_supported(int nx, int ny) { return nx >= 3 && ny >= 3 && nx <= KMAX && ny <= KMAX; }
+bool phase2d_supported(int nx, int ny) { return nx >= 3 && ny >= 3 && nx <= 512 && ny <= 512; }
 
 hipError_t launch_phase2d_one(int which, const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx,
                               const DevOperator& Dy, float* p, float* ux, float* uy, const float* c2, int nx, int ny,
                               hipStream_t s) {
-  if (!phase2d_supported(nx, ny)) return hipErrorInvalidValue;
-  hipError_t e = configure(reinterpret_cast<const void*>(velocity2d_kernel));
-  if (e == hipSuccess) e = configure(reinterpret_cast<const void*>(pressure2d_kernel));
-  if (e != hipSuccess) return e;
-  Phase2DArgs a{static_cast<const float*>(Gx.data), Gx.Kp, static_cast<const float*>(Gy.data), Gy.Kp,
-                static_cast<const float*>(Dx.data), Dx.Kp, static_cast<const float*>(Dy.data), Dy.Kp,
-                p, ux, uy, c2, nx, ny};
-  const int nA = ((nx - 1 + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE) +
-                 ((nx + TILE - 1) / TILE) * ((ny - 1 + TILE - 1) / TILE);
-  const int nB = ((nx + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE);
-  if (which == 0) hipLaunchKernelGGL(velocity2d_kernel, dim3(nA), dim3(NT), kLds, s, a);
-  else hipLaunchKernelGGL(pressure2d_kernel, dim3(nB), dim3(NT), kLds, s, a);
-  return hipGetLastError();
+  if (!phase2d_supported(nx, ny) || !operators_fit(Gx, Gy, Dx, Dy, nx, ny)) return hipErrorInvalidValue;
+  const Phase2DArgs a = make_args(Gx, Gy, Dx, Dy, p, ux, uy, c2, nx, ny);
+  return (nx <= 256 && ny <= 256) ? launch_one<256>(which, a, s) : launch_one<512>(which, a, s);
 }
 
 hipError_t launch_phase2d(const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx, const DevOperator& Dy,
                           float* p, float* ux, float* uy, const float* c2, int nx, int ny, int64_t steps,
                           hipStream_t s) {
-  if (!phase2d_supported(nx, ny)) return hipErrorInvalidValue;
-  hipError_t e = configure(reinterpret_cast<const void*>(velocity2d_kernel));
-  if (e == hipSuccess) e = configure(reinterpret_cast<const void*>(pressure2d_kernel));
-  if (e != hipSuccess) return e;
-  Phase2DArgs a{static_cast<const float*>(Gx.data), Gx.Kp, static_cast<const float*>(Gy.data), Gy.Kp,
-                static_cast<const float*>(Dx.data), Dx.Kp, static_cast<const float*>(Dy.data), Dy.Kp,
-                p, ux, uy, c2, nx, ny};
-  const int nA = ((nx - 1 + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE) +
-                 ((nx + TILE - 1) / TILE) * ((ny - 1 + TILE - 1) / TILE);
-  const int nB = ((nx + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE);
+  if (!phase2d_supported(nx, ny) || !operators_fit(Gx, Gy, Dx, Dy, nx, ny)) return hipErrorInvalidValue;
+  const Phase2DArgs a = make_args(Gx, Gy, Dx, Dy, p, ux, uy, c2, nx, ny);
+  const bool small = nx <= 256 && ny <= 256;
   for (int64_t t = 0; t < steps; ++t) {
-    hipLaunchKernelGGL(velocity2d_kernel, dim3(nA), dim3(NT), kLds, s, a);
-    hipLaunchKernelGGL(pressure2d_kernel, dim3(nB), dim3(NT), kLds, s, a);
+    hipError_t e = small ? launch_one<256>(0, a, s) : launch_one<512>(0, a, s);
+    if (e == hipSuccess) e = small ? launch_one<256>(1, a, s) : launch_one<512>(1, a, s);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace pstd

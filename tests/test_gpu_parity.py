@@ -117,6 +117,7 @@ def test_sound_speed_map_2d():
     ((150, 133), ((D, N), (N, D))),
     ((37, 500), ((D, D), (N, N))),
     ((512, 512), ((N, D), (D, D))),             # largest grid of the fused path
+    ((129, 257), ((N, D), (D, N))),             # last tile rows past the allocated operator rows
 ])
 def test_2d_paths_fp32(path, shape, bcs):
     rng = np.random.default_rng(shape[0] * 7 + shape[1])
@@ -206,12 +207,15 @@ def test_check_finite_flags_planted_nan():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
-def test_misaligned_state_buffers(prec):
+@pytest.mark.parametrize("prec,shape,bcs", [
+    ("fp32", (41, 36, 37), ((N, D), (D, D), (D, N))),
+    ("split_bf16", (41, 36, 37), ((N, D), (D, D), (D, N))),
+    ("fp32", (65, 46), ((D, N), (N, D))),        # 2D: the fused phase kernels
+])
+def test_misaligned_state_buffers(prec, shape, bcs):
     # state tensors that start 4 bytes past a 16-byte boundary take the scalar-load paths
     import torch
     from paper_2005_00322_amd import Plan, State
-    shape, bcs = (41, 36, 37), ((N, D), (D, D), (D, N))
     rng = np.random.default_rng(77)
     p0 = rng.standard_normal(shape)
     c0 = 1500.0
@@ -232,7 +236,7 @@ def test_misaligned_state_buffers(prec):
         bp, p = offset_view(shape, p0)
         keep.append(bp)
         us = []
-        for a in range(3):
+        for a in range(len(shape)):
             bu, u = offset_view(plan.u_shape(a))
             keep.append(bu)
             us.append(u)
