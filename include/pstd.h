@@ -225,15 +225,17 @@ int pstd_batch_destroy(pstd_batch batch);
  *   layer l  v = GELU(W_l v + b_l + IDCT(R_l . DCT(v)))      W_l: C x C; R_l: (Mm/2) x (Mm/2) x C x C
  *   project  q = GELU(Q1 v + q1b),  out = Q2 q + q2b         Q1: Hp x C; Q2: Hp
  * DCT: orthonormal DCT-II along both axes keeping the Mm lowest modes; IDCT: its transpose; R_l mixes
- * channels per mode, one matrix per 2 x 2 block of modes.  GELU uses the exact erf.  The flat
+ * channels per mode, one matrix per 2 x 2 block of modes.  GELU is x Phi(x) with the normal CDF; the
+ * kernels evaluate Phi in the forward pass with Hastings' rational approximation of erfc (Abramowitz &
+ * Stegun 7.1.26, absolute error <= 1.5e-7) and use the exact erf in the backward pass.  The flat
  * parameter vector is P, pb, then per layer (R_l, W_l, b_l), then Q1, q1b, Q2, q2b, each row-major.
  * Loss: batch mean of |out - target|^2 / |target|^2. */
 typedef struct {
   int32_t H, W;        /* grid */
   int32_t channels;    /* C, 1 .. 32 */
-  int32_t modes;       /* Mm, even, <= H and <= W */
+  int32_t modes;       /* Mm, even, <= H, <= W and <= 256 */
   int32_t layers;      /* 1 .. 16 */
-  int32_t hidden;      /* Hp */
+  int32_t hidden;      /* Hp, 1 .. 256 */
   int32_t max_batch;   /* buffers are sized for this batch */
   int32_t split;       /* 1: each product as hi*hi + hi*lo + lo*hi bf16 parts (near FP32), 0: one bf16 product */
 } pstd_nop_config;

@@ -22,7 +22,7 @@ struct pstd_nop_s {
   float* F = nullptr;
   std::vector<float*> V, PRE, AT;
   float *qpre = nullptr, *q = nullptr, *out = nullptr;
-  float *Y1 = nullptr, *Ahat = nullptr, *Zt = nullptr, *At2 = nullptr, *S = nullptr;
+  float *Y1 = nullptr, *Ahat = nullptr, *Zt = nullptr, *At2 = nullptr, *T = nullptr;
   float *dv = nullptr, *dvn = nullptr, *dpre = nullptr, *dq = nullptr, *dout = nullptr, *part = nullptr;
   double* terms = nullptr;
   std::vector<void*> owned;
@@ -90,7 +90,8 @@ int chunks_of(int64_t P) {
     if (e_ != hipSuccess) return fail(PSTD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
   } while (0)
 
-// Y[b*C... ] spectral part S = IDCT(R . DCT(vin)) for one layer; keeps the blocked DCT in `at`.
+// Spectral term of one layer up to its last stage: T = (inverse DCT along H of) R . DCT(vin), laid out
+// [b][h][c][kw]; keeps the blocked DCT in `at`.
 int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int B) {
   const pstd_nop_config& c = N->cfg;
   const int H = c.H, W = c.W, C = c.channels, Mm = c.modes;
@@ -114,14 +115,15 @@ int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int
   g.bC1 = 4LL * B * C;
   NOP_RUN(launch_nop_gemm(g, s));
   NOP_RUN(launch_nop_mode_transpose(N->Zt, N->Ahat, B, C, Mm, false, s));
-  // inverse along W: Y1[(bc,kh)][w] = sum_kw Z[(bc,kh)][kw] Cw[kw][w]
-  g = gemm(N, N->Ahat, Mm, 1, N->Cw, W, 1, N->Y1, W, 1, B * C * Mm, W, Mm);
-  NOP_RUN(launch_nop_gemm(g, s));
-  // inverse along H: S[bc][h][w] = sum_kh Ch[kh][h] Y1[bc][kh][w]
-  g = gemm(N, N->Ch, 1, H, N->Y1, W, 1, N->S, W, 1, H, W, Mm);
-  g.nb1 = B * C;
-  g.bB1 = static_cast<int64_t>(Mm) * W;
-  g.bC1 = P;
+  // inverse along H: T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw]; the inverse along W is the
+  // second K segment of the channel-mixing kernel that consumes T
+  g = gemm(N, N->Ch, 1, H, N->Ahat, Mm, 1, N->T, static_cast<int64_t>(C) * Mm, 1, H, Mm, Mm);
+  g.nb1 = B;
+  g.bB1 = static_cast<int64_t>(C) * Mm * Mm;
+  g.bC1 = static_cast<int64_t>(H) * C * Mm;
+  g.nb2 = C;
+  g.bB2 = static_cast<int64_t>(Mm) * Mm;
+  g.bC2 = Mm;
   NOP_RUN(launch_nop_gemm(g, s));
   return PSTD_OK;
 }
@@ -158,8 +160,8 @@ int pstd_nop_create(const pstd_nop_config* cfg, void* hip_stream, pstd_nop* out)
   if (!cfg) return fail(PSTD_E_INVALID_ARG, "cfg is null");
   const pstd_nop_config c = *cfg;
   if (c.H < 2 || c.W < 2 || c.channels < 1 || c.channels > 32 || c.modes < 2 || c.modes % 2 || c.modes > c.H ||
-      c.modes > c.W ||
-      c.layers < 1 || c.layers > 16 || c.hidden < 1 || c.max_batch < 1 || (c.split != 0 && c.split != 1))
+      c.modes > c.W || c.modes > 256 ||
+      c.layers < 1 || c.layers > 16 || c.hidden < 1 || c.hidden > 256 || c.max_batch < 1 || (c.split != 0 && c.split != 1))
     return fail(PSTD_E_INVALID_ARG, "bad surrogate configuration");
   const int64_t P = static_cast<int64_t>(c.H) * c.W;
   const int64_t B = c.max_batch;
@@ -216,7 +218,7 @@ int pstd_nop_create(const pstd_nop_config* cfg, void* hip_stream, pstd_nop* out)
   A(&N->Ahat, spec);
   A(&N->Zt, spec);
   A(&N->At2, spec);
-  A(&N->S, act);
+  A(&N->T, B * c.H * C * Mm);
   A(&N->dv, act);
   A(&N->dvn, act);
   A(&N->dpre, act);
@@ -290,20 +292,21 @@ int forward_impl(pstd_nop N, const float* p0, const float* c0, float* out, int32
   const float* th = N->theta;
   NOP_RUN(launch_nop_features(p0, c0, N->F, B, c.H, c.W, s));
   // lift: V0[b] (C x P) = Pw (C x 4) F[b] (4 x P) + pb
-  NOP_RUN(launch_nop_mix(th + N->oP, false, N->F, N->V[0], th + N->opb, nullptr, nullptr, C, 4, P, B, false, s));
+  NOP_RUN(launch_nop_mix(th + N->oP, false, N->F, N->V[0], th + N->opb, nullptr, nullptr, nullptr, nullptr, 0, C, 4,
+                         c.H, c.W, B, false, c.split != 0, s));
   float* vin = N->V[0];
   for (int l = 0; l < c.layers; ++l) {
     float* vout = keep ? N->V[l + 1] : N->V[(l + 1) & 1];
     const int st = spectral_fwd(N, vin, th + N->oR[l], keep ? N->AT[l] : N->At2, B);
     if (st != PSTD_OK) return st;
     // vout = GELU(W vin + b + S), pre-activation kept for the backward pass
-    NOP_RUN(launch_nop_mix(th + N->oW[l], false, vin, vout, th + N->ob[l], N->S, keep ? N->PRE[l] : nullptr, C, C, P,
-                           B, true, s));
+    NOP_RUN(launch_nop_mix(th + N->oW[l], false, vin, vout, th + N->ob[l], nullptr, keep ? N->PRE[l] : nullptr, N->T,
+                           N->Cw, c.modes, C, C, c.H, c.W, B, true, c.split != 0, s));
     vin = vout;
   }
   // projection: out = Q2 GELU(Q1 v + q1b) + q2b
   NOP_RUN(launch_nop_project(th + N->oQ1, th + N->oq1b, th + N->oQ2, th + N->oq2b, vin, N->out,
-                             keep ? N->qpre : nullptr, keep ? N->q : nullptr, C, Hp, P, B, s));
+                             keep ? N->qpre : nullptr, keep ? N->q : nullptr, C, Hp, P, B, c.split != 0, s));
   if (out != N->out)
     PSTD_HIP(hipMemcpyAsync(out, N->out, static_cast<size_t>(B) * P * sizeof(float), hipMemcpyDeviceToDevice, s));
   N->last_batch = B;
@@ -349,14 +352,16 @@ int pstd_nop_backward(pstd_nop N, const float* target, double* loss) {
   st = weight_grad(N, N->dq, Hp, N->V[c.layers], C, gr + N->oQ1, B);
   if (st != PSTD_OK) return st;
   // dv = Q1^T dq
-  NOP_RUN(launch_nop_mix(th + N->oQ1, true, N->dq, N->dv, nullptr, nullptr, nullptr, C, Hp, P, B, false, s));
+  NOP_RUN(launch_nop_mix(th + N->oQ1, true, N->dq, N->dv, nullptr, nullptr, nullptr, nullptr, nullptr, 0, C, Hp, H, W,
+                         B, false, c.split != 0, s));
   for (int l = c.layers - 1; l >= 0; --l) {
     NOP_RUN(launch_nop_gelu_bwd(N->dv, N->PRE[l], N->dpre, static_cast<int64_t>(B) * C * P, s));
     NOP_RUN(launch_nop_rowsum(N->dpre, gr + N->ob[l], B, C, P, s));
     st = weight_grad(N, N->dpre, C, N->V[l], C, gr + N->oW[l], B);
     if (st != PSTD_OK) return st;
     // dvn = W^T dpre
-    NOP_RUN(launch_nop_mix(th + N->oW[l], true, N->dpre, N->dvn, nullptr, nullptr, nullptr, C, C, P, B, false, s));
+    NOP_RUN(launch_nop_mix(th + N->oW[l], true, N->dpre, N->dvn, nullptr, nullptr, nullptr, nullptr, nullptr, 0, C, C,
+                           H, W, B, false, c.split != 0, s));
     // spectral path: dZ = DCT(dpre) (the inverse's adjoint), blocked
     g = gemm(N, N->Ch, H, 1, N->dpre, W, 1, N->Y1, W, 1, Mm, W, H);
     g.nb1 = B * C;

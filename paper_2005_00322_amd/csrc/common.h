@@ -204,13 +204,17 @@ struct NopGemm {
   int split;            // 1: hi*hi + hi*lo + lo*hi bf16 products (near FP32); 0: one bf16 product
 };
 hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s);
-// Y[b][o][p] = sum_i A[o][i] X[b][i][p] (+ bias[o]) (+ D[b][o][p]) (-> pre, GELU) for O <= 32, on the FP32
-// matrix cores; A is O x I row-major, or I x O (its transpose) with transA.
+// Y[b][o][p] = sum_i A[o][i] X[b][i][p] (+ bias[o]) (+ D[b][o][p]) (+ sum_k T[b][h][o][k] Cw[k][w] at
+// p = (h, w)) (-> pre, GELU) for O <= 32 over an H x W grid, on the bf16 matrix cores (split: hi/lo
+// parts); A is O x I row-major, or I x O (its transpose) with transA; T ([b][h][o][Mm]) and Cw (Mm x W)
+// optional.
 hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y, const float* bias, const float* D,
-                          float* pre, int O, int I, int64_t P, int B, bool act, hipStream_t s);
+                          float* pre, const float* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
+                          bool split, hipStream_t s);
 // out = Q2 GELU(Q1 v + q1b) + q2b per position (C <= 32); qpre and q stored when non-null.
 hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
-                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, hipStream_t s);
+                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split,
+                              hipStream_t s);
 hipError_t launch_nop_mode_transpose(const float* in, float* out, int B, int C, int Mm, bool to_block, hipStream_t s);
 hipError_t launch_nop_features(const float* p0, const float* c0, float* f, int B, int H, int W, hipStream_t s);
 hipError_t launch_nop_gelu_bwd(const float* gin, const float* pre, float* d, int64_t n, hipStream_t s);

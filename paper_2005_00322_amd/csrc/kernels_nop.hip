@@ -25,7 +25,20 @@ constexpr int BK = 32;
 constexpr int LDK = BK + 8;     // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
 constexpr int NT = 256;         // 4 waves
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU x Phi(x) with the normal CDF from Hastings' rational approximation of erfc (Abramowitz & Stegun
+// 7.1.26, |error| <= 1.5e-7): branch-free, a reciprocal, five FMAs and one exponential.  Phi(x) =
+// erfc(-x/sqrt2)/2, with erfc(z) = t P(t) exp(-z^2), t = 1/(1 + p z) for z >= 0.  Worst absolute error of
+// the GELU value in FP32 over [-10, 10]: 4.2e-7.  The backward pass keeps the exact derivative.
+__device__ __forceinline__ float gelu_f(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  const float y = t * poly * __expf(-z * z);     // erfc(z)
+  return x * (x >= 0.f ? fmaf(-0.5f, y, 1.0f) : 0.5f * y);
+}
 __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
@@ -210,21 +223,49 @@ __global__ __launch_bounds__(NT) void nop_gemm_kernel(NopGemm g) {
 
 // Natural spectral layout [b][c][kh][kw] <-> block layout [blk][q][b][c] (blk = (kh/2)(Mm/2) + kw/2,
 // q = 2 (kh%2) + kw%2): the modes that share one mixing matrix become one contiguous GEMM operand.
-__global__ void nop_mode_transpose_kernel(const float* in, float* out, int B, int C, int Mm, int to_block) {
-  const int64_t total = static_cast<int64_t>(B) * C * Mm * Mm;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  // i enumerates the natural layout
-  const int kw = static_cast<int>(i % Mm);
-  const int kh = static_cast<int>((i / Mm) % Mm);
-  const int64_t bc = i / (static_cast<int64_t>(Mm) * Mm);
-  const int c = static_cast<int>(bc % C);
-  const int b = static_cast<int>(bc / C);
-  const int blk = (kh >> 1) * (Mm >> 1) + (kw >> 1);
-  const int q = 2 * (kh & 1) + (kw & 1);
-  const int64_t j = ((static_cast<int64_t>(blk) * 4 + q) * B + b) * C + c;
-  if (to_block) out[j] = in[i];
-  else out[i] = in[j];
+// One block moves the C x 64 slab of modes m0 .. m0+63 (m = kh Mm + kw) of one sample through LDS: the
+// natural side is read or written as 64 consecutive modes per channel, the block side as C consecutive
+// channels per mode.  C <= 32.
+__global__ __launch_bounds__(256) void nop_mode_transpose_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                                 int B, int C, int Mm, int to_block) {
+  __shared__ float tile[32][65];
+  const int M2 = Mm * Mm;
+  const int m0 = blockIdx.x * 64;
+  const int64_t b = blockIdx.y;
+  const int t = threadIdx.x;
+  // natural side: lane -> mode, wave -> channel
+  const int nm = m0 + (t & 63);
+  // block side: lane -> channel, half-wave -> mode
+  const int bc = t & 31;
+  int64_t boff[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int m = m0 + (t >> 5) + 8 * u;
+    const int kh = m / Mm, kw = m - kh * Mm;
+    const int blk = (kh >> 1) * (Mm >> 1) + (kw >> 1), q = 2 * (kh & 1) + (kw & 1);
+    boff[u] = m < M2 ? ((static_cast<int64_t>(blk) * 4 + q) * B + b) * C + bc : -1;
+  }
+  if (to_block) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (t >> 6) + 4 * u;
+      if (c < C && nm < M2) tile[c][t & 63] = in[(b * C + c) * M2 + nm];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (bc < C && boff[u] >= 0) out[boff[u]] = tile[bc][(t >> 5) + 8 * u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (bc < C && boff[u] >= 0) tile[bc][(t >> 5) + 8 * u] = in[boff[u]];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (t >> 6) + 4 * u;
+      if (c < C && nm < M2) out[(b * C + c) * M2 + nm] = tile[c][t & 63];
+    }
+  }
 }
 
 // Input features [b][4][H][W]: p0, (c0 - 1500)/100, x = i/(H-1), y = j/(W-1).
@@ -367,41 +408,121 @@ __global__ void nop_input_stats_kernel(const float* p0, const float* c0, double*
   }
 }
 
-// Pointwise channel mixing on the FP32 matrix cores: Y[b][o][p] = sum_i A[o][i] X[b][i][p] (+ bias[o])
-// (+ D[b][o][p]), then optionally pre = value and Y = GELU(value), for O <= 32 output channels.  Each
-// wave computes all O outputs of 32 consecutive positions with v_mfma_f32_32x32x2f32: lane l supplies
-// A[l%32][k0 + l/32] and X[k0 + l/32][l%32] (read straight from HBM, coalesced along the positions) and
-// receives Y[8(r/4) + 4(l/32) + r%4][l%32] in register r.  A is O x I row-major, or I x O with tA.
+// Eight consecutive k of one operand row as bf16, and (split) the bf16 remainder.
+__device__ __forceinline__ void to_bf16x8(const float (&x)[8], bf16x8& hi, bf16x8& lo, bool split) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = static_cast<__bf16>(x[e]);
+    hi[e] = h;
+    lo[e] = split ? static_cast<__bf16>(x[e] - static_cast<float>(h)) : static_cast<__bf16>(0.f);
+  }
+}
+
+// acc += P . Q over one K-step of 16 on the bf16 matrix cores; with split as hi*hi + hi*lo + lo*hi.
+__device__ __forceinline__ void mma_bf16(const float (&p)[8], const float (&q)[8], f32x16& acc, bool split) {
+  bf16x8 ph, pl, qh, ql;
+  to_bf16x8(p, ph, pl, split);
+  to_bf16x8(q, qh, ql, split);
+  if (split) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, qh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, ql, acc, 0, 0, 0);
+  }
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, qh, acc, 0, 0, 0);
+}
+
+// Pointwise channel mixing on the bf16 matrix cores (FP32 accumulation): Y[b][o][p] = sum_i A[o][i]
+// X[b][i][p] (+ bias[o]) (+ D[b][o][p]) (+ sum_k T[b][h][o][k] Cw[k][w] at p = (h, w)), then optionally
+// pre = value and Y = GELU(value), for O <= 32 output channels.  A block covers up to 128 consecutive
+// positions of one grid row, a wave 32 of them; each wave computes all O outputs of its positions with
+// v_mfma_f32_32x32x16_bf16: lane l supplies A[l%32][k0 + 8(l/32) .. +7] and X[k0 + 8(l/32) .. +7][l%32]
+// and receives Y[8(r/4) + 4(l/32) + r%4][l%32] in register r.  X is read straight from HBM, coalesced
+// along the positions; A (O x I row-major, or I x O with tA), the bias and the block's row of T
+// ([b][h][o][Mm]) are staged in LDS by coalesced loads, since a lane-per-row read of them would touch one
+// cache line per lane.  With T the second term is the last stage of the inverse DCT, T being the first
+// stage (along H) for the row: its K extent (the retained modes along W) continues the same
+// accumulation.  split: every product as hi*hi + hi*lo + lo*hi (near FP32).
 __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ A, const float* __restrict__ X,
                                                       float* __restrict__ Y, const float* __restrict__ bias,
-                                                      const float* __restrict__ D, float* __restrict__ pre, int O, int I,
-                                                      int64_t P, int act, int tA) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                      const float* __restrict__ D, float* __restrict__ pre,
+                                                      const float* __restrict__ T, const float* __restrict__ Cw, int O,
+                                                      int I, int H, int W, int Mm, int act, int tA, int split) {
+  extern __shared__ float sm[];
+  const int lda = I + 1, ldt = Mm + 1;
+  float* sA = sm;                          // [32][I + 1]: A as [o][k]
+  float* sT = sA + 32 * lda;               // [32][Mm + 1]: T row as [o][k]
+  float* sb = sT + (T ? 32 * ldt : 0);     // [32]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.y;
-  const int64_t n = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32 + (lane & 31);
-  const int kk = lane >> 5, o = lane & 31;
-  const bool nok = n < P;
-  const float* xb = X + b * I * P + (nok ? n : 0);
+  const int64_t P = static_cast<int64_t>(H) * W;
+  const int groups = (W + 127) >> 7;       // 128-position groups per row
+  const int h = blockIdx.x / groups;
+  const int w = (blockIdx.x - h * groups) * 128 + wave * 32 + (lane & 31);
+  const int kh = 8 * (lane >> 5), o = lane & 31;
+  const bool nok = w < W;
+  const int64_t n = nok ? static_cast<int64_t>(h) * W + w : 0;
+  const float* xb = X + b * I * P + n;
+  // the first 32 k of X in flight while the block stages its operands
+  float xv[2][8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * c + kh + e;
+      xv[c][e] = (nok && k < I) ? xb[static_cast<int64_t>(k) * P] : 0.f;
+    }
+  for (int i = tid; i < O * I; i += 256) {
+    const int r = tA ? i % O : i / I, k = tA ? i / O : i % I;
+    sA[r * lda + k] = A[i];
+  }
+  if (T) {
+    const float* tr = T + (b * H + h) * static_cast<int64_t>(O) * Mm;
+    for (int i = tid; i < O * Mm; i += 256) sT[(i / Mm) * ldt + i % Mm] = tr[i];
+  }
+  if (tid < 32) sb[tid] = (bias && tid < O) ? bias[tid] : 0.f;
+  __syncthreads();
+  const bool sp = split != 0;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-  for (int k0 = 0; k0 < I; k0 += 32) {
-    float av[16], xv[16];
+  // the first two K-steps from the prefetched registers, the rest loaded in the loop (k0 wave-uniform)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = k0 + 2 * j + kk;
-      const bool kok = k < I;
-      av[j] = (o < O && kok) ? (tA ? A[static_cast<int64_t>(k) * O + o] : A[static_cast<int64_t>(o) * I + k]) : 0.f;
-      xv[j] = (nok && kok) ? xb[static_cast<int64_t>(k) * P] : 0.f;
+  for (int c = 0; c < 2; ++c) {
+    if (16 * c >= I) break;
+    float af[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * c + kh + e;
+      af[e] = (o < O && k < I) ? sA[o * lda + k] : 0.f;
     }
+    mma_bf16(af, xv[c], acc, sp);
+  }
+  for (int k0 = 32; k0 < I; k0 += 16) {
+    float xf[8], af[8];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], xv[j], acc, 0, 0, 0);
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + kh + e;
+      xf[e] = (nok && k < I) ? xb[static_cast<int64_t>(k) * P] : 0.f;
+      af[e] = (o < O && k < I) ? sA[o * lda + k] : 0.f;
+    }
+    mma_bf16(af, xf, acc, sp);
+  }
+  if (T) {
+    for (int k0 = 0; k0 < Mm; k0 += 16) {
+      float cf[8], tf[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + kh + e;
+        cf[e] = (nok && k < Mm) ? Cw[static_cast<int64_t>(k) * W + w] : 0.f;
+        tf[e] = (o < O && k < Mm) ? sT[o * ldt + k] : 0.f;
+      }
+      mma_bf16(tf, cf, acc, sp);
+    }
   }
   float e[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int oo = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    e[r] = (oo < O && nok) ? ((D ? D[(b * O + oo) * P + n] : 0.f) + (bias ? bias[oo] : 0.f)) : 0.f;
+    e[r] = (oo < O && nok) ? ((D ? D[(b * O + oo) * P + n] : 0.f) + sb[oo]) : 0.f;
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -418,51 +539,78 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
   }
 }
 
-// Fused projection on the FP32 matrix cores: out[b][p] = sum_j Q2[j] GELU(sum_c Q1[j][c] v[b][c][p] + q1b[j])
-// + q2b (C <= 32 channels), 32 hidden rows per pass; each lane sums its rows, the two halves of the wave
-// are added with a lane exchange.  With keep (qpre non-null), qpre and q ([b][Hp][P]) are stored.
+// Fused projection on the bf16 matrix cores (FP32 accumulation): out[b][p] = sum_j Q2[j] GELU(sum_c
+// Q1[j][c] v[b][c][p] + q1b[j]) + q2b (C <= 32 channels), 32 hidden rows per pass; each lane sums its
+// rows, the two halves of the wave are added with a lane exchange.  Q1, q1b and Q2 are staged in LDS once
+// per block.  With keep (qpre non-null), qpre and q ([b][Hp][P]) are stored.
 __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restrict__ Q1, const float* __restrict__ q1b,
                                                           const float* __restrict__ Q2, const float* __restrict__ q2b,
                                                           const float* __restrict__ v, float* __restrict__ out,
                                                           float* __restrict__ qpre, float* __restrict__ q, int C,
-                                                          int Hp, int64_t P) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                          int Hp, int64_t P, int split) {
+  extern __shared__ float sm[];
+  const int ldq = C + 1;
+  float* sQ1 = sm;                  // [Hp][C + 1]
+  float* sb = sQ1 + Hp * ldq;       // [Hp]
+  float* s2 = sb + Hp;              // [Hp]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.y;
   const int64_t n = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32 + (lane & 31);
-  const int kk = lane >> 5, o = lane & 31;
+  const int kh = 8 * (lane >> 5), o = lane & 31;
   const bool nok = n < P;
   const float* vb = v + b * C * P + (nok ? n : 0);
-  float xv[16];
+  float xv[2][8];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int k = 2 * j + kk;
-    xv[j] = (nok && k < C) ? vb[static_cast<int64_t>(k) * P] : 0.f;
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * c + kh + e;
+      xv[c][e] = (nok && k < C) ? vb[static_cast<int64_t>(k) * P] : 0.f;
+    }
+  for (int i = tid; i < Hp * C; i += 256) sQ1[(i / C) * ldq + i % C] = Q1[i];
+  for (int i = tid; i < Hp; i += 256) {
+    sb[i] = q1b[i];
+    s2[i] = Q2[i];
   }
+  __syncthreads();
+  const bool sp = split != 0;
+  bf16x8 xh[2], xl[2];
+  to_bf16x8(xv[0], xh[0], xl[0], sp);
+  to_bf16x8(xv[1], xh[1], xl[1], sp);
   float part = 0.f;
   for (int t0 = 0; t0 < Hp; t0 += 32) {
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    float av[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = 2 * j + kk;
-      av[j] = (t0 + o < Hp && k < C) ? Q1[static_cast<int64_t>(t0 + o) * C + k] : 0.f;
+    for (int c = 0; c < 2; ++c) {
+      if (16 * c >= C) break;
+      float af[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * c + kh + e;
+        af[e] = (t0 + o < Hp && k < C) ? sQ1[(t0 + o) * ldq + k] : 0.f;
+      }
+      bf16x8 ah, al;
+      to_bf16x8(af, ah, al, sp);
+      if (sp) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh[c], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[c], acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh[c], acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], xv[j], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int jj = t0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       if (jj < Hp) {
-        const float h = acc[r] + q1b[jj];
-        const float g = gelu_f(h);
+        const float hv = acc[r] + sb[jj];
+        const float g = gelu_f(hv);
         if (qpre && nok) {
           const int64_t off = (b * Hp + jj) * P + n;
-          qpre[off] = h;
+          qpre[off] = hv;
           q[off] = g;
         }
-        part = fmaf(Q2[jj], g, part);
+        part = fmaf(s2[jj], g, part);
       }
     }
   }
@@ -490,23 +638,30 @@ hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s) {
 }
 
 hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y, const float* bias, const float* D,
-                          float* pre, int O, int I, int64_t P, int B, bool act, hipStream_t s) {
-  hipLaunchKernelGGL(nop_mix_kernel, dim3(blocks_for(P, 128), B), dim3(256), 0, s, A, X, Y, bias, D, pre, O, I, P,
-                     act ? 1 : 0, transA ? 1 : 0);
+                          float* pre, const float* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
+                          bool split, hipStream_t s) {
+  const size_t lds = sizeof(float) * (32 * (I + 1) + (T ? 32 * (Mm + 1) : 0) + 32);
+  if (O > 32 || H < 1 || W < 1 || I < 1 || lds > 65536) return hipErrorInvalidValue;
+  const int64_t blocks = static_cast<int64_t>(H) * ((W + 127) / 128);
+  hipLaunchKernelGGL(nop_mix_kernel, dim3(static_cast<unsigned>(blocks), B), dim3(256), lds, s, A, X, Y, bias, D, pre, T,
+                     Cw, O, I, H, W, Mm, act ? 1 : 0, transA ? 1 : 0, split ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
-                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, hipStream_t s) {
-  hipLaunchKernelGGL(nop_project_kernel, dim3(blocks_for(P, 128), B), dim3(256), 0, s, Q1, q1b, Q2, q2b, v, out, qpre,
-                     q, C, Hp, P);
+                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split,
+                              hipStream_t s) {
+  const size_t lds = sizeof(float) * (static_cast<size_t>(Hp) * (C + 1) + 2 * Hp);
+  if (C > 32 || lds > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nop_project_kernel, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b, v, out, qpre,
+                     q, C, Hp, P, split ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_nop_mode_transpose(const float* in, float* out, int B, int C, int Mm, bool to_block, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(B) * C * Mm * Mm;
-  hipLaunchKernelGGL(nop_mode_transpose_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, B, C, Mm,
-                     to_block ? 1 : 0);
+  if (C > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nop_mode_transpose_kernel, dim3(blocks_for(static_cast<int64_t>(Mm) * Mm, 64), B), dim3(256), 0,
+                     s, in, out, B, C, Mm, to_block ? 1 : 0);
   return hipGetLastError();
 }
 
