@@ -19,6 +19,7 @@ struct pstd_nop_s {
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   int64_t adam_t = 0;
   float *Ch = nullptr, *Cw = nullptr;
+  void *dct2_img = nullptr, *idct_img = nullptr;   // bf16 LDS images of the tables
   float* F = nullptr;
   std::vector<float*> V, PRE, AT;
   float *qpre = nullptr, *q = nullptr, *out = nullptr;
@@ -97,15 +98,21 @@ int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int
   const int H = c.H, W = c.W, C = c.channels, Mm = c.modes;
   const int64_t P = N->P;
   hipStream_t s = N->stream;
-  // DCT along H: Y1[bc] (Mm x W) = Ch (Mm x H) vin[bc] (H x W)
-  NopGemm g = gemm(N, N->Ch, H, 1, vin, W, 1, N->Y1, W, 1, Mm, W, H);
-  g.nb1 = B * C;
-  g.bB1 = P;
-  g.bC1 = static_cast<int64_t>(Mm) * W;
-  NOP_RUN(launch_nop_gemm(g, s));
-  // DCT along W: Ahat[(bc,kh)][kw] = sum_w Y1[(bc,kh)][w] Cw[kw][w]
-  g = gemm(N, N->Y1, W, 1, N->Cw, 1, W, N->Ahat, Mm, 1, B * C * Mm, Mm, W);
-  NOP_RUN(launch_nop_gemm(g, s));
+  NopGemm g;
+  if (nop_dct2_supported(H, W, Mm)) {
+    // both DCT stages per plane in registers: Ahat[b][c] = Ch vin[b][c] Cw^T
+    NOP_RUN(launch_nop_dct2(vin, N->Ahat, N->dct2_img, B * C, H, W, Mm, c.split != 0, s));
+  } else {
+    // DCT along H: Y1[bc] (Mm x W) = Ch (Mm x H) vin[bc] (H x W)
+    g = gemm(N, N->Ch, H, 1, vin, W, 1, N->Y1, W, 1, Mm, W, H);
+    g.nb1 = B * C;
+    g.bB1 = P;
+    g.bC1 = static_cast<int64_t>(Mm) * W;
+    NOP_RUN(launch_nop_gemm(g, s));
+    // DCT along W: Ahat[(bc,kh)][kw] = sum_w Y1[(bc,kh)][w] Cw[kw][w]
+    g = gemm(N, N->Y1, W, 1, N->Cw, 1, W, N->Ahat, Mm, 1, B * C * Mm, Mm, W);
+    NOP_RUN(launch_nop_gemm(g, s));
+  }
   NOP_RUN(launch_nop_mode_transpose(N->Ahat, at, B, C, Mm, true, s));
   // mixing per 2 x 2 mode block: Zt[blk] (4B x C) = at[blk] (4B x C) R[blk]^T
   g = gemm(N, at, C, 1, R, 1, C, N->Zt, C, 1, 4 * B, C, C);
@@ -117,14 +124,18 @@ int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int
   NOP_RUN(launch_nop_mode_transpose(N->Zt, N->Ahat, B, C, Mm, false, s));
   // inverse along H: T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw]; the inverse along W is the
   // second K segment of the channel-mixing kernel that consumes T
-  g = gemm(N, N->Ch, 1, H, N->Ahat, Mm, 1, N->T, static_cast<int64_t>(C) * Mm, 1, H, Mm, Mm);
-  g.nb1 = B;
-  g.bB1 = static_cast<int64_t>(C) * Mm * Mm;
-  g.bC1 = static_cast<int64_t>(H) * C * Mm;
-  g.nb2 = C;
-  g.bB2 = static_cast<int64_t>(Mm) * Mm;
-  g.bC2 = Mm;
-  NOP_RUN(launch_nop_gemm(g, s));
+  if (Mm <= 64 && H <= 512) {
+    NOP_RUN(launch_nop_idct_h(N->Ahat, N->T, N->idct_img, B, C, H, Mm, c.split != 0, s));
+  } else {
+    g = gemm(N, N->Ch, 1, H, N->Ahat, Mm, 1, N->T, static_cast<int64_t>(C) * Mm, 1, H, Mm, Mm);
+    g.nb1 = B;
+    g.bB1 = static_cast<int64_t>(C) * Mm * Mm;
+    g.bC1 = static_cast<int64_t>(H) * C * Mm;
+    g.nb2 = C;
+    g.bB2 = static_cast<int64_t>(Mm) * Mm;
+    g.bC2 = Mm;
+    NOP_RUN(launch_nop_gemm(g, s));
+  }
   return PSTD_OK;
 }
 
@@ -239,6 +250,19 @@ int pstd_nop_create(const pstd_nop_config* cfg, void* hip_stream, pstd_nop* out)
     if (hipMemcpy(ax == 0 ? N->Ch : N->Cw, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
       nop_free(N);
       return fail(PSTD_E_HIP, "copy of the DCT matrices failed");
+    }
+  }
+  {
+    size_t db = 0, ib = 0;
+    nop_table_bytes(c.H, c.W, Mm, c.split != 0, &db, &ib);
+    if (nop_alloc(N, &N->dct2_img, db) != PSTD_OK || nop_alloc(N, &N->idct_img, ib) != PSTD_OK) {
+      nop_free(N);
+      return PSTD_E_OOM;
+    }
+    if (launch_nop_tables(N->Ch, N->Cw, N->dct2_img, N->idct_img, c.H, c.W, Mm, c.split != 0, N->stream) != hipSuccess ||
+        hipStreamSynchronize(N->stream) != hipSuccess) {
+      nop_free(N);
+      return fail(PSTD_E_HIP, "building the DCT table images failed");
     }
   }
   if (hipMemset(N->theta, 0, o * sizeof(float)) != hipSuccess || hipMemset(N->m1, 0, o * sizeof(float)) != hipSuccess ||

@@ -215,6 +215,20 @@ hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y,
 hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
                               float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split,
                               hipStream_t s);
+// A[pl][kh][kw] = sum_h sum_w Ch[kh][h] V[pl][h][w] Cw[kw][w] for every plane (the truncated 2D DCT, Ch:
+// Mm x H, Cw: Mm x W), one plane per wave on the bf16 matrix cores; W <= 128, Mm <= 64.
+// The per-plane DCT kernels read their tables from images (bf16, remainders with split) built once:
+// sizes, and the kernel that builds them from the FP32 tables Ch (Mm x H) and Cw (Mm x W).
+void nop_table_bytes(int H, int W, int Mm, bool split, size_t* dct2_bytes, size_t* idct_bytes);
+hipError_t launch_nop_tables(const float* Ch, const float* Cw, void* dct2_img, void* idct_img, int H, int W, int Mm,
+                             bool split, hipStream_t s);
+bool nop_dct2_supported(int H, int W, int Mm);
+hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
+                           hipStream_t s);
+// T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw] (first inverse-DCT stage), one plane per wave on the
+// bf16 matrix cores; Mm <= 64 and H <= 512 (LDS).
+hipError_t launch_nop_idct_h(const float* Z, float* T, const void* img, int B, int C, int H, int Mm, bool split,
+                             hipStream_t s);
 hipError_t launch_nop_mode_transpose(const float* in, float* out, int B, int C, int Mm, bool to_block, hipStream_t s);
 hipError_t launch_nop_features(const float* p0, const float* c0, float* f, int B, int H, int W, hipStream_t s);
 hipError_t launch_nop_gelu_bwd(const float* gin, const float* pre, float* d, int64_t n, hipStream_t s);

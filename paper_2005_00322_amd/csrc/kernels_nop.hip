@@ -20,6 +20,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;
 constexpr int LDK = BK + 8;     // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
@@ -430,6 +431,34 @@ __device__ __forceinline__ void mma_bf16(const float (&p)[8], const float (&q)[8
   acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, qh, acc, 0, 0, 0);
 }
 
+// dst[r * ldd + k] = element (r, k) of an R x K matrix, read row-major (src[r * K + k]) or, with trans,
+// from its K x R transpose (src[k * R + r]); 256 threads, eight loads per thread in flight before their
+// LDS stores.  The row/column split uses a float reciprocal: (i + 1/2) / cols is at least 1/(2 cols)
+// away from an integer and its relative error is below 2^-23, exact for R K < 2^22.
+__device__ __forceinline__ void stage_matrix(float* dst, int ldd, const float* __restrict__ src, int R, int K,
+                                             bool trans) {
+  const int n = R * K;
+  const int cols = trans ? R : K;
+  const float inv = 1.0f / static_cast<float>(cols);
+  for (int base = 0; base < n; base += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
+      v[u] = i < n ? src[i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
+      if (i < n) {
+        const int q = static_cast<int>((static_cast<float>(i) + 0.5f) * inv);
+        const int rem = i - q * cols;
+        dst[(trans ? rem : q) * ldd + (trans ? q : rem)] = v[u];
+      }
+    }
+  }
+}
+
 // Pointwise channel mixing on the bf16 matrix cores (FP32 accumulation): Y[b][o][p] = sum_i A[o][i]
 // X[b][i][p] (+ bias[o]) (+ D[b][o][p]) (+ sum_k T[b][h][o][k] Cw[k][w] at p = (h, w)), then optionally
 // pre = value and Y = GELU(value), for O <= 32 output channels.  A block covers up to 128 consecutive
@@ -470,14 +499,8 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
       const int k = 16 * c + kh + e;
       xv[c][e] = (nok && k < I) ? xb[static_cast<int64_t>(k) * P] : 0.f;
     }
-  for (int i = tid; i < O * I; i += 256) {
-    const int r = tA ? i % O : i / I, k = tA ? i / O : i % I;
-    sA[r * lda + k] = A[i];
-  }
-  if (T) {
-    const float* tr = T + (b * H + h) * static_cast<int64_t>(O) * Mm;
-    for (int i = tid; i < O * Mm; i += 256) sT[(i / Mm) * ldt + i % Mm] = tr[i];
-  }
+  stage_matrix(sA, lda, A, O, I, tA != 0);
+  if (T) stage_matrix(sT, ldt, T + (b * H + h) * static_cast<int64_t>(O) * Mm, O, Mm, false);
   if (tid < 32) sb[tid] = (bias && tid < O) ? bias[tid] : 0.f;
   __syncthreads();
   const bool sp = split != 0;
@@ -567,7 +590,7 @@ __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restric
       const int k = 16 * c + kh + e;
       xv[c][e] = (nok && k < C) ? vb[static_cast<int64_t>(k) * P] : 0.f;
     }
-  for (int i = tid; i < Hp * C; i += 256) sQ1[(i / C) * ldq + i % C] = Q1[i];
+  stage_matrix(sQ1, ldq, Q1, Hp, C, false);
   for (int i = tid; i < Hp; i += 256) {
     sb[i] = q1b[i];
     s2[i] = Q2[i];
@@ -618,6 +641,266 @@ __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restric
   if (lane < 32 && nok) out[b * P + n] = part + q2b[0];
 }
 
+// Truncated 2D DCT of every (b, c) plane, entirely in registers: A[pl][kh][kw] = sum_h sum_w Ch[kh][h]
+// V[pl][h][w] Cw[kw][w] (natural layout [b][c][kh][kw]), one plane per wave, on the bf16 matrix cores
+// (FP32 accumulation; split: hi/lo parts).  v_mfma_f32_16x16x16_bf16: lane l = 16 g + j supplies
+// P[j][4g .. 4g+3] and Q[j][4g .. 4g+3] and receives C[4g + r][j] in register r.
+//   pass 1, per block of 16 rows h:  C1[h][kw] = sum_w V[h][w] Cw[kw][w]   (P: 4 consecutive w of one
+//            row of V, a 16-byte load; Q: a row of Cw)
+//   pass 2:  A[kh][kw] += sum_h Ch[kh][h] C1[h][kw] over the same 16 rows   (P: a row of Ch; Q: C1 as it
+//            sits in the registers, since lane (g, j) holds rows 4g .. 4g+3 of column j)
+// so the intermediate never leaves the wave.  The DCT tables are staged in LDS as bf16 (and remainders),
+// zero padded to multiples of 16.  NT = ceil(Mm / 16) tiles per mode axis; W <= 128.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a), __builtin_bit_cast(s16x4, b), c, 0, 0,
+                                                   0);
+}
+__device__ __forceinline__ void to_bf16x4(const float (&x)[4], bf16x4& hi, bf16x4& lo, bool split) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 h = static_cast<__bf16>(x[e]);
+    hi[e] = h;
+    lo[e] = split ? static_cast<__bf16>(x[e] - static_cast<float>(h)) : static_cast<__bf16>(0.f);
+  }
+}
+// acc += P Q^T over one K-step of 16 (hi*hi, and with split hi*lo + lo*hi)
+__device__ __forceinline__ f32x4 mma16(bf16x4 ph, bf16x4 pl, bf16x4 qh, bf16x4 ql, f32x4 acc, bool split) {
+  if (split) {
+    acc = mfma16(pl, qh, acc);
+    acc = mfma16(ph, ql, acc);
+  }
+  return mfma16(ph, qh, acc);
+}
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOOB = 0x80000000u;   // buffer offset past every range: the load returns zero
+
+// LDS <- n16 16-byte chunks from global memory, eight loads per thread in flight before their stores.
+__device__ __forceinline__ void stage_bytes(void* dst, const void* __restrict__ src, int n16) {
+  const uint4* s4 = static_cast<const uint4*>(src);
+  uint4* d4 = static_cast<uint4*>(dst);
+  for (int base = 0; base < n16; base += 8 * 256) {
+    uint4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
+      if (i < n16) v[u] = s4[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
+      if (i < n16) d4[i] = v[u];
+    }
+  }
+}
+
+// LDS images of the DCT tables for the per-plane kernels, built once per surrogate, in exactly the
+// layout those kernels read (bf16, and the bf16 remainders with split; zero padded to multiples of 16):
+//   dct2 image:    Cw [M16][W16 + 4] hi, (lo), then Ch [M16][H16 + 4] hi, (lo)
+//   idct_h image:  Ch^T [H16][M16 + 4] hi, (lo)
+__global__ void nop_tables_kernel(const float* __restrict__ Ch, const float* __restrict__ Cw, __bf16* dimg,
+                                  __bf16* iimg, int H, int W, int Mm, int M16, int split) {
+  const int H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
+  const int ldw = W16 + 4, ldh = H16 + 4, ldc = M16 + 4;
+  const int parts = split ? 2 : 1;
+  const int64_t nd = static_cast<int64_t>(parts) * M16 * (ldw + ldh), ni = static_cast<int64_t>(parts) * H16 * ldc;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nd + ni;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float x = 0.f;
+    bool lo = false;
+    if (i < nd) {
+      const int64_t cwn = static_cast<int64_t>(parts) * M16 * ldw;
+      if (i < cwn) {
+        const int64_t e = i % (static_cast<int64_t>(M16) * ldw);
+        lo = i >= static_cast<int64_t>(M16) * ldw;
+        const int r = static_cast<int>(e / ldw), c = static_cast<int>(e % ldw);
+        x = (r < Mm && c < W) ? Cw[r * W + c] : 0.f;
+      } else {
+        const int64_t e0 = i - cwn, e = e0 % (static_cast<int64_t>(M16) * ldh);
+        lo = e0 >= static_cast<int64_t>(M16) * ldh;
+        const int r = static_cast<int>(e / ldh), c = static_cast<int>(e % ldh);
+        x = (r < Mm && c < H) ? Ch[r * H + c] : 0.f;
+      }
+    } else {
+      const int64_t e0 = i - nd, e = e0 % (static_cast<int64_t>(H16) * ldc);
+      lo = e0 >= static_cast<int64_t>(H16) * ldc;
+      const int r = static_cast<int>(e / ldc), c = static_cast<int>(e % ldc);
+      x = (r < H && c < Mm) ? Ch[c * H + r] : 0.f;
+    }
+    const __bf16 h = static_cast<__bf16>(x);
+    const __bf16 v = lo ? static_cast<__bf16>(x - static_cast<float>(h)) : h;
+    if (i < nd) dimg[i] = v;
+    else iimg[i - nd] = v;
+  }
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__ V, float* __restrict__ A,
+                                                       const __bf16* __restrict__ img, int planes, int H, int W, int Mm,
+                                                       int split) {
+  constexpr int M16 = 16 * NT;
+  extern __shared__ __attribute__((aligned(16))) __bf16 tb[];
+  const int H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
+  const int ldw = W16 + 4, ldh = H16 + 4;       // bf16 row strides (8-byte aligned rows)
+  const bool sp = split != 0;
+  __bf16* cwh = tb;                              // [M16][ldw]
+  __bf16* cwl = cwh + M16 * ldw;
+  __bf16* chh = cwl + (sp ? M16 * ldw : 0);      // [M16][ldh]
+  __bf16* chl = chh + M16 * ldh;
+  const int tid = threadIdx.x;
+  stage_bytes(tb, img, static_cast<int>((sp ? 2 : 1) * M16 * (ldw + ldh) * sizeof(__bf16) / 16));
+  __syncthreads();
+  const int lane = tid & 63, g = lane >> 4, j = lane & 15;
+  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + (tid >> 6);
+  if (pl >= planes) return;
+  // loads through a buffer resource over the plane: an out-of-range offset reads zero, so no load is
+  // predicated and the next block's loads stay in flight during this block's MFMAs
+  const rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(V + pl * H * W), 0, H * W * 4, 0x00020000);
+  const int KS = W16 >> 4, MT = H16 >> 4;
+  f32x4 acc[NT][NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto load_rows = [&](float (&v)[8][4], int mt) {
+    const int h = 16 * mt + j;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int w0 = 16 * ks + 4 * g;
+      if (VEC) {   // W % 4 == 0: a 16-byte group is all inside the row or all past it
+        const uint32_t off = (h < H && w0 < W) ? 4u * static_cast<uint32_t>(h * W + w0) : kOOB;
+        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rv, off, 0, 0));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[ks][e] = x[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t off = (h < H && w0 + e < W) ? 4u * static_cast<uint32_t>(h * W + w0 + e) : kOOB;
+          v[ks][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, 0));
+        }
+      }
+    }
+  };
+  auto block = [&](const float (&v)[8][4], int mt) {
+    f32x4 c1[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) c1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      if (ks < KS) {
+        bf16x4 vh, vl;
+        to_bf16x4(v[ks], vh, vl, sp);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int o = (16 * nt + j) * ldw + 16 * ks + 4 * g;
+          const bf16x4 qh = *reinterpret_cast<const bf16x4*>(cwh + o);
+          const bf16x4 ql = sp ? *reinterpret_cast<const bf16x4*>(cwl + o) : qh;
+          c1[nt] = mma16(vh, vl, qh, ql, c1[nt], sp);
+        }
+      }
+    }
+    bf16x4 yh[NT], yl[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const float y[4] = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
+      to_bf16x4(y, yh[nt], yl[nt], sp);
+    }
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const int o = (16 * a + j) * ldh + 16 * mt + 4 * g;
+      const bf16x4 ph = *reinterpret_cast<const bf16x4*>(chh + o);
+      const bf16x4 pq = sp ? *reinterpret_cast<const bf16x4*>(chl + o) : ph;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) acc[a][c] = mma16(ph, pq, yh[c], yl[c], acc[a][c], sp);
+    }
+  };
+  float va[8][4], vb[8][4];
+  load_rows(va, 0);
+  for (int mt = 0; mt < MT; mt += 2) {
+    if (mt + 1 < MT) load_rows(vb, mt + 1);
+    block(va, mt);
+    if (mt + 1 >= MT) break;
+    if (mt + 2 < MT) load_rows(va, mt + 2);
+    block(vb, mt + 1);
+  }
+  float* ap = A + pl * Mm * Mm;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kh = 16 * a + 4 * g + r, kw = 16 * c + j;
+        if (kh < Mm && kw < Mm) ap[kh * Mm + kw] = acc[a][c][r];
+      }
+}
+
+// First stage of the inverse DCT for every (b, c) plane: T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw]
+// (Z in natural layout, T laid out for the channel-mixing kernel), one plane per wave on MFMA 16x16x16
+// bf16: P = Ch^T rows from LDS (bf16, remainders with split), Q = the plane's Mm x Mm coefficients,
+// loaded once into registers and reused for every 16 rows of h.  NT = ceil(Mm / 16).
+template <int NT>
+__global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict__ Z, float* __restrict__ T,
+                                                         const __bf16* __restrict__ img, int B, int C, int H, int Mm,
+                                                         int split) {
+  constexpr int M16 = 16 * NT;
+  constexpr int ldc = M16 + 4;                   // bf16 row stride of Ch^T
+  extern __shared__ __attribute__((aligned(16))) __bf16 tb[];
+  const int H16 = (H + 15) & ~15;
+  const bool sp = split != 0;
+  __bf16* cth = tb;                              // [H16][ldc]: Ch^T
+  __bf16* ctl = cth + H16 * ldc;
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, j = lane & 15;
+  stage_bytes(tb, img, static_cast<int>((sp ? 2 : 1) * H16 * ldc * sizeof(__bf16) / 16));
+  __syncthreads();
+  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + (tid >> 6);
+  if (pl >= static_cast<int64_t>(B) * C) return;
+  const int64_t b = pl / C;
+  const int c = static_cast<int>(pl - b * C);
+  const rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Z + pl * Mm * Mm), 0, Mm * Mm * 4, 0x00020000);
+  // Q operands: lane (g, j) of K-step ks and column tile nt holds Z[16 ks + 4 g + e][16 nt + j]
+  bf16x4 qh[NT][NT], ql[NT][NT];
+#pragma unroll
+  for (int ks = 0; ks < NT; ++ks)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      float z[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kh = 16 * ks + 4 * g + e, kw = 16 * nt + j;
+        const uint32_t off = (kh < Mm && kw < Mm) ? 4u * static_cast<uint32_t>(kh * Mm + kw) : kOOB;
+        z[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rz, off, 0, 0));
+      }
+      to_bf16x4(z, qh[ks][nt], ql[ks][nt], sp);
+    }
+  const int64_t rowstride = static_cast<int64_t>(C) * Mm;      // T: one h row holds every channel
+  float* tp = T + b * H * rowstride + static_cast<int64_t>(c) * Mm;
+  for (int mt = 0; mt < (H16 >> 4); ++mt) {
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < NT; ++ks) {
+      const int o = (16 * mt + j) * ldc + 16 * ks + 4 * g;
+      const bf16x4 ph = *reinterpret_cast<const bf16x4*>(cth + o);
+      const bf16x4 pq = sp ? *reinterpret_cast<const bf16x4*>(ctl + o) : ph;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = mma16(ph, pq, qh[ks][nt], ql[ks][nt], acc[nt], sp);
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h = 16 * mt + 4 * g + r, kw = 16 * nt + j;
+        if (h < H && kw < Mm) tp[h * rowstride + kw] = acc[nt][r];
+      }
+  }
+}
+
 unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
 
 }  // namespace
@@ -655,6 +938,68 @@ hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2
   if (C > 32 || lds > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(nop_project_kernel, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b, v, out, qpre,
                      q, C, Hp, P, split ? 1 : 0);
+  return hipGetLastError();
+}
+
+void nop_table_bytes(int H, int W, int Mm, bool split, size_t* dct2_bytes, size_t* idct_bytes) {
+  const int M16 = (Mm + 15) & ~15, H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
+  const size_t parts = split ? 2 : 1;
+  *dct2_bytes = parts * M16 * ((W16 + 4) + (H16 + 4)) * sizeof(__bf16);
+  *idct_bytes = parts * H16 * (M16 + 4) * sizeof(__bf16);
+}
+
+hipError_t launch_nop_tables(const float* Ch, const float* Cw, void* dct2_img, void* idct_img, int H, int W, int Mm,
+                             bool split, hipStream_t s) {
+  const int M16 = (Mm + 15) & ~15;
+  hipLaunchKernelGGL(nop_tables_kernel, dim3(256), dim3(256), 0, s, Ch, Cw, static_cast<__bf16*>(dct2_img),
+                     static_cast<__bf16*>(idct_img), H, W, Mm, M16, split ? 1 : 0);
+  return hipGetLastError();
+}
+
+bool nop_dct2_supported(int H, int W, int Mm) { return W <= 128 && Mm <= 64 && H >= 1 && W >= 1 && Mm >= 1; }
+
+hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
+                           hipStream_t s) {
+  if (!nop_dct2_supported(H, W, Mm) || planes < 1) return hipErrorInvalidValue;
+  if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & 15) != 0) return hipErrorInvalidValue;
+  const int NT = (Mm + 15) / 16;
+  const int H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
+  const size_t lds = sizeof(__bf16) * (split ? 2 : 1) * 16 * NT * ((W16 + 4) + (H16 + 4));
+  if (lds > 65536 || static_cast<int64_t>(H) * W * 4 >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((planes + 3) / 4)), blk(256);
+  const int sp = split ? 1 : 0;
+  const bool vec = (W & 3) == 0;
+  const __bf16* tab = static_cast<const __bf16*>(img);
+#define PSTD_DCT2(NTV)                                                                                         \
+  if (vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true>), grid, blk, lds, s, V, A, tab, planes, H, W, Mm, sp); \
+  else hipLaunchKernelGGL((nop_dct2_kernel<NTV, false>), grid, blk, lds, s, V, A, tab, planes, H, W, Mm, sp);
+  switch (NT) {
+    case 1: PSTD_DCT2(1) break;
+    case 2: PSTD_DCT2(2) break;
+    case 3: PSTD_DCT2(3) break;
+    default: PSTD_DCT2(4) break;
+  }
+#undef PSTD_DCT2
+  return hipGetLastError();
+}
+
+hipError_t launch_nop_idct_h(const float* Z, float* T, const void* img, int B, int C, int H, int Mm, bool split,
+                             hipStream_t s) {
+  if (Mm < 1 || Mm > 64 || H < 1 || B < 1 || C < 1) return hipErrorInvalidValue;
+  const int NT = (Mm + 15) / 16;
+  const int H16 = (H + 15) & ~15;
+  const size_t lds = sizeof(__bf16) * (split ? 2 : 1) * H16 * (16 * NT + 4);
+  if (lds > 65536) return hipErrorInvalidValue;
+  const int64_t planes = static_cast<int64_t>(B) * C;
+  const dim3 grid(static_cast<unsigned>((planes + 3) / 4)), blk(256);
+  const int sp = split ? 1 : 0;
+  const __bf16* tab = static_cast<const __bf16*>(img);
+  switch (NT) {
+    case 1: hipLaunchKernelGGL(nop_idct_h_kernel<1>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
+    case 2: hipLaunchKernelGGL(nop_idct_h_kernel<2>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
+    case 3: hipLaunchKernelGGL(nop_idct_h_kernel<3>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
+    default: hipLaunchKernelGGL(nop_idct_h_kernel<4>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
+  }
   return hipGetLastError();
 }
 

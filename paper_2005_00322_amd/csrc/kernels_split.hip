@@ -80,11 +80,15 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& h, bf16x8& l
   }
 }
 
-// FMODE (contiguous layout only): 0 = one 4-byte load per field element; 2 = two 16-byte loads per 8
-// floats (X 16-byte aligned and K % 4 == 0).
+// FMODE (contiguous layout only): 0 = one 4-byte load per field element, 8 consecutive k per lane;
+// 1 = one 4-byte load per element with the lanes along k (two rows of 32 consecutive floats per wave
+// instruction, coalesced at any row length and alignment), neighbouring lanes pairing their values
+// with a DPP swap so that each lane stores one packed bf16 pair (even lanes the hi parts, odd lanes
+// the lo parts); 2 = two 16-byte loads per 8 floats (X 16-byte aligned and K % 4 == 0).
 template <bool CONTIG, int FMODE>
 __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
   constexpr bool VEC = FMODE == 2;
+  constexpr bool LANEK = CONTIG && FMODE == 1;
   __shared__ __attribute__((aligned(16))) __bf16 lds[2][4][TILE_ELEMS];   // [buffer][P hi, P lo, Q hi, Q lo]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -155,6 +159,10 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
                         : static_cast<uint32_t>(4 * (static_cast<int64_t>(fl_grp[i]) * 8 * a.ncols + line));
   }
   const uint32_t kstride = CONTIG ? 4u : static_cast<uint32_t>(4 * a.ncols);   // bytes per unit of k
+  // FMODE 1: element q (0 .. 15) of a slice is row (tid / 32) + 8 q, k = k0 + tid % 32
+  const int lk = tid & 31, lrow = tid >> 5;
+  const uint32_t lk_base = static_cast<uint32_t>(4 * ((f0 + lrow) * a.K + lk));
+  const uint32_t lk_qstride = static_cast<uint32_t>(4 * 8 * a.K);
 
   u32x4 rOh[2][OP_CH], rOl[2][OP_CH];
   float rF[2][FL_G][8];
@@ -178,6 +186,12 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
           rF[R][i][j] = h0 ? v0[j] : 0.f;                                                             \
           rF[R][i][4 + j] = h1 ? v1[j] : 0.f;                                                         \
         }                                                                                             \
+      } else if (LANEK) {                                                                             \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                               \
+          const int q_ = 8 * i + j;                                                                   \
+          const bool ok_ = f0 + lrow + 8 * q_ < a.ncols && k0_ + lk < a.K;                            \
+          rF[R][i][j] = ld_f32(rX, ok_ ? lk_base + q_ * lk_qstride : kOOB, 4u * k0_);                  \
+        }                                                                                             \
       } else {                                                                                        \
         _Pragma("unroll") for (int j = 0; j < 8; ++j)                                                 \
           rF[R][i][j] = ld_f32(rX, (fl_ok[i] && kb + j < a.K) ? fl_voff[i] + j * kstride : kOOB,      \
@@ -194,12 +208,30 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
       *reinterpret_cast<u32x4*>(L + OPH * TILE_ELEMS + o) = rOh[R][i];                                \
       *reinterpret_cast<u32x4*>(L + OPL * TILE_ELEMS + o) = rOl[R][i];                                \
     }                                                                                                 \
-    _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                                \
-      bf16x8 h, l;                                                                                    \
-      split8(rF[R][i], h, l);                                                                         \
-      const int o = fl_line[i] * LDK + fl_grp[i] * 8;                                                 \
-      *reinterpret_cast<bf16x8*>(L + FLH * TILE_ELEMS + o) = h;                                       \
-      *reinterpret_cast<bf16x8*>(L + FLL * TILE_ELEMS + o) = l;                                       \
+    if (LANEK) {                                                                                      \
+      /* lanes 2m and 2m+1 hold k = 2m, 2m+1 of one row: after the swap both hold the pair; the even */ \
+      /* lane stores its hi parts, the odd lane its lo parts, each as one dword */                    \
+      const bool odd_ = (lk & 1) != 0;                                                                \
+      __bf16* dst_ = L + (odd_ ? FLL : FLH) * TILE_ELEMS + (lk & ~1);                                 \
+      _Pragma("unroll") for (int i = 0; i < FL_G; ++i) _Pragma("unroll") for (int j = 0; j < 8; ++j) { \
+        const float x_ = rF[R][i][j];                                                                 \
+        const float y_ = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x_), 0xB1, 0xF, 0xF, false)); \
+        const float e_ = odd_ ? y_ : x_, o_ = odd_ ? x_ : y_;                                         \
+        const __bf16 he_ = static_cast<__bf16>(e_), ho_ = static_cast<__bf16>(o_);                    \
+        const __bf16 pe_ = odd_ ? static_cast<__bf16>(e_ - static_cast<float>(he_)) : he_;            \
+        const __bf16 po_ = odd_ ? static_cast<__bf16>(o_ - static_cast<float>(ho_)) : ho_;            \
+        const uint32_t w_ = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, pe_)) |                \
+                            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, po_)) << 16);         \
+        *reinterpret_cast<uint32_t*>(dst_ + (lrow + 8 * (8 * i + j)) * LDK) = w_;                     \
+      }                                                                                               \
+    } else {                                                                                          \
+      _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                              \
+        bf16x8 h, l;                                                                                  \
+        split8(rF[R][i], h, l);                                                                       \
+        const int o = fl_line[i] * LDK + fl_grp[i] * 8;                                               \
+        *reinterpret_cast<bf16x8*>(L + FLH * TILE_ELEMS + o) = h;                                     \
+        *reinterpret_cast<bf16x8*>(L + FLL * TILE_ELEMS + o) = l;                                     \
+      }                                                                                               \
     }                                                                                                 \
   }
 
@@ -330,6 +362,8 @@ hipError_t launch_s(const ContractArgs& c, hipStream_t s) {
   const bool vec = CONTIG && c.K % 4 == 0 && (reinterpret_cast<uintptr_t>(c.X) & 15) == 0;
   if (vec)
     hipLaunchKernelGGL((split_kernel<CONTIG, 2>), grid, dim3(NT), 0, s, a);
+  else if (CONTIG)   // other contiguous rows: lanes along k
+    hipLaunchKernelGGL((split_kernel<CONTIG, 1>), grid, dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL((split_kernel<CONTIG, 0>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();

@@ -19,6 +19,9 @@ pytestmark = pytest.mark.gpu
 SMALL = dict(H=16, W=12, channels=4, modes=6, layers=2, hidden=8)
 # 256 positions: both GEMM tile shapes of the library (32 x 256 and 64 x 64) are used
 MEDIUM = dict(H=16, W=16, channels=8, modes=8, layers=1, hidden=128)
+# three 16-mode tiles per axis and an odd number of 16-row blocks in the per-plane DCT kernel
+LARGE = dict(H=48, W=64, channels=4, modes=40, layers=1, hidden=16)
+SHAPES = {"small": SMALL, "medium": MEDIUM, "large": LARGE}
 
 
 def _setup(split, B=3, seed=0, shape=SMALL):
@@ -38,10 +41,10 @@ def _setup(split, B=3, seed=0, shape=SMALL):
     return torch, net, ocfg, theta, p0, c0, tgt
 
 
-@pytest.mark.parametrize("shape", ["small", "medium"])
+@pytest.mark.parametrize("shape", ["small", "medium", "large"])
 @pytest.mark.parametrize("split,tol", [(True, 1e-4), (False, 3e-2)])
 def test_forward_and_gradients_match_reference(split, tol, shape):
-    torch, net, ocfg, theta, p0, c0, tgt = _setup(split, shape=SMALL if shape == "small" else MEDIUM)
+    torch, net, ocfg, theta, p0, c0, tgt = _setup(split, shape=SHAPES[shape])
     print("surrogate parity split", split, shape, flush=True)
     out = net.forward(p0, c0)
     loss = net.backward(tgt)
