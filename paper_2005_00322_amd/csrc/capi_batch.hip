@@ -27,10 +27,11 @@ struct pstd_batch_s {
   pstd::BatchSolve* d_solves = nullptr;
   std::vector<void*> key;                     // state pointers the device table was built for
   std::vector<pstd::BatchTask> tasksA, tasksB;
+  int segA[pstd::kBatchQueues + 1] = {}, segB[pstd::kBatchQueues + 1] = {};   // queue boundaries
   pstd::BatchTask* d_tasks = nullptr;         // A then B
   int order_built = -1;
   int tile_built = -1;
-  unsigned* d_counters = nullptr;             // 4 per step of a launch, then the barrier timeout flag
+  unsigned* d_counters = nullptr;             // kBatchCountersPerStep per step of a launch, then the timeout flag
   int blocks = 0;                             // 0 = occupancy maximum
   int order = 0;
   int tile = 32;                              // output tile edge of the persistent kernel (32 or 64)
@@ -41,7 +42,7 @@ struct pstd_batch_s {
 namespace pstd {
 namespace {
 
-constexpr int64_t kChunk = 1024;   // steps per persistent launch (4 counters each)
+constexpr int64_t kChunk = 1024;   // steps per persistent launch
 
 int upload_unscaled(const std::vector<double>& m, int M, int K, DevOperator* op) {
   op->M = M;
@@ -73,26 +74,50 @@ void free_batch(pstd_batch_s* B) {
 }
 
 // Tile lists of both phases for output tiles of edge T, in the requested order.
+// Tile lists of both phases, split into one queue per XCD.  Solves go to queues greedily, most costly
+// first (cost: per-step multiply-adds, n_x n_y (n_x + n_y)), so each queue carries about 1/8 of the work
+// and all tiles of a solve share one L2.  Within a queue: order 0 longest contraction first (stable, so
+// a solve's tiles stay together), order 1 solve after solve.
 void build_tasks(pstd_batch_s* B, int order, int T) {
+  constexpr int Q = kBatchQueues;
   B->tasksA.clear();
   B->tasksB.clear();
-  std::vector<std::pair<int, BatchTask>> a, b;   // (contracted length, task)
-  for (int s = 0; s < B->count; ++s) {
-    const int nx = B->nx[s], ny = B->ny[s];
-    for (int i0 = 0; i0 < nx - 1; i0 += T)
-      for (int j0 = 0; j0 < ny; j0 += T) a.push_back({nx, BatchTask{s, 0, i0, j0}});
-    for (int i0 = 0; i0 < nx; i0 += T)
-      for (int j0 = 0; j0 < ny - 1; j0 += T) a.push_back({ny, BatchTask{s, 1, i0, j0}});
-    for (int i0 = 0; i0 < nx; i0 += T)
-      for (int j0 = 0; j0 < ny; j0 += T) b.push_back({nx + ny - 2, BatchTask{s, 2, i0, j0}});
+  std::vector<int> by_cost(B->count);
+  for (int s = 0; s < B->count; ++s) by_cost[s] = s;
+  auto cost = [&](int s) { return static_cast<double>(B->nx[s]) * B->ny[s] * (B->nx[s] + B->ny[s]); };
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<double> load(Q, 0.0);
+  std::vector<std::vector<int>> members(Q);
+  for (int s : by_cost) {
+    const int q = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    members[q].push_back(s);
+    load[q] += cost(s);
   }
-  if (order == 0) {
-    auto longest_first = [](const std::pair<int, BatchTask>& x, const std::pair<int, BatchTask>& y) { return x.first > y.first; };
-    std::stable_sort(a.begin(), a.end(), longest_first);
-    std::stable_sort(b.begin(), b.end(), longest_first);
+  B->segA[0] = B->segB[0] = 0;
+  for (int q = 0; q < Q; ++q) {
+    std::sort(members[q].begin(), members[q].end());
+    std::vector<std::pair<int, BatchTask>> a, b;   // (contracted length, task)
+    for (int s : members[q]) {
+      const int nx = B->nx[s], ny = B->ny[s];
+      for (int i0 = 0; i0 < nx - 1; i0 += T)
+        for (int j0 = 0; j0 < ny; j0 += T) a.push_back({nx, BatchTask{s, 0, i0, j0}});
+      for (int i0 = 0; i0 < nx; i0 += T)
+        for (int j0 = 0; j0 < ny - 1; j0 += T) a.push_back({ny, BatchTask{s, 1, i0, j0}});
+      for (int i0 = 0; i0 < nx; i0 += T)
+        for (int j0 = 0; j0 < ny; j0 += T) b.push_back({nx + ny - 2, BatchTask{s, 2, i0, j0}});
+    }
+    if (order == 0) {
+      auto longest_first = [](const std::pair<int, BatchTask>& x, const std::pair<int, BatchTask>& y) {
+        return x.first > y.first;
+      };
+      std::stable_sort(a.begin(), a.end(), longest_first);
+      std::stable_sort(b.begin(), b.end(), longest_first);
+    }
+    for (auto& t : a) B->tasksA.push_back(t.second);
+    for (auto& t : b) B->tasksB.push_back(t.second);
+    B->segA[q + 1] = static_cast<int>(B->tasksA.size());
+    B->segB[q + 1] = static_cast<int>(B->tasksB.size());
   }
-  for (auto& t : a) B->tasksA.push_back(t.second);
-  for (auto& t : b) B->tasksB.push_back(t.second);
 }
 
 int ensure_tasks(pstd_batch_s* B) {
@@ -159,11 +184,13 @@ int graph_for(pstd_batch_s* B, int64_t steps, int blocks, hipGraphExec_t* out) {
   BatchArgs a;
   a.solves = B->d_solves;
   a.tasksA = B->d_tasks;
-  a.nA = static_cast<int>(B->tasksA.size());
   a.tasksB = B->d_tasks + B->tasksA.size();
-  a.nB = static_cast<int>(B->tasksB.size());
+  for (int q = 0; q <= kBatchQueues; ++q) {
+    a.segA[q] = B->segA[q];
+    a.segB[q] = B->segB[q];
+  }
   a.counters = B->d_counters;
-  a.timeout = B->d_counters + 4 * kChunk;
+  a.timeout = B->d_counters + kBatchCountersPerStep * kChunk;
   a.steps = steps;
   hipGraph_t g = nullptr;
   PSTD_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
@@ -311,17 +338,21 @@ int pstd_batch_create(int32_t count, const int64_t* n, const int32_t* bc, const 
     S.lddx = ox.D.Kp;
     S.ldgy = oy.G.Kp;
     S.lddy = oy.D.Kp;
+    S.mgx = ox.G.Mp;
+    S.mdx = ox.D.Mp;
+    S.mgy = oy.G.Mp;
+    S.mdy = oy.D.Mp;
     S.nx = B->nx[s];
     S.ny = B->ny[s];
     S.sG = -B->dt[s] / (rho0 * B->dx[s]);
     S.sD = -B->dt[s] * rho0 * B->c0[s] * B->c0[s] / B->dx[s];
     B->solves.push_back(S);
   }
-  if (hipMalloc(&B->d_counters, sizeof(unsigned) * (4 * kChunk + 1)) != hipSuccess) {
+  if (hipMalloc(&B->d_counters, sizeof(unsigned) * (kBatchCountersPerStep * kChunk + 1)) != hipSuccess) {
     free_batch(B);
     return fail(PSTD_E_OOM, "hipMalloc of the phase counters failed");
   }
-  if (hipMemset(B->d_counters, 0, sizeof(unsigned) * (4 * kChunk + 1)) != hipSuccess) {
+  if (hipMemset(B->d_counters, 0, sizeof(unsigned) * (kBatchCountersPerStep * kChunk + 1)) != hipSuccess) {
     free_batch(B);
     return fail(PSTD_E_HIP, "hipMemset of the phase counters failed");
   }
@@ -349,9 +380,9 @@ int pstd_batch_synchronize(pstd_batch B) {
   if (!B) return fail(PSTD_E_INVALID_ARG, "null batch");
   PSTD_HIP(B->stream ? hipStreamSynchronize(B->stream) : hipDeviceSynchronize());
   unsigned flag = 0;
-  PSTD_HIP(hipMemcpy(&flag, B->d_counters + 4 * kChunk, sizeof(unsigned), hipMemcpyDeviceToHost));
+  PSTD_HIP(hipMemcpy(&flag, B->d_counters + kBatchCountersPerStep * kChunk, sizeof(unsigned), hipMemcpyDeviceToHost));
   if (flag) {
-    PSTD_HIP(hipMemset(B->d_counters + 4 * kChunk, 0, sizeof(unsigned)));
+    PSTD_HIP(hipMemset(B->d_counters + kBatchCountersPerStep * kChunk, 0, sizeof(unsigned)));
     return fail(PSTD_E_HIP, "a grid barrier of the persistent launch timed out (blocks not all resident); "
                             "the state is not valid");
   }

@@ -114,6 +114,7 @@ struct BatchSolve {
   float* uy;                // nx x (ny-1)
   const float* Gx; const float* Dx; const float* Gy; const float* Dy;   // unscaled (dx = 1) operators
   int ldgx, lddx, ldgy, lddy;                                          // their row strides
+  int mgx, mdx, mgy, mdy;                                              // their allocated (padded) rows
   int nx, ny;
   double sG;                // -dt / (rho0 dx)
   double sD;                // -dt rho0 c0^2 / dx, or -dt rho0 / dx with a c0^2 map
@@ -124,13 +125,18 @@ struct BatchTask {
   int kind;                 // 0 u_x tile, 1 u_y tile, 2 p tile
   int i0, j0;
 };
+// Tiles of each phase are kept in kBatchQueues queues, one per XCD (blocks of XCD x are those with
+// blockIdx % 8 == x): queue q holds the tiles of the solves assigned to XCD q, so a solve's operator rows
+// and field strips are fetched into one L2; a block drains its own queue, then takes tiles from the others.
+constexpr int kBatchQueues = 8;
+constexpr int kBatchCountersPerStep = 2 * kBatchQueues + 2;   // tickets per queue and phase, two arrivals
 struct BatchArgs {
   const BatchSolve* solves;
-  const BatchTask* tasksA;  // velocity-phase tiles
-  int nA;
+  const BatchTask* tasksA;  // velocity-phase tiles, queue after queue
+  int segA[kBatchQueues + 1];   // queue q is tasksA[segA[q] .. segA[q + 1])
   const BatchTask* tasksB;  // pressure-phase tiles
-  int nB;
-  unsigned* counters;       // 4 per step (two tile tickets, two barrier arrivals), zeroed by the launcher
+  int segB[kBatchQueues + 1];
+  unsigned* counters;       // kBatchCountersPerStep per step, zeroed by the launcher
   unsigned* timeout;        // set to 1 when a grid barrier gives up waiting (sticky; cleared by the host)
   int64_t steps;
 };

@@ -4,7 +4,8 @@
 // blocks as the GPU holds at once runs all the steps: each step is a velocity phase over the velocity
 // tiles of every solve, a grid-wide barrier, a pressure phase over the pressure tiles of every solve
 // (each p tile takes both axes' terms), and a second barrier.  Within a phase blocks take tiles from a
-// per-phase atomic ticket, largest tiles first, so the uneven sizes balance.  Output tiles are 32 x 32
+// per-phase atomic ticket, largest tiles first, so the uneven sizes balance; the tickets are kept per
+// XCD, each XCD's queue holding whole solves so their data stays in that XCD's L2.  Output tiles are 32 x 32
 // (FP32 MFMA 16x16x4) or 64 x 64 (FP32 MFMA 32x32x2), chosen per batch by the autotuner.  The grid barrier is an
 // arrival counter per (step, phase) with agent-scope release/acquire ordering (the L2 of every XCD is
 // written back and invalidated around it); it gives up after a bounded wait and flags the launch, so a
@@ -34,37 +35,44 @@ constexpr int NT = 256;
 constexpr uint32_t kOOB = 0x80000000u;
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Every descriptor here is the same for the whole wave (it comes from the task of the block); passing
+// base and size through readfirstlane keeps it in scalar registers, where a buffer access needs it,
+// instead of a per-lane loop over distinct descriptors.
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+  void* u = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, 0, static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), 0x00020000);
 }
 __device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
-// Stage one BK slice of a TILE-row tile operand into LDS [row][k].
-//   operator rows: A[(r0 + r) * lda + k], zero padded on the host (no checks)
-//   field rows (contiguous):  X[(r0 + r) * ldx + k] for r0 + r < rows, k < K
-//   field columns (strided):  X[k * ldx + c0 + c]   for c0 + c < cols, k < K   (transposed into [c][k])
-// Each thread holds TILE/8 values of the next slice in registers between load and store.
-template <int TILE>
+// Stage one BK slice of a TILE-row tile operand into LDS [row][k].  KIND:
+//   0 operator rows: A[(r0 + r) * lda + k], zero padded on the host to its allocated rows and stride
+//   1 field rows (contiguous):  X[(r0 + r) * ldx + k] for r0 + r < rows, k < K
+//   2 field columns (strided):  X[k * ldx + c0 + c]   for c0 + c < cols, k < K   (transposed into [c][k])
+// Every access is a buffer load whose out-of-range offset reads zero, so a thread issues the same loads
+// for every slice (past the last one too) and the compiler can count them exactly.  A thread holds
+// V = TILE/8 values of a slice between its load and its LDS store.
+template <int TILE, int KIND>
 struct Stager {
   static constexpr int V = TILE / 8;
-  int kind;          // 0 operator rows, 1 field rows, 2 field columns
-  const float* base;
   rsrc_t rs;
   int ld, r0, lim, K;
-  float v[V];
 
-  __device__ void load(int k0) {
+  __device__ void load(int k0, float (&v)[V]) const {
     const int t = threadIdx.x;
-    if (kind == 0) {
+    if (KIND == 0) {
 #pragma unroll
       for (int h = 0; h < V / 4; ++h) {
         const int r = (t >> 3) + 32 * h, kk = (t & 7) * 4;
-        const f32x4 x = *reinterpret_cast<const f32x4*>(base + static_cast<int64_t>(r0 + r) * ld + k0 + kk);
+        const f32x4 x = __builtin_bit_cast(
+            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 4u * static_cast<uint32_t>((r0 + r) * ld + k0 + kk), 0, 0));
         v[4 * h] = x[0]; v[4 * h + 1] = x[1]; v[4 * h + 2] = x[2]; v[4 * h + 3] = x[3];
       }
-    } else if (kind == 1) {
+    } else if (KIND == 1) {
 #pragma unroll
       for (int h = 0; h < V / 4; ++h) {
         const int r = (t >> 3) + 32 * h, kk = (t & 7) * 4;
@@ -84,9 +92,9 @@ struct Stager {
       }
     }
   }
-  __device__ void store(float* lds) const {
+  __device__ void store(float* lds, const float (&v)[V]) const {
     const int t = threadIdx.x;
-    if (kind == 2) {
+    if (KIND == 2) {
       const int k = t >> 3, c = (t & 7) * V;
 #pragma unroll
       for (int j = 0; j < V; ++j) lds[(c + j) * LDB + k] = v[j];
@@ -155,34 +163,43 @@ struct Acc<64> {
   __device__ static int col() { return (threadIdx.x >> 7) * 32 + (threadIdx.x & 31); }
 };
 
-// accd += P . Q^T over K (multiple of BK after zero fill), P and Q described by their stagers.
-template <int TILE>
-__device__ __forceinline__ void tile_contract(Stager<TILE>& P, Stager<TILE>& Q, int K, float* lds,
+// accd += P . Q^T over K (zero filled to a multiple of BK), P and Q described by their stagers.  Two LDS
+// buffers and a ring of D register sets: while slice t is multiplied out of one buffer, slice t+1 is
+// stored into the other and the loads of slice t+D are issued into the set slice t came from, so a
+// slice's loads have D-1 slices of MFMA work to arrive.  The loop is unrolled by D so every set and
+// buffer index is a constant; a tile whose slice count is not a multiple of D runs up to D-1 steps
+// without MFMA work at its end.
+template <int TILE, int PK, int QK>
+__device__ __forceinline__ void tile_contract(const Stager<TILE, PK>& P, const Stager<TILE, QK>& Q, int K, float* lds,
                                               double (&accd)[Acc<TILE>::R]) {
+  constexpr int V = TILE / 8, D = 4;
   float* Pl[2] = {lds, lds + 2 * TILE * LDB};
   float* Ql[2] = {lds + TILE * LDB, lds + 3 * TILE * LDB};
   const int nsl = (K + BK - 1) / BK;
-  P.load(0);
-  Q.load(0);
-  lds_barrier();  // the previous user of the LDS buffers is done
-  P.store(Pl[0]);
-  Q.store(Ql[0]);
-  if (nsl > 1) {
-    P.load(BK);
-    Q.load(BK);
+  float rp[D][V], rq[D][V];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    P.load(i * BK, rp[i]);
+    Q.load(i * BK, rq[i]);
   }
+  lds_barrier();  // the previous user of the LDS buffers is done
+  P.store(Pl[0], rp[0]);
+  Q.store(Ql[0], rq[0]);
   lds_barrier();
-  for (int s = 0; s < nsl; ++s) {
-    Acc<TILE>::slice(Pl[s & 1], Ql[s & 1], accd);
-    if (s + 1 < nsl) {
-      P.store(Pl[(s + 1) & 1]);
-      Q.store(Ql[(s + 1) & 1]);
-      if (s + 2 < nsl) {
-        P.load((s + 2) * BK);
-        Q.load((s + 2) * BK);
-      }
+  // Only the MFMA work is conditional: the stores and loads run in every step (past the last slice they
+  // move zeros or unused values into the buffer that is not read), so each load stays where it is issued
+  // instead of being sunk into a conditional block next to its store.
+  for (int s0 = 0; s0 < nsl; s0 += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int t = s0 + i;   // wave-uniform
+      if (t < nsl) Acc<TILE>::slice(Pl[i & 1], Ql[i & 1], accd);
+      P.store(Pl[(i + 1) & 1], rp[(i + 1) % D]);
+      Q.store(Ql[(i + 1) & 1], rq[(i + 1) % D]);
+      P.load((t + D) * BK, rp[i]);
+      Q.load((t + D) * BK, rq[i]);
+      lds_barrier();
     }
-    lds_barrier();
   }
 }
 
@@ -198,23 +215,23 @@ __device__ void run_task(const BatchSolve& S, const BatchTask& T, float* lds) {
   double scale;
   if (T.kind == 0) {
     // u_x[i][j] += sG * sum_k Gx[i][k] p[k][j]
-    Stager<TILE> P{0, S.Gx, make_rsrc(S.Gx, 0u), S.ldgx, T.i0, nx - 1, nx};
-    Stager<TILE> Q{2, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.j0, ny, nx};
+    const Stager<TILE, 0> P{make_rsrc(S.Gx, 4u * S.mgx * S.ldgx), S.ldgx, T.i0, nx - 1, nx};
+    const Stager<TILE, 2> Q{make_rsrc(S.p, 4u * nx * ny), ny, T.j0, ny, nx};
     tile_contract<TILE>(P, Q, nx, lds, accd);
     Y = S.ux; rows = nx - 1; cols = ny; scale = S.sG;
   } else if (T.kind == 1) {
     // u_y[i][j] += sG_y * sum_k p[i][k] Gy[j][k]
-    Stager<TILE> P{1, nullptr, make_rsrc(S.p, 4u * nx * ny), ny, T.i0, nx, ny};
-    Stager<TILE> Q{0, S.Gy, make_rsrc(S.Gy, 0u), S.ldgy, T.j0, ny - 1, ny};
+    const Stager<TILE, 1> P{make_rsrc(S.p, 4u * nx * ny), ny, T.i0, nx, ny};
+    const Stager<TILE, 0> Q{make_rsrc(S.Gy, 4u * S.mgy * S.ldgy), S.ldgy, T.j0, ny - 1, ny};
     tile_contract<TILE>(P, Q, ny, lds, accd);
     Y = S.uy; rows = nx; cols = ny - 1; scale = S.sG;
   } else {
     // p[i][j] += sD * (sum_k Dx[i][k] u_x[k][j] + sum_k u_y[i][k] Dy[j][k])
-    Stager<TILE> P{0, S.Dx, make_rsrc(S.Dx, 0u), S.lddx, T.i0, nx, nx - 1};
-    Stager<TILE> Q{2, nullptr, make_rsrc(S.ux, 4u * (nx - 1) * ny), ny, T.j0, ny, nx - 1};
+    const Stager<TILE, 0> P{make_rsrc(S.Dx, 4u * S.mdx * S.lddx), S.lddx, T.i0, nx, nx - 1};
+    const Stager<TILE, 2> Q{make_rsrc(S.ux, 4u * (nx - 1) * ny), ny, T.j0, ny, nx - 1};
     tile_contract<TILE>(P, Q, nx - 1, lds, accd);
-    Stager<TILE> P2{1, nullptr, make_rsrc(S.uy, 4u * nx * (ny - 1)), ny - 1, T.i0, nx, ny - 1};
-    Stager<TILE> Q2{0, S.Dy, make_rsrc(S.Dy, 0u), S.lddy, T.j0, ny, ny - 1};
+    const Stager<TILE, 1> P2{make_rsrc(S.uy, 4u * nx * (ny - 1)), ny - 1, T.i0, nx, ny - 1};
+    const Stager<TILE, 0> Q2{make_rsrc(S.Dy, 4u * S.mdy * S.lddy), S.lddy, T.j0, ny, ny - 1};
     tile_contract<TILE>(P2, Q2, ny - 1, lds, accd);
     Y = S.p; rows = nx; cols = ny; scale = S.sD;
   }
@@ -261,22 +278,34 @@ __device__ void grid_barrier(unsigned* arrivals, unsigned* timeout) {
 template <int TILE>
 __global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
   __shared__ float lds[4 * TILE * LDB];
+  const int home = blockIdx.x % kBatchQueues;
   for (int64_t s = 0; s < a.steps; ++s) {
+    unsigned* cs = a.counters + kBatchCountersPerStep * s;
     for (int phase = 0; phase < 2; ++phase) {
       const BatchTask* tasks = phase == 0 ? a.tasksA : a.tasksB;
-      const int n = phase == 0 ? a.nA : a.nB;
-      unsigned* ctr = a.counters + 4 * s + phase;
+      const int* seg = phase == 0 ? a.segA : a.segB;
       __shared__ int t_shared;
-      for (;;) {
-        if (threadIdx.x == 0) t_shared = static_cast<int>(atomicAdd(ctr, 1u));
-        lds_barrier();
-        const int t = t_shared;
-        lds_barrier();
-        if (t >= n) break;
-        const BatchTask T = tasks[t];
-        run_task<TILE>(a.solves[T.solve], T, lds);
+      // the home queue first, then the others in turn
+      for (int qi = 0; qi < kBatchQueues; ++qi) {
+        const int q = (home + qi) % kBatchQueues;
+        const int beg = __builtin_amdgcn_readfirstlane(seg[q]);
+        const int len = __builtin_amdgcn_readfirstlane(seg[q + 1]) - beg;
+        unsigned* ctr = cs + phase * kBatchQueues + q;
+        for (;;) {
+          if (threadIdx.x == 0) t_shared = static_cast<int>(atomicAdd(ctr, 1u));
+          lds_barrier();
+          // uniform by construction; readfirstlane lets the compiler keep the task, the solve and the
+          // buffer descriptors built from them in scalar registers (no per-lane descriptor loops)
+          const int t = __builtin_amdgcn_readfirstlane(t_shared);
+          lds_barrier();
+          if (t >= len) break;
+          const BatchTask L = tasks[beg + t];
+          const BatchTask T{__builtin_amdgcn_readfirstlane(L.solve), __builtin_amdgcn_readfirstlane(L.kind),
+                            __builtin_amdgcn_readfirstlane(L.i0), __builtin_amdgcn_readfirstlane(L.j0)};
+          run_task<TILE>(a.solves[T.solve], T, lds);
+        }
       }
-      grid_barrier(a.counters + 4 * s + 2 + phase, a.timeout);
+      grid_barrier(cs + 2 * kBatchQueues + phase, a.timeout);
     }
   }
 }
@@ -303,7 +332,7 @@ int batch2d_max_blocks(int tile, int* out) {
 hipError_t launch_batch2d(const BatchArgs& a, int tile, int blocks, hipStream_t s) {
   // fresh tickets and barrier counters for every launch (a fill kernel, not a memset, so the pair of
   // launches can be captured in a graph)
-  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, 4 * a.steps);
+  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, s, a.counters, kBatchCountersPerStep * a.steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tile == 64) hipLaunchKernelGGL(batch2d_kernel<64>, dim3(blocks), dim3(NT), 0, s, a);

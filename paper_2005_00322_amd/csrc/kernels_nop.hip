@@ -678,6 +678,16 @@ __device__ __forceinline__ f32x4 mma16(bf16x4 ph, bf16x4 pl, bf16x4 qh, bf16x4 q
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr uint32_t kOOB = 0x80000000u;   // buffer offset past every range: the load returns zero
 
+// A buffer descriptor that is the same for the whole wave, built from base and size passed through
+// readfirstlane so it lives in scalar registers (no per-lane loop over descriptors around each access).
+__device__ __forceinline__ rsrc_t wave_rsrc(const void* p, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo), 0,
+                                           static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), 0x00020000);
+}
+
 // LDS <- n16 16-byte chunks from global memory, eight loads per thread in flight before their stores.
 __device__ __forceinline__ void stage_bytes(void* dst, const void* __restrict__ src, int n16) {
   const uint4* s4 = static_cast<const uint4*>(src);
@@ -754,11 +764,12 @@ __global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__
   stage_bytes(tb, img, static_cast<int>((sp ? 2 : 1) * M16 * (ldw + ldh) * sizeof(__bf16) / 16));
   __syncthreads();
   const int lane = tid & 63, g = lane >> 4, j = lane & 15;
-  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + (tid >> 6);
+  // the wave index through readfirstlane: the plane and its buffer descriptor stay in scalar registers
+  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(tid >> 6);
   if (pl >= planes) return;
   // loads through a buffer resource over the plane: an out-of-range offset reads zero, so no load is
   // predicated and the next block's loads stay in flight during this block's MFMAs
-  const rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(V + pl * H * W), 0, H * W * 4, 0x00020000);
+  const rsrc_t rv = wave_rsrc(V + pl * H * W, static_cast<uint32_t>(H * W * 4));
   const int KS = W16 >> 4, MT = H16 >> 4;
   f32x4 acc[NT][NT];
 #pragma unroll
@@ -857,11 +868,11 @@ __global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, j = lane & 15;
   stage_bytes(tb, img, static_cast<int>((sp ? 2 : 1) * H16 * ldc * sizeof(__bf16) / 16));
   __syncthreads();
-  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + (tid >> 6);
+  const int64_t pl = static_cast<int64_t>(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(tid >> 6);
   if (pl >= static_cast<int64_t>(B) * C) return;
   const int64_t b = pl / C;
   const int c = static_cast<int>(pl - b * C);
-  const rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Z + pl * Mm * Mm), 0, Mm * Mm * 4, 0x00020000);
+  const rsrc_t rz = wave_rsrc(Z + pl * Mm * Mm, static_cast<uint32_t>(Mm * Mm * 4));
   // Q operands: lane (g, j) of K-step ks and column tile nt holds Z[16 ks + 4 g + e][16 nt + j]
   bf16x4 qh[NT][NT], ql[NT][NT];
 #pragma unroll

@@ -185,7 +185,8 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
   int b = blockIdx.x;
   if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);   // consecutive tiles on one XCD
   const int i0 = (b / tiles_y) * T, j0 = (b % tiles_y) * T;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // the wave index through readfirstlane keeps per-wave buffer descriptors in scalar registers
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
 
   // the two contractions of this phase
   const float* A0 = PH == 0 ? a.Gx : a.Dx;

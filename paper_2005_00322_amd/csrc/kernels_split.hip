@@ -276,15 +276,16 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
   PSTD_STORE_SLICE(0, 0);
   PSTD_LOAD_SLICE(0, min(2, last) * BK);
   lds_barrier();
+  // Only the MFMA work is conditional: the stores and (clamped) loads run in every step, so each load
+  // stays where it is issued instead of being moved next to its store behind a branch.
   for (int s = 0; s < nslices; s += 2) {
     // even slice s: LDS buffer 0; slice s+1 waits in register set 1, slice s+2 in set 0
     PSTD_COMPUTE(0);
     PSTD_STORE_SLICE(1, 1);
     PSTD_LOAD_SLICE(1, min(s + 3, last) * BK);
     lds_barrier();
-    if (s + 1 >= nslices) break;
-    // odd slice s+1: LDS buffer 1; slice s+2 waits in register set 0, slice s+3 in set 1
-    PSTD_COMPUTE(1);
+    // odd slice s+1 (none past the last): LDS buffer 1; slice s+2 waits in set 0, slice s+3 in set 1
+    if (s + 1 < nslices) PSTD_COMPUTE(1);
     PSTD_STORE_SLICE(0, 0);
     PSTD_LOAD_SLICE(0, min(s + 4, last) * BK);
     lds_barrier();
