@@ -93,7 +93,7 @@ int chunks_of(int64_t P) {
 
 // Spectral term of one layer up to its last stage: T = (inverse DCT along H of) R . DCT(vin), laid out
 // [b][h][c][kw]; keeps the blocked DCT in `at`.
-int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int B) {
+int spectral_fwd(pstd_nop_s* N, const void* vin, const float* R, float* at, int B, bool half) {
   const pstd_nop_config& c = N->cfg;
   const int H = c.H, W = c.W, C = c.channels, Mm = c.modes;
   const int64_t P = N->P;
@@ -101,10 +101,10 @@ int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int
   NopGemm g;
   if (nop_dct2_supported(H, W, Mm)) {
     // both DCT stages per plane in registers: Ahat[b][c] = Ch vin[b][c] Cw^T
-    NOP_RUN(launch_nop_dct2(vin, N->Ahat, N->dct2_img, B * C, H, W, Mm, c.split != 0, s));
+    NOP_RUN(launch_nop_dct2(vin, N->Ahat, N->dct2_img, B * C, H, W, Mm, c.split != 0, half, s));
   } else {
     // DCT along H: Y1[bc] (Mm x W) = Ch (Mm x H) vin[bc] (H x W)
-    g = gemm(N, N->Ch, H, 1, vin, W, 1, N->Y1, W, 1, Mm, W, H);
+    g = gemm(N, N->Ch, H, 1, static_cast<const float*>(vin), W, 1, N->Y1, W, 1, Mm, W, H);
     g.nb1 = B * C;
     g.bB1 = P;
     g.bC1 = static_cast<int64_t>(Mm) * W;
@@ -125,7 +125,7 @@ int spectral_fwd(pstd_nop_s* N, const float* vin, const float* R, float* at, int
   // inverse along H: T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw]; the inverse along W is the
   // second K segment of the channel-mixing kernel that consumes T
   if (Mm <= 64 && H <= 512) {
-    NOP_RUN(launch_nop_idct_h(N->Ahat, N->T, N->idct_img, B, C, H, Mm, c.split != 0, s));
+    NOP_RUN(launch_nop_idct_h(N->Ahat, N->T, N->idct_img, B, C, H, Mm, c.split != 0, half, s));
   } else {
     g = gemm(N, N->Ch, 1, H, N->Ahat, Mm, 1, N->T, static_cast<int64_t>(C) * Mm, 1, H, Mm, Mm);
     g.nb1 = B;
@@ -316,21 +316,25 @@ int forward_impl(pstd_nop N, const float* p0, const float* c0, float* out, int32
   const float* th = N->theta;
   NOP_RUN(launch_nop_features(p0, c0, N->F, B, c.H, c.W, s));
   // lift: V0[b] (C x P) = Pw (C x 4) F[b] (4 x P) + pb
+  // Inference without split keeps the activations (each layer's field and the first inverse stage T) in
+  // bf16: every consumer rounds them to bf16 before its product, so the output is the same as with FP32
+  // storage while the traffic of the dominant tensors halves.  Training and split keep FP32.
+  const bool half = !keep && c.split == 0 && nop_dct2_supported(c.H, c.W, c.modes) && c.modes <= 64 && c.H <= 512;
   NOP_RUN(launch_nop_mix(th + N->oP, false, N->F, N->V[0], th + N->opb, nullptr, nullptr, nullptr, nullptr, 0, C, 4,
-                         c.H, c.W, B, false, c.split != 0, s));
+                         c.H, c.W, B, false, c.split != 0, half ? 1 : 0, s));
   float* vin = N->V[0];
   for (int l = 0; l < c.layers; ++l) {
     float* vout = keep ? N->V[l + 1] : N->V[(l + 1) & 1];
-    const int st = spectral_fwd(N, vin, th + N->oR[l], keep ? N->AT[l] : N->At2, B);
+    const int st = spectral_fwd(N, vin, th + N->oR[l], keep ? N->AT[l] : N->At2, B, half);
     if (st != PSTD_OK) return st;
     // vout = GELU(W vin + b + S), pre-activation kept for the backward pass
     NOP_RUN(launch_nop_mix(th + N->oW[l], false, vin, vout, th + N->ob[l], nullptr, keep ? N->PRE[l] : nullptr, N->T,
-                           N->Cw, c.modes, C, C, c.H, c.W, B, true, c.split != 0, s));
+                           N->Cw, c.modes, C, C, c.H, c.W, B, true, c.split != 0, half ? 2 : 0, s));
     vin = vout;
   }
   // projection: out = Q2 GELU(Q1 v + q1b) + q2b
   NOP_RUN(launch_nop_project(th + N->oQ1, th + N->oq1b, th + N->oQ2, th + N->oq2b, vin, N->out,
-                             keep ? N->qpre : nullptr, keep ? N->q : nullptr, C, Hp, P, B, c.split != 0, s));
+                             keep ? N->qpre : nullptr, keep ? N->q : nullptr, C, Hp, P, B, c.split != 0, half, s));
   if (out != N->out)
     PSTD_HIP(hipMemcpyAsync(out, N->out, static_cast<size_t>(B) * P * sizeof(float), hipMemcpyDeviceToDevice, s));
   N->last_batch = B;
@@ -377,7 +381,7 @@ int pstd_nop_backward(pstd_nop N, const float* target, double* loss) {
   if (st != PSTD_OK) return st;
   // dv = Q1^T dq
   NOP_RUN(launch_nop_mix(th + N->oQ1, true, N->dq, N->dv, nullptr, nullptr, nullptr, nullptr, nullptr, 0, C, Hp, H, W,
-                         B, false, c.split != 0, s));
+                         B, false, c.split != 0, 0, s));
   for (int l = c.layers - 1; l >= 0; --l) {
     NOP_RUN(launch_nop_gelu_bwd(N->dv, N->PRE[l], N->dpre, static_cast<int64_t>(B) * C * P, s));
     NOP_RUN(launch_nop_rowsum(N->dpre, gr + N->ob[l], B, C, P, s));
@@ -385,7 +389,7 @@ int pstd_nop_backward(pstd_nop N, const float* target, double* loss) {
     if (st != PSTD_OK) return st;
     // dvn = W^T dpre
     NOP_RUN(launch_nop_mix(th + N->oW[l], true, N->dpre, N->dvn, nullptr, nullptr, nullptr, nullptr, nullptr, 0, C, C,
-                           H, W, B, false, c.split != 0, s));
+                           H, W, B, false, c.split != 0, 0, s));
     // spectral path: dZ = DCT(dpre) (the inverse's adjoint), blocked
     g = gemm(N, N->Ch, H, 1, N->dpre, W, 1, N->Y1, W, 1, Mm, W, H);
     g.nb1 = B * C;

@@ -213,13 +213,15 @@ hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s);
 // Y[b][o][p] = sum_i A[o][i] X[b][i][p] (+ bias[o]) (+ D[b][o][p]) (+ sum_k T[b][h][o][k] Cw[k][w] at
 // p = (h, w)) (-> pre, GELU) for O <= 32 over an H x W grid, on the bf16 matrix cores (split: hi/lo
 // parts); A is O x I row-major, or I x O (its transpose) with transA; T ([b][h][o][Mm]) and Cw (Mm x W)
-// optional.
-hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y, const float* bias, const float* D,
-                          float* pre, const float* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
-                          bool split, hipStream_t s);
-// out = Q2 GELU(Q1 v + q1b) + q2b per position (C <= 32); qpre and q stored when non-null.
-hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
-                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split,
+// optional.  act_types: 0 X, Y, T in FP32; 1 X in FP32, Y in bf16; 2 X, Y, T in bf16 (inference
+// activations, which every consumer rounds to bf16 before its product).
+hipError_t launch_nop_mix(const float* A, bool transA, const void* X, void* Y, const float* bias, const float* D,
+                          float* pre, const void* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
+                          bool split, int act_types, hipStream_t s);
+// out = Q2 GELU(Q1 v + q1b) + q2b per position (C <= 32); qpre and q stored when non-null; v in bf16 with
+// half.
+hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const void* v,
+                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split, bool half,
                               hipStream_t s);
 // A[pl][kh][kw] = sum_h sum_w Ch[kh][h] V[pl][h][w] Cw[kw][w] for every plane (the truncated 2D DCT, Ch:
 // Mm x H, Cw: Mm x W), one plane per wave on the bf16 matrix cores; W <= 128, Mm <= 64.
@@ -229,12 +231,12 @@ void nop_table_bytes(int H, int W, int Mm, bool split, size_t* dct2_bytes, size_
 hipError_t launch_nop_tables(const float* Ch, const float* Cw, void* dct2_img, void* idct_img, int H, int W, int Mm,
                              bool split, hipStream_t s);
 bool nop_dct2_supported(int H, int W, int Mm);
-hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
-                           hipStream_t s);
+hipError_t launch_nop_dct2(const void* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
+                           bool half, hipStream_t s);   // V in bf16 with half
 // T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw] (first inverse-DCT stage), one plane per wave on the
 // bf16 matrix cores; Mm <= 64 and H <= 512 (LDS).
-hipError_t launch_nop_idct_h(const float* Z, float* T, const void* img, int B, int C, int H, int Mm, bool split,
-                             hipStream_t s);
+hipError_t launch_nop_idct_h(const float* Z, void* T, const void* img, int B, int C, int H, int Mm, bool split,
+                             bool half, hipStream_t s);   // T in bf16 with half
 hipError_t launch_nop_mode_transpose(const float* in, float* out, int B, int C, int Mm, bool to_block, hipStream_t s);
 hipError_t launch_nop_features(const float* p0, const float* c0, float* f, int B, int H, int W, hipStream_t s);
 hipError_t launch_nop_gelu_bwd(const float* gin, const float* pre, float* d, int64_t n, hipStream_t s);

@@ -22,6 +22,27 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOOB = 0x80000000u;   // buffer offset past every range: the load returns zero
+
+// A buffer descriptor that is the same for the whole wave, built from base and size passed through
+// readfirstlane so it lives in scalar registers (no per-lane loop over descriptors around each access).
+__device__ __forceinline__ rsrc_t wave_rsrc(const void* p, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo), 0,
+                                           static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), 0x00020000);
+}
+
+// One activation element through a buffer descriptor: a float, or a bf16 widened to float; an offset
+// of kOOB reads zero, so no load needs a branch around it.
+template <typename T>
+__device__ __forceinline__ float ld_elem(rsrc_t r, uint32_t byte_off) {
+  if (sizeof(T) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+  return static_cast<float>(__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0)));
+}
+
 constexpr int BK = 32;
 constexpr int LDK = BK + 8;     // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
 constexpr int NT = 256;         // 4 waves
@@ -435,26 +456,29 @@ __device__ __forceinline__ void mma_bf16(const float (&p)[8], const float (&q)[8
 // from its K x R transpose (src[k * R + r]); 256 threads, eight loads per thread in flight before their
 // LDS stores.  The row/column split uses a float reciprocal: (i + 1/2) / cols is at least 1/(2 cols)
 // away from an integer and its relative error is below 2^-23, exact for R K < 2^22.
-__device__ __forceinline__ void stage_matrix(float* dst, int ldd, const float* __restrict__ src, int R, int K,
+template <typename TS>
+__device__ __forceinline__ void stage_matrix(float* dst, int ldd, const TS* __restrict__ src, int R, int K,
                                              bool trans) {
   const int n = R * K;
   const int cols = trans ? R : K;
   const float inv = 1.0f / static_cast<float>(cols);
+  const rsrc_t rs = wave_rsrc(src, static_cast<uint32_t>(n * sizeof(TS)));
+  // indices past the end are clamped to the last element, whose value they store again: no branch, so
+  // the loads stay ahead of the stores
   for (int base = 0; base < n; base += 8 * 256) {
     float v[8];
+    int idx[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
-      v[u] = i < n ? src[i] : 0.f;
+      idx[u] = min(base + static_cast<int>(threadIdx.x) + 256 * u, n - 1);
+      v[u] = ld_elem<TS>(rs, static_cast<uint32_t>(idx[u] * sizeof(TS)));
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
-      if (i < n) {
-        const int q = static_cast<int>((static_cast<float>(i) + 0.5f) * inv);
-        const int rem = i - q * cols;
-        dst[(trans ? rem : q) * ldd + (trans ? q : rem)] = v[u];
-      }
+      const int i = idx[u];
+      const int q = static_cast<int>((static_cast<float>(i) + 0.5f) * inv);
+      const int rem = i - q * cols;
+      dst[(trans ? rem : q) * ldd + (trans ? q : rem)] = v[u];
     }
   }
 }
@@ -470,10 +494,13 @@ __device__ __forceinline__ void stage_matrix(float* dst, int ldd, const float* _
 // cache line per lane.  With T the second term is the last stage of the inverse DCT, T being the first
 // stage (along H) for the row: its K extent (the retained modes along W) continues the same
 // accumulation.  split: every product as hi*hi + hi*lo + lo*hi (near FP32).
-__global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ A, const float* __restrict__ X,
-                                                      float* __restrict__ Y, const float* __restrict__ bias,
+// TX, TY, TT: storage types of X, Y and T (float, or __bf16 for inference activations, which every
+// consumer rounds to bf16 before its product anyway).
+template <typename TX, typename TY, typename TT>
+__global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ A, const TX* __restrict__ X,
+                                                      TY* __restrict__ Y, const float* __restrict__ bias,
                                                       const float* __restrict__ D, float* __restrict__ pre,
-                                                      const float* __restrict__ T, const float* __restrict__ Cw, int O,
+                                                      const TT* __restrict__ T, const float* __restrict__ Cw, int O,
                                                       int I, int H, int W, int Mm, int act, int tA, int split) {
   extern __shared__ float sm[];
   const int lda = I + 1, ldt = Mm + 1;
@@ -489,16 +516,16 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
   const int kh = 8 * (lane >> 5), o = lane & 31;
   const bool nok = w < W;
   const int64_t n = nok ? static_cast<int64_t>(h) * W + w : 0;
-  const float* xb = X + b * I * P + n;
+  constexpr uint32_t XS = sizeof(TX);
+  const rsrc_t rX = wave_rsrc(X + b * I * P, static_cast<uint32_t>(I * P) * XS);
+  const rsrc_t rC = wave_rsrc(Cw, T ? static_cast<uint32_t>(Mm * W * 4) : 0u);
+  auto xoff = [&](int k) { return (nok && k < I) ? XS * static_cast<uint32_t>(k * P + n) : kOOB; };
   // the first 32 k of X in flight while the block stages its operands
   float xv[2][8];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = 16 * c + kh + e;
-      xv[c][e] = (nok && k < I) ? xb[static_cast<int64_t>(k) * P] : 0.f;
-    }
+    for (int e = 0; e < 8; ++e) xv[c][e] = ld_elem<TX>(rX, xoff(16 * c + kh + e));
   stage_matrix(sA, lda, A, O, I, tA != 0);
   if (T) stage_matrix(sT, ldt, T + (b * H + h) * static_cast<int64_t>(O) * Mm, O, Mm, false);
   if (tid < 32) sb[tid] = (bias && tid < O) ? bias[tid] : 0.f;
@@ -524,7 +551,7 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = k0 + kh + e;
-      xf[e] = (nok && k < I) ? xb[static_cast<int64_t>(k) * P] : 0.f;
+      xf[e] = ld_elem<TX>(rX, xoff(k));
       af[e] = (o < O && k < I) ? sA[o * lda + k] : 0.f;
     }
     mma_bf16(af, xf, acc, sp);
@@ -535,7 +562,7 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = k0 + kh + e;
-        cf[e] = (nok && k < Mm) ? Cw[static_cast<int64_t>(k) * W + w] : 0.f;
+        cf[e] = ld_elem<float>(rC, (nok && k < Mm) ? 4u * static_cast<uint32_t>(k * W + w) : kOOB);
         tf[e] = (o < O && k < Mm) ? sT[o * ldt + k] : 0.f;
       }
       mma_bf16(tf, cf, acc, sp);
@@ -557,7 +584,7 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
         if (pre) pre[off] = v;
         v = gelu_f(v);
       }
-      Y[off] = v;
+      Y[off] = static_cast<TY>(v);
     }
   }
 }
@@ -566,9 +593,10 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
 // Q1[j][c] v[b][c][p] + q1b[j]) + q2b (C <= 32 channels), 32 hidden rows per pass; each lane sums its
 // rows, the two halves of the wave are added with a lane exchange.  Q1, q1b and Q2 are staged in LDS once
 // per block.  With keep (qpre non-null), qpre and q ([b][Hp][P]) are stored.
+template <typename TV>
 __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restrict__ Q1, const float* __restrict__ q1b,
                                                           const float* __restrict__ Q2, const float* __restrict__ q2b,
-                                                          const float* __restrict__ v, float* __restrict__ out,
+                                                          const TV* __restrict__ v, float* __restrict__ out,
                                                           float* __restrict__ qpre, float* __restrict__ q, int C,
                                                           int Hp, int64_t P, int split) {
   extern __shared__ float sm[];
@@ -581,14 +609,14 @@ __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restric
   const int64_t n = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32 + (lane & 31);
   const int kh = 8 * (lane >> 5), o = lane & 31;
   const bool nok = n < P;
-  const float* vb = v + b * C * P + (nok ? n : 0);
+  const rsrc_t rv = wave_rsrc(v + b * C * P, static_cast<uint32_t>(C * P * sizeof(TV)));
   float xv[2][8];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 16 * c + kh + e;
-      xv[c][e] = (nok && k < C) ? vb[static_cast<int64_t>(k) * P] : 0.f;
+      xv[c][e] = ld_elem<TV>(rv, (nok && k < C) ? static_cast<uint32_t>((k * P + n) * sizeof(TV)) : kOOB);
     }
   stage_matrix(sQ1, ldq, Q1, Hp, C, false);
   for (int i = tid; i < Hp; i += 256) {
@@ -675,35 +703,22 @@ __device__ __forceinline__ f32x4 mma16(bf16x4 ph, bf16x4 pl, bf16x4 qh, bf16x4 q
   return mfma16(ph, qh, acc);
 }
 
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-constexpr uint32_t kOOB = 0x80000000u;   // buffer offset past every range: the load returns zero
-
-// A buffer descriptor that is the same for the whole wave, built from base and size passed through
-// readfirstlane so it lives in scalar registers (no per-lane loop over descriptors around each access).
-__device__ __forceinline__ rsrc_t wave_rsrc(const void* p, uint32_t bytes) {
-  const uint64_t a = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo), 0,
-                                           static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), 0x00020000);
-}
 
 // LDS <- n16 16-byte chunks from global memory, eight loads per thread in flight before their stores.
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void stage_bytes(void* dst, const void* __restrict__ src, int n16) {
-  const uint4* s4 = static_cast<const uint4*>(src);
-  uint4* d4 = static_cast<uint4*>(dst);
+  const u32x4v* s4 = static_cast<const u32x4v*>(src);
+  u32x4v* d4 = static_cast<u32x4v*>(dst);
   for (int base = 0; base < n16; base += 8 * 256) {
-    uint4 v[8];
+    u32x4v v[8];
+    int idx[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
-      if (i < n16) v[u] = s4[i];
+    for (int u = 0; u < 8; ++u) {   // clamped: lanes past the end copy the last chunk again
+      idx[u] = min(base + static_cast<int>(threadIdx.x) + 256 * u, n16 - 1);
+      v[u] = s4[idx[u]];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = base + static_cast<int>(threadIdx.x) + 256 * u;
-      if (i < n16) d4[i] = v[u];
-    }
+    for (int u = 0; u < 8; ++u) d4[idx[u]] = v[u];
   }
 }
 
@@ -747,8 +762,8 @@ __global__ void nop_tables_kernel(const float* __restrict__ Ch, const float* __r
   }
 }
 
-template <int NT, bool VEC>
-__global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__ V, float* __restrict__ A,
+template <int NT, bool VEC, typename TV>
+__global__ __launch_bounds__(256) void nop_dct2_kernel(const TV* __restrict__ V, float* __restrict__ A,
                                                        const __bf16* __restrict__ img, int planes, int H, int W, int Mm,
                                                        int split) {
   constexpr int M16 = 16 * NT;
@@ -769,7 +784,8 @@ __global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__
   if (pl >= planes) return;
   // loads through a buffer resource over the plane: an out-of-range offset reads zero, so no load is
   // predicated and the next block's loads stay in flight during this block's MFMAs
-  const rsrc_t rv = wave_rsrc(V + pl * H * W, static_cast<uint32_t>(H * W * 4));
+  constexpr uint32_t ES = sizeof(TV);
+  const rsrc_t rv = wave_rsrc(V + pl * H * W, static_cast<uint32_t>(H * W) * ES);
   const int KS = W16 >> 4, MT = H16 >> 4;
   f32x4 acc[NT][NT];
 #pragma unroll
@@ -782,16 +798,25 @@ __global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int w0 = 16 * ks + 4 * g;
-      if (VEC) {   // W % 4 == 0: a 16-byte group is all inside the row or all past it
-        const uint32_t off = (h < H && w0 < W) ? 4u * static_cast<uint32_t>(h * W + w0) : kOOB;
-        const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rv, off, 0, 0));
+      if (VEC) {   // W % 4 == 0: a 4-element group is all inside the row or all past it
+        const uint32_t off = (h < H && w0 < W) ? ES * static_cast<uint32_t>(h * W + w0) : kOOB;
+        if (ES == 4) {
+          const f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rv, off, 0, 0));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[ks][e] = x[e];
+          for (int e = 0; e < 4; ++e) v[ks][e] = x[e];
+        } else {
+          const bf16x4 x = __builtin_bit_cast(bf16x4, __builtin_amdgcn_raw_buffer_load_b64(rv, off, 0, 0));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[ks][e] = static_cast<float>(x[e]);
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const uint32_t off = (h < H && w0 + e < W) ? 4u * static_cast<uint32_t>(h * W + w0 + e) : kOOB;
-          v[ks][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, 0));
+          const uint32_t off = (h < H && w0 + e < W) ? ES * static_cast<uint32_t>(h * W + w0 + e) : kOOB;
+          if (ES == 4)
+            v[ks][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, 0));
+          else
+            v[ks][e] = static_cast<float>(__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rv, off, 0, 0)));
         }
       }
     }
@@ -854,8 +879,8 @@ __global__ __launch_bounds__(256) void nop_dct2_kernel(const float* __restrict__
 // (Z in natural layout, T laid out for the channel-mixing kernel), one plane per wave on MFMA 16x16x16
 // bf16: P = Ch^T rows from LDS (bf16, remainders with split), Q = the plane's Mm x Mm coefficients,
 // loaded once into registers and reused for every 16 rows of h.  NT = ceil(Mm / 16).
-template <int NT>
-__global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict__ Z, float* __restrict__ T,
+template <int NT, typename TT>
+__global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict__ Z, TT* __restrict__ T,
                                                          const __bf16* __restrict__ img, int B, int C, int H, int Mm,
                                                          int split) {
   constexpr int M16 = 16 * NT;
@@ -889,7 +914,7 @@ __global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict
       to_bf16x4(z, qh[ks][nt], ql[ks][nt], sp);
     }
   const int64_t rowstride = static_cast<int64_t>(C) * Mm;      // T: one h row holds every channel
-  float* tp = T + b * H * rowstride + static_cast<int64_t>(c) * Mm;
+  TT* tp = T + b * H * rowstride + static_cast<int64_t>(c) * Mm;
   for (int mt = 0; mt < (H16 >> 4); ++mt) {
     f32x4 acc[NT];
 #pragma unroll
@@ -907,7 +932,7 @@ __global__ __launch_bounds__(256) void nop_idct_h_kernel(const float* __restrict
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h = 16 * mt + 4 * g + r, kw = 16 * nt + j;
-        if (h < H && kw < Mm) tp[h * rowstride + kw] = acc[nt][r];
+        if (h < H && kw < Mm) tp[h * rowstride + kw] = static_cast<TT>(acc[nt][r]);
       }
   }
 }
@@ -931,24 +956,43 @@ hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_nop_mix(const float* A, bool transA, const float* X, float* Y, const float* bias, const float* D,
-                          float* pre, const float* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
-                          bool split, hipStream_t s) {
+hipError_t launch_nop_mix(const float* A, bool transA, const void* X, void* Y, const float* bias, const float* D,
+                          float* pre, const void* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
+                          bool split, int act_types, hipStream_t s) {
   const size_t lds = sizeof(float) * (32 * (I + 1) + (T ? 32 * (Mm + 1) : 0) + 32);
   if (O > 32 || H < 1 || W < 1 || I < 1 || lds > 65536) return hipErrorInvalidValue;
   const int64_t blocks = static_cast<int64_t>(H) * ((W + 127) / 128);
-  hipLaunchKernelGGL(nop_mix_kernel, dim3(static_cast<unsigned>(blocks), B), dim3(256), lds, s, A, X, Y, bias, D, pre, T,
-                     Cw, O, I, H, W, Mm, act ? 1 : 0, transA ? 1 : 0, split ? 1 : 0);
+  const dim3 grid(static_cast<unsigned>(blocks), B), blk(256);
+  const int a = act ? 1 : 0, t = transA ? 1 : 0, sp = split ? 1 : 0;
+  typedef __bf16 bf;
+  switch (act_types) {
+    case 0:   // FP32 X, Y, T
+      hipLaunchKernelGGL((nop_mix_kernel<float, float, float>), grid, blk, lds, s, A, static_cast<const float*>(X),
+                         static_cast<float*>(Y), bias, D, pre, static_cast<const float*>(T), Cw, O, I, H, W, Mm, a, t, sp);
+      break;
+    case 1:   // FP32 X (the features), bf16 Y
+      hipLaunchKernelGGL((nop_mix_kernel<float, bf, float>), grid, blk, lds, s, A, static_cast<const float*>(X),
+                         static_cast<bf*>(Y), bias, D, pre, static_cast<const float*>(T), Cw, O, I, H, W, Mm, a, t, sp);
+      break;
+    default:  // bf16 X, Y, T
+      hipLaunchKernelGGL((nop_mix_kernel<bf, bf, bf>), grid, blk, lds, s, A, static_cast<const bf*>(X), static_cast<bf*>(Y),
+                         bias, D, pre, static_cast<const bf*>(T), Cw, O, I, H, W, Mm, a, t, sp);
+      break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const float* v,
-                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split,
+hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2, const float* q2b, const void* v,
+                              float* out, float* qpre, float* q, int C, int Hp, int64_t P, int B, bool split, bool half,
                               hipStream_t s) {
   const size_t lds = sizeof(float) * (static_cast<size_t>(Hp) * (C + 1) + 2 * Hp);
   if (C > 32 || lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(nop_project_kernel, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b, v, out, qpre,
-                     q, C, Hp, P, split ? 1 : 0);
+  if (half)
+    hipLaunchKernelGGL(nop_project_kernel<__bf16>, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b,
+                       static_cast<const __bf16*>(v), out, qpre, q, C, Hp, P, split ? 1 : 0);
+  else
+    hipLaunchKernelGGL(nop_project_kernel<float>, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b,
+                       static_cast<const float*>(v), out, qpre, q, C, Hp, P, split ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -969,10 +1013,10 @@ hipError_t launch_nop_tables(const float* Ch, const float* Cw, void* dct2_img, v
 
 bool nop_dct2_supported(int H, int W, int Mm) { return W <= 128 && Mm <= 64 && H >= 1 && W >= 1 && Mm >= 1; }
 
-hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
-                           hipStream_t s) {
+hipError_t launch_nop_dct2(const void* V, float* A, const void* img, int planes, int H, int W, int Mm, bool split,
+                           bool half, hipStream_t s) {
   if (!nop_dct2_supported(H, W, Mm) || planes < 1) return hipErrorInvalidValue;
-  if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & 15) != 0) return hipErrorInvalidValue;
+  if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & (half ? 7 : 15)) != 0) return hipErrorInvalidValue;
   const int NT = (Mm + 15) / 16;
   const int H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
   const size_t lds = sizeof(__bf16) * (split ? 2 : 1) * 16 * NT * ((W16 + 4) + (H16 + 4));
@@ -981,9 +1025,13 @@ hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes
   const int sp = split ? 1 : 0;
   const bool vec = (W & 3) == 0;
   const __bf16* tab = static_cast<const __bf16*>(img);
-#define PSTD_DCT2(NTV)                                                                                         \
-  if (vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true>), grid, blk, lds, s, V, A, tab, planes, H, W, Mm, sp); \
-  else hipLaunchKernelGGL((nop_dct2_kernel<NTV, false>), grid, blk, lds, s, V, A, tab, planes, H, W, Mm, sp);
+  const float* Vf = static_cast<const float*>(V);
+  const __bf16* Vh = static_cast<const __bf16*>(V);
+#define PSTD_DCT2(NTV)                                                                                          \
+  if (half && vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true, __bf16>), grid, blk, lds, s, Vh, A, tab, planes, H, W, Mm, sp); \
+  else if (half) hipLaunchKernelGGL((nop_dct2_kernel<NTV, false, __bf16>), grid, blk, lds, s, Vh, A, tab, planes, H, W, Mm, sp); \
+  else if (vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true, float>), grid, blk, lds, s, Vf, A, tab, planes, H, W, Mm, sp); \
+  else hipLaunchKernelGGL((nop_dct2_kernel<NTV, false, float>), grid, blk, lds, s, Vf, A, tab, planes, H, W, Mm, sp);
   switch (NT) {
     case 1: PSTD_DCT2(1) break;
     case 2: PSTD_DCT2(2) break;
@@ -994,8 +1042,8 @@ hipError_t launch_nop_dct2(const float* V, float* A, const void* img, int planes
   return hipGetLastError();
 }
 
-hipError_t launch_nop_idct_h(const float* Z, float* T, const void* img, int B, int C, int H, int Mm, bool split,
-                             hipStream_t s) {
+hipError_t launch_nop_idct_h(const float* Z, void* T, const void* img, int B, int C, int H, int Mm, bool split,
+                             bool half, hipStream_t s) {
   if (Mm < 1 || Mm > 64 || H < 1 || B < 1 || C < 1) return hipErrorInvalidValue;
   const int NT = (Mm + 15) / 16;
   const int H16 = (H + 15) & ~15;
@@ -1005,12 +1053,18 @@ hipError_t launch_nop_idct_h(const float* Z, float* T, const void* img, int B, i
   const dim3 grid(static_cast<unsigned>((planes + 3) / 4)), blk(256);
   const int sp = split ? 1 : 0;
   const __bf16* tab = static_cast<const __bf16*>(img);
+  float* Tf = static_cast<float*>(T);
+  __bf16* Th = static_cast<__bf16*>(T);
+#define PSTD_IDCT(NTV)                                                                                          \
+  if (half) hipLaunchKernelGGL((nop_idct_h_kernel<NTV, __bf16>), grid, blk, lds, s, Z, Th, tab, B, C, H, Mm, sp);    \
+  else hipLaunchKernelGGL((nop_idct_h_kernel<NTV, float>), grid, blk, lds, s, Z, Tf, tab, B, C, H, Mm, sp);
   switch (NT) {
-    case 1: hipLaunchKernelGGL(nop_idct_h_kernel<1>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
-    case 2: hipLaunchKernelGGL(nop_idct_h_kernel<2>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
-    case 3: hipLaunchKernelGGL(nop_idct_h_kernel<3>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
-    default: hipLaunchKernelGGL(nop_idct_h_kernel<4>, grid, blk, lds, s, Z, T, tab, B, C, H, Mm, sp); break;
+    case 1: PSTD_IDCT(1) break;
+    case 2: PSTD_IDCT(2) break;
+    case 3: PSTD_IDCT(3) break;
+    default: PSTD_IDCT(4) break;
   }
+#undef PSTD_IDCT
   return hipGetLastError();
 }
 
