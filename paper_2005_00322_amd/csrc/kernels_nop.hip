@@ -11,7 +11,9 @@
 //
 // MFMA v_mfma_f32_32x32x16_bf16: lane l supplies A[l%32][8*(l/32) .. +7] and B^T[l%32][8*(l/32) .. +7]
 // (both staged as [row][k] in LDS) and receives C[8*(r/4) + 4*(l/32) + r%4][l%32] in register r.
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
@@ -589,6 +591,201 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
   }
 }
 
+// Register-resident form of the same product for O <= 32, I <= 32 and at most KT K-steps of modes (no D
+// term): each block walks `rpb` consecutive rows r = b H + h of up to 128 positions.  A, the bias and the
+// Cw columns of the block's positions are loaded once and kept in registers; bf16 T rows arrive as
+// 16-byte vectors when TVEC (Mm % 8 == 0).  Three register sets form a ring: the X and T operands of
+// rows r + 1 and r + 2 are in flight while row r is multiplied and stored.
+// The MFMA sequence (X K-steps, then T K-steps, each hi/lo-split when split) is the one of
+// nop_mix_kernel, so both forms give the same bits.
+typedef unsigned u32x4r __attribute__((ext_vector_type(4)));
+template <typename TX, typename TY, typename TT, int KT, bool TVEC, bool SPLIT>
+__global__ __launch_bounds__(256) void nop_mixrows_kernel(const float* __restrict__ A, const TX* __restrict__ X,
+                                                          TY* __restrict__ Y, const float* __restrict__ bias,
+                                                          float* __restrict__ pre, const TT* __restrict__ T,
+                                                          const float* __restrict__ Cw, int O, int I, int H, int W,
+                                                          int Mm, int B, int rpb, int act, int tA) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int groups = (W + 127) >> 7;
+  const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x));
+  const int g = blk % groups;
+  const int rows = B * H;
+  const int r0 = (blk / groups) * rpb, r1 = min(r0 + rpb, rows);
+  const int w = g * 128 + wave * 32 + (lane & 31);
+  const int kh = 8 * (lane >> 5), o = lane & 31;
+  const bool nok = w < W;
+  const int P = H * W;
+  constexpr bool sp = SPLIT;
+  constexpr uint32_t XS = sizeof(TX), YS = sizeof(TY), TS = sizeof(TT);
+  const rsrc_t rX = wave_rsrc(X, static_cast<uint32_t>(B * I * P) * XS);
+  const rsrc_t rY = wave_rsrc(Y, static_cast<uint32_t>(B * O * P) * YS);
+  const rsrc_t rPre = wave_rsrc(pre ? static_cast<void*>(pre) : static_cast<void*>(Y), pre ? static_cast<uint32_t>(B * O * P) * 4u : 0u);
+  const rsrc_t rT = wave_rsrc(T ? static_cast<const void*>(T) : static_cast<const void*>(X),
+                              T ? static_cast<uint32_t>(rows * O * Mm) * TS : 0u);
+
+  // operands that stay for all rows: A (P port of the X steps), Cw (Q port of the T steps), bias; all
+  // their loads are issued together (out-of-range lanes read zero through the descriptors)
+  const rsrc_t rA = wave_rsrc(A, static_cast<uint32_t>(O * I) * 4u);
+  const rsrc_t rC = wave_rsrc(Cw, T ? static_cast<uint32_t>(Mm * W) * 4u : 0u);
+  float af[2][8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * c + kh + e;
+      const uint32_t off = (4u * static_cast<uint32_t>(tA ? k * O + o : o * I + k)) | ((o < O && k < I) ? 0u : kOOB);
+      af[c][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rA, off, 0, 0));
+    }
+  float cf[KT > 0 ? KT : 1][8];
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int m = 16 * t + kh + e;
+      const uint32_t off = (4u * static_cast<uint32_t>(m * W + w)) | ((nok && m < Mm) ? 0u : kOOB);
+      cf[t][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rC, off, 0, 0));
+    }
+  bf16x8 ah[2], al[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) to_bf16x8(af[c], ah[c], al[c], sp);
+  bf16x8 ch[KT > 0 ? KT : 1], cl[KT > 0 ? KT : 1];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) to_bf16x8(cf[t], ch[t], cl[t], sp);
+  __shared__ __attribute__((aligned(16))) float sb[32];
+  if (tid < 32) sb[tid] = (bias && tid < O) ? bias[tid] : 0.f;
+  __syncthreads();
+  const int nxs = I > 16 ? 2 : 1;                         // X K-steps
+  const int nts = T ? (Mm + 15) / 16 : 0;                 // T K-steps (<= KT)
+
+  // three register sets of row operands.  Offsets are split into a per-lane part, which an out-of-range
+  // lane ORs with kOOB (a select between constants: no branch around the load), and a row-uniform part
+  // passed as the scalar offset.
+  // bf16 X elements go straight into packed bf16 operands (16-bit loads into register halves)
+  constexpr bool XH = sizeof(TX) == 2;
+  float xr[3][2][XH ? 1 : 8];
+  bf16x8 xb[3][2];
+  u32x4r tr[3][KT > 0 ? KT : 1];
+  float te[3][KT > 0 ? KT : 1][TVEC ? 1 : 8];
+  static_assert(!TVEC || TS == 2, "16-byte T rows are read for bf16 storage only");
+  const uint32_t xlane = XS * static_cast<uint32_t>(kh * P + w);
+  const uint32_t tlane = TS * static_cast<uint32_t>(o * Mm + kh);
+  auto load_row = [&](int set, int r) {
+    const int b = r / H, h = r - b * H;
+    const uint32_t xrow = XS * static_cast<uint32_t>(b * I * P + h * W);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * c + kh + e;
+        const uint32_t off = (xlane + XS * static_cast<uint32_t>((16 * c + e) * P)) | ((nok && k < I) ? 0u : kOOB);
+        if (XH)
+          xb[set][c][e] = __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rX, off, xrow, 0));
+        else
+          xr[set][c][XH ? 0 : e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rX, off, xrow, 0));
+      }
+    const uint32_t trow = TS * static_cast<uint32_t>(r * O * Mm);
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const int m0 = 16 * t + kh;
+      if (TVEC) {
+        const uint32_t off = (tlane + TS * 16u * t) | ((o < O && m0 < Mm) ? 0u : kOOB);
+        tr[set][t] = __builtin_bit_cast(u32x4r, __builtin_amdgcn_raw_buffer_load_b128(rT, off, trow, 0));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t off = (tlane + TS * static_cast<uint32_t>(16 * t + e)) | ((o < O && m0 + e < Mm) ? 0u : kOOB);
+          if (TS == 4)
+            te[set][t][TVEC ? 0 : e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rT, off, trow, 0));
+          else
+            te[set][t][TVEC ? 0 : e] = static_cast<float>(
+                __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rT, off, trow, 0)));
+        }
+      }
+    }
+  };
+  auto row = [&](int set, int r, bool valid) {
+    const int b = r / H, h = r - b * H;
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c >= nxs) break;
+      bf16x8 xh, xl;
+      if (XH) {   // bf16 storage: hi is the stored value, lo is zero
+        xh = xb[set][c];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xl[e] = static_cast<__bf16>(0.f);
+      } else {
+        float xf[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xf[e] = xr[set][c][XH ? 0 : e];
+        to_bf16x8(xf, xh, xl, sp);
+      }
+      if (sp) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[c], xh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[c], xl, acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[c], xh, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      if (t >= nts) break;
+      bf16x8 th, tl;
+      if (TVEC) {   // bf16 storage: the loaded words are the hi operand, the lo part is zero
+        th = __builtin_bit_cast(bf16x8, tr[set][t]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tl[e] = static_cast<__bf16>(0.f);
+      } else {
+        float tf[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tf[e] = te[set][t][TVEC ? 0 : e];
+        to_bf16x8(tf, th, tl, sp);
+      }
+      if (sp) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tl, ch[t], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, cl[t], acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, ch[t], acc, 0, 0, 0);
+    }
+    const uint32_t yrow = static_cast<uint32_t>(b * O * P + h * W);     // elements, row-uniform
+    // one branch per row picks the epilogue form; each form is straight-line over the 16 outputs
+    auto epilogue = [&](auto gelu, auto keep_pre) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int oo = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const uint32_t bad = (valid && nok && oo < O) ? 0u : kOOB;
+        const uint32_t e = static_cast<uint32_t>(oo * P + w);
+        float v = acc[i] + sb[oo];
+        if (decltype(keep_pre)::value)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rPre, (4u * e) | bad, 4u * yrow, 0);
+        if (decltype(gelu)::value) v = gelu_f(v);
+        if (YS == 4)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rY, (4u * e) | bad, 4u * yrow, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, static_cast<__bf16>(v)), rY,
+                                                (2u * e) | bad, 2u * yrow, 0);
+      }
+    };
+    if (!act) epilogue(std::false_type{}, std::false_type{});
+    else if (!pre) epilogue(std::true_type{}, std::false_type{});
+    else epilogue(std::true_type{}, std::true_type{});
+  };
+  if (r0 >= r1) return;
+  // rows past the block's last are clamped to it (loaded again, computed, not stored): every load and
+  // store is issued unconditionally, so each wait covers exactly the loads it needs
+  load_row(0, r0);
+  load_row(1, min(r0 + 1, r1 - 1));
+  for (int r = r0; r < r1; r += 3) {
+    load_row(2, min(r + 2, r1 - 1));
+    row(0, r, true);
+    load_row(0, min(r + 3, r1 - 1));
+    row(1, min(r + 1, r1 - 1), r + 1 < r1);
+    load_row(1, min(r + 4, r1 - 1));
+    row(2, min(r + 2, r1 - 1), r + 2 < r1);
+  }
+}
+
 // Fused projection on the bf16 matrix cores (FP32 accumulation): out[b][p] = sum_j Q2[j] GELU(sum_c
 // Q1[j][c] v[b][c][p] + q1b[j]) + q2b (C <= 32 channels), 32 hidden rows per pass; each lane sums its
 // rows, the two halves of the wave are added with a lane exchange.  Q1, q1b and Q2 are staged in LDS once
@@ -956,11 +1153,73 @@ hipError_t launch_nop_gemm(const NopGemm& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+template <typename TX, typename TY, typename TT, int KT, bool TVEC>
+void launch_mixrows_t(const float* A, bool transA, const void* X, void* Y, const float* bias, float* pre, const void* T,
+                      const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act, bool split, hipStream_t s) {
+  const int64_t rows = static_cast<int64_t>(B) * H, groups = (W + 127) / 128;
+  // about 2048 blocks: two rounds of four 4-wave blocks per CU, each walking its rows with loads ahead
+  const int rpb = static_cast<int>(std::max<int64_t>(1, (rows * groups + 2047) / 2048));
+  const unsigned nblk = static_cast<unsigned>(((rows + rpb - 1) / rpb) * groups);
+  const TX* x = static_cast<const TX*>(X);
+  const TT* t = static_cast<const TT*>(T);
+  TY* y = static_cast<TY*>(Y);
+  if (split)
+    hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, true>), dim3(nblk), dim3(256), 0, s, A, x, y, bias,
+                       pre, t, Cw, O, I, H, W, Mm, B, rpb, act ? 1 : 0, transA ? 1 : 0);
+  else
+    hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, false>), dim3(nblk), dim3(256), 0, s, A, x, y, bias,
+                       pre, t, Cw, O, I, H, W, Mm, B, rpb, act ? 1 : 0, transA ? 1 : 0);
+}
+
+template <typename TX, typename TY, typename TT>
+void launch_mixrows(const float* A, bool transA, const void* X, void* Y, const float* bias, float* pre, const void* T,
+                    const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act, bool split, hipStream_t s) {
+  const int kt = T ? (Mm + 15) / 16 : 0;
+  const bool vec = T && Mm % 8 == 0 && sizeof(TT) == 2;
+#define PSTD_MIXROWS(KTV)                                                                                        \
+  if constexpr (sizeof(TT) == 2) {                                                                               \
+    if (vec) launch_mixrows_t<TX, TY, TT, KTV, true>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); \
+    else launch_mixrows_t<TX, TY, TT, KTV, false>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); \
+  } else {                                                                                                       \
+    launch_mixrows_t<TX, TY, TT, KTV, false>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); \
+  }
+  switch (kt) {
+    case 0: launch_mixrows_t<TX, TY, TT, 0, false>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); break;
+    case 1: PSTD_MIXROWS(1) break;
+    case 2: PSTD_MIXROWS(2) break;
+    case 3: PSTD_MIXROWS(3) break;
+    default: PSTD_MIXROWS(4) break;
+  }
+#undef PSTD_MIXROWS
+}
+
+}  // namespace
+
 hipError_t launch_nop_mix(const float* A, bool transA, const void* X, void* Y, const float* bias, const float* D,
                           float* pre, const void* T, const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act,
                           bool split, int act_types, hipStream_t s) {
+  if (O > 32 || H < 1 || W < 1 || I < 1 || B < 1) return hipErrorInvalidValue;
+  {
+    // the register-resident row form: no D term, at most 32 inputs and 64 modes, 32-bit offsets
+    const int64_t P = static_cast<int64_t>(H) * W;
+    const int64_t xs = act_types == 2 ? 2 : 4, ts = act_types == 2 ? 2 : 4;
+    const bool fits = static_cast<int64_t>(B) * I * P * xs < (int64_t(1) << 31) &&
+                      static_cast<int64_t>(B) * O * P * 4 < (int64_t(1) << 31) &&
+                      (!T || static_cast<int64_t>(B) * H * O * Mm * ts < (int64_t(1) << 31));
+    if (!D && I <= 32 && (!T || (Mm >= 1 && Mm <= 64)) && fits) {
+      typedef __bf16 bf;
+      switch (act_types) {
+        case 0: launch_mixrows<float, float, float>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); break;
+        case 1: launch_mixrows<float, bf, float>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); break;
+        default: launch_mixrows<bf, bf, bf>(A, transA, X, Y, bias, pre, T, Cw, Mm, O, I, H, W, B, act, split, s); break;
+      }
+      return hipGetLastError();
+    }
+  }
   const size_t lds = sizeof(float) * (32 * (I + 1) + (T ? 32 * (Mm + 1) : 0) + 32);
-  if (O > 32 || H < 1 || W < 1 || I < 1 || lds > 65536) return hipErrorInvalidValue;
+  if (lds > 65536) return hipErrorInvalidValue;
   const int64_t blocks = static_cast<int64_t>(H) * ((W + 127) / 128);
   const dim3 grid(static_cast<unsigned>(blocks), B), blk(256);
   const int a = act ? 1 : 0, t = transA ? 1 : 0, sp = split ? 1 : 0;
