@@ -599,7 +599,7 @@ __global__ __launch_bounds__(256) void nop_mix_kernel(const float* __restrict__ 
 // The MFMA sequence (X K-steps, then T K-steps, each hi/lo-split when split) is the one of
 // nop_mix_kernel, so both forms give the same bits.
 typedef unsigned u32x4r __attribute__((ext_vector_type(4)));
-template <typename TX, typename TY, typename TT, int KT, bool TVEC, bool SPLIT>
+template <typename TX, typename TY, typename TT, int KT, bool TVEC, bool SPLIT, bool KFULL>
 __global__ __launch_bounds__(256) void nop_mixrows_kernel(const float* __restrict__ A, const TX* __restrict__ X,
                                                           TY* __restrict__ Y, const float* __restrict__ bias,
                                                           float* __restrict__ pre, const TT* __restrict__ T,
@@ -668,6 +668,7 @@ __global__ __launch_bounds__(256) void nop_mixrows_kernel(const float* __restric
   float te[3][KT > 0 ? KT : 1][TVEC ? 1 : 8];
   static_assert(!TVEC || TS == 2, "16-byte T rows are read for bf16 storage only");
   const uint32_t xlane = XS * static_cast<uint32_t>(kh * P + w);
+  const uint32_t xlane_ok = xlane | (nok ? 0u : kOOB);
   const uint32_t tlane = TS * static_cast<uint32_t>(o * Mm + kh);
   auto load_row = [&](int set, int r) {
     const int b = r / H, h = r - b * H;
@@ -677,11 +678,15 @@ __global__ __launch_bounds__(256) void nop_mixrows_kernel(const float* __restric
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 16 * c + kh + e;
-        const uint32_t off = (xlane + XS * static_cast<uint32_t>((16 * c + e) * P)) | ((nok && k < I) ? 0u : kOOB);
+        // with all 32 inputs present the per-lane offset is one register and the channel goes into the
+        // scalar offset; otherwise each element carries its own range mask
+        const uint32_t kst = XS * static_cast<uint32_t>((16 * c + e) * P);
+        const uint32_t off = KFULL ? xlane_ok : (xlane + kst) | ((nok && k < I) ? 0u : kOOB);
+        const uint32_t so = KFULL ? xrow + kst : xrow;
         if (XH)
-          xb[set][c][e] = __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rX, off, xrow, 0));
+          xb[set][c][e] = __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rX, off, so, 0));
         else
-          xr[set][c][XH ? 0 : e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rX, off, xrow, 0));
+          xr[set][c][XH ? 0 : e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rX, off, so, 0));
       }
     const uint32_t trow = TS * static_cast<uint32_t>(r * O * Mm);
 #pragma unroll
@@ -864,6 +869,150 @@ __global__ __launch_bounds__(256) void nop_project_kernel(const float* __restric
   }
   part += __shfl_xor(part, 32);
   if (lane < 32 && nok) out[b * P + n] = part + q2b[0];
+}
+
+// Chunk-walking form of the projection for Hp <= 128 and C <= 32: each block walks `rpb` chunks of 128
+// consecutive positions of one plane.  Q1 is converted once to bf16 MFMA operands in LDS, q1b and Q2 sit
+// in LDS, and the v operands of the next two chunks are in flight while a chunk is multiplied; the
+// hidden tiles of a chunk run one after the other, so one tile's accumulators are live at a time.  The
+// MFMA sequence, the epilogue arithmetic and the order of the Q2 dot product are those of
+// nop_project_kernel, so both forms give the same bits for finite activations.  KFULL: C == 32 (no channel masks); KEEP: the
+// pre-activations and activations are stored for the backward pass.
+template <typename TV, bool SPLIT, bool KFULL, bool KEEP>
+__global__ __launch_bounds__(256) void nop_projrows_kernel(const float* __restrict__ Q1, const float* __restrict__ q1b,
+                                                           const float* __restrict__ Q2, const float* __restrict__ q2b,
+                                                           const TV* __restrict__ v, float* __restrict__ out,
+                                                           float* __restrict__ qpre, float* __restrict__ q, int C,
+                                                           int Hp, int P, int B, int rpb) {
+  constexpr int MAXT = 4;                          // hidden tiles of 32
+  __shared__ float sb[32 * MAXT], s2[32 * MAXT];
+  __shared__ bf16x8 sah[2 * MAXT][64], sal[SPLIT ? 2 * MAXT : 1][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nc = (P + 127) >> 7;                  // chunks per plane
+  const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x));
+  const int q0 = blk * rpb, q1 = min(q0 + rpb, B * nc);
+  const int kh = 8 * (lane >> 5), o = lane & 31;
+  const int wl = wave * 32 + (lane & 31);
+  const int nth = (Hp + 31) >> 5;
+  constexpr bool sp = SPLIT;
+  constexpr uint32_t VS = sizeof(TV);
+  constexpr bool VH = VS == 2;
+  for (int i = tid; i < 32 * MAXT; i += 256) {
+    sb[i] = i < Hp ? q1b[i] : 0.f;
+    s2[i] = i < Hp ? Q2[i] : 0.f;
+  }
+  // Q1 rows 32 th + o as the P operand of tile th, in operand order (entry (th, c) of lane l at
+  // [2 th + c][l]); each wave converts every fourth entry
+  const rsrc_t rQ = wave_rsrc(Q1, static_cast<uint32_t>(Hp * C) * 4u);
+  for (int pe = wave; pe < 2 * nth; pe += 4) {
+    const int th = pe >> 1, c = pe & 1;
+    float af[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int j = 32 * th + o, k = 16 * c + kh + e;
+      const uint32_t off = (4u * static_cast<uint32_t>(j * C + k)) | ((j < Hp && k < C) ? 0u : kOOB);
+      af[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rQ, off, 0, 0));
+    }
+    bf16x8 h, l;
+    to_bf16x8(af, h, l, sp);
+    sah[pe][lane] = h;
+    if (SPLIT) sal[SPLIT ? pe : 0][lane] = l;
+  }
+  const float b2 = q2b[0];
+  __syncthreads();
+  const int nxs = C > 16 ? 2 : 1;
+  const rsrc_t rV = wave_rsrc(v, static_cast<uint32_t>(B * C * P) * VS);
+  const rsrc_t rQp = wave_rsrc(KEEP ? static_cast<void*>(qpre) : static_cast<void*>(out),
+                               KEEP ? static_cast<uint32_t>(B * Hp * P) * 4u : 0u);
+  const rsrc_t rQg = wave_rsrc(KEEP ? static_cast<void*>(q) : static_cast<void*>(out),
+                               KEEP ? static_cast<uint32_t>(B * Hp * P) * 4u : 0u);
+  const rsrc_t rO = wave_rsrc(out, static_cast<uint32_t>(B * P) * 4u);
+
+  float xr[3][2][VH ? 1 : 8];
+  bf16x8 xb[3][2];
+  auto load_chunk = [&](int set, int qi) {
+    const int b = qi / nc, n = (qi - b * nc) * 128 + wl;
+    const uint32_t vrow = VS * static_cast<uint32_t>(b * C * P);
+    // with all 32 channels present the per-lane offset is one register and the channel goes into the
+    // scalar offset; otherwise each element carries its own range mask
+    const uint32_t vlane = (VS * static_cast<uint32_t>(kh * P + n)) | (n < P ? 0u : kOOB);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * c + kh + e;
+        const uint32_t off = KFULL ? vlane : (VS * static_cast<uint32_t>(k * P + n)) | ((n < P && k < C) ? 0u : kOOB);
+        const uint32_t so = KFULL ? vrow + VS * static_cast<uint32_t>((16 * c + e) * P) : vrow;
+        if (VH)
+          xb[set][c][e] = __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rV, off, so, 0));
+        else
+          xr[set][c][VH ? 0 : e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rV, off, so, 0));
+      }
+  };
+  auto chunk = [&](int set, int qi, bool valid) {
+    const int b = qi / nc, n = (qi - b * nc) * 128 + wl;
+    const bool nok = valid && n < P;
+    bf16x8 xh[2], xl[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (VH) {
+        xh[c] = xb[set][c];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xl[c][e] = static_cast<__bf16>(0.f);
+      } else {
+        float xf[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xf[e] = xr[set][c][VH ? 0 : e];
+        to_bf16x8(xf, xh[c], xl[c], sp);
+      }
+    }
+    const uint32_t qrow = static_cast<uint32_t>(b * Hp * P);
+    float part = 0.f;
+#pragma unroll 1
+    for (int th = 0; th < nth; ++th) {
+      f32x16 acc;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= nxs) break;
+        const bf16x8 ah = sah[2 * th + c][lane];
+        if (sp) {
+          const bf16x8 al = sal[SPLIT ? 2 * th + c : 0][lane];
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh[c], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl[c], acc, 0, 0, 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh[c], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int jj = 32 * th + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const float hv = acc[i] + sb[jj];
+        const float g = gelu_f(hv);
+        if (KEEP) {
+          const uint32_t off = (4u * static_cast<uint32_t>(jj * P + n)) | ((nok && jj < Hp) ? 0u : kOOB);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, hv), rQp, off, 4u * qrow, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, g), rQg, off, 4u * qrow, 0);
+        }
+        // rows past Hp have zero Q1 rows, bias and Q2 entries: they add 0 * GELU(0) = 0
+        part = fmaf(s2[jj], g, part);
+      }
+    }
+    part += __shfl_xor(part, 32);
+    const uint32_t ooff = (4u * static_cast<uint32_t>(b * P + n)) | ((lane < 32 && nok) ? 0u : kOOB);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, part + b2), rO, ooff, 0, 0);
+  };
+  if (q0 >= q1) return;
+  load_chunk(0, q0);
+  load_chunk(1, min(q0 + 1, q1 - 1));
+  for (int qi = q0; qi < q1; qi += 3) {
+    load_chunk(2, min(qi + 2, q1 - 1));
+    chunk(0, qi, true);
+    load_chunk(0, min(qi + 3, q1 - 1));
+    chunk(1, min(qi + 1, q1 - 1), qi + 1 < q1);
+    load_chunk(1, min(qi + 4, q1 - 1));
+    chunk(2, min(qi + 2, q1 - 1), qi + 2 < q1);
+  }
 }
 
 // Truncated 2D DCT of every (b, c) plane, entirely in registers: A[pl][kh][kw] = sum_h sum_w Ch[kh][h]
@@ -1159,18 +1308,38 @@ template <typename TX, typename TY, typename TT, int KT, bool TVEC>
 void launch_mixrows_t(const float* A, bool transA, const void* X, void* Y, const float* bias, float* pre, const void* T,
                       const float* Cw, int Mm, int O, int I, int H, int W, int B, bool act, bool split, hipStream_t s) {
   const int64_t rows = static_cast<int64_t>(B) * H, groups = (W + 127) / 128;
-  // about 2048 blocks: two rounds of four 4-wave blocks per CU, each walking its rows with loads ahead
-  const int rpb = static_cast<int>(std::max<int64_t>(1, (rows * groups + 2047) / 2048));
+  // about 1024 blocks of 4 waves, each walking its rows with loads two rows ahead
+  const int rpb = static_cast<int>(std::max<int64_t>(1, (rows * groups + 1023) / 1024));
   const unsigned nblk = static_cast<unsigned>(((rows + rpb - 1) / rpb) * groups);
   const TX* x = static_cast<const TX*>(X);
   const TT* t = static_cast<const TT*>(T);
   TY* y = static_cast<TY*>(Y);
-  if (split)
-    hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, true>), dim3(nblk), dim3(256), 0, s, A, x, y, bias,
-                       pre, t, Cw, O, I, H, W, Mm, B, rpb, act ? 1 : 0, transA ? 1 : 0);
-  else
-    hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, false>), dim3(nblk), dim3(256), 0, s, A, x, y, bias,
-                       pre, t, Cw, O, I, H, W, Mm, B, rpb, act ? 1 : 0, transA ? 1 : 0);
+  const int a = act ? 1 : 0, ta = transA ? 1 : 0;
+  // bf16 activations come with plain products only; the lift (FP32 features into bf16) has four inputs
+  constexpr bool half_act = sizeof(TX) == 2, lift = sizeof(TX) == 4 && sizeof(TY) == 2;
+  if constexpr (!half_act) {
+    if (split) {
+      if constexpr (!lift) {
+        if (I == 32) {
+          hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, true, true>), dim3(nblk), dim3(256), 0, s, A, x,
+                             y, bias, pre, t, Cw, O, I, H, W, Mm, B, rpb, a, ta);
+          return;
+        }
+      }
+      hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, true, false>), dim3(nblk), dim3(256), 0, s, A, x, y,
+                         bias, pre, t, Cw, O, I, H, W, Mm, B, rpb, a, ta);
+      return;
+    }
+  }
+  if constexpr (!lift) {
+    if (I == 32) {
+      hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, false, true>), dim3(nblk), dim3(256), 0, s, A, x, y,
+                         bias, pre, t, Cw, O, I, H, W, Mm, B, rpb, a, ta);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((nop_mixrows_kernel<TX, TY, TT, KT, TVEC, false, false>), dim3(nblk), dim3(256), 0, s, A, x, y,
+                     bias, pre, t, Cw, O, I, H, W, Mm, B, rpb, a, ta);
 }
 
 template <typename TX, typename TY, typename TT>
@@ -1246,6 +1415,32 @@ hipError_t launch_nop_project(const float* Q1, const float* q1b, const float* Q2
                               hipStream_t s) {
   const size_t lds = sizeof(float) * (static_cast<size_t>(Hp) * (C + 1) + 2 * Hp);
   if (C > 32 || lds > 65536) return hipErrorInvalidValue;
+  const int64_t vs = half ? 2 : 4;
+  const bool fits = static_cast<int64_t>(B) * C * P * vs < (int64_t(1) << 31) &&
+                    static_cast<int64_t>(B) * P * 4 < (int64_t(1) << 31) &&
+                    (!qpre || static_cast<int64_t>(B) * Hp * P * 4 < (int64_t(1) << 31));
+  const bool keep = qpre != nullptr;
+  if (Hp >= 1 && Hp <= 128 && C >= 1 && fits && keep == (q != nullptr) && !(half && (split || keep))) {
+    // the chunk-walking form: about 1024 blocks of 4 waves
+    const int64_t chunks = static_cast<int64_t>(B) * ((P + 127) / 128);
+    const int rpb = static_cast<int>(std::max<int64_t>(1, (chunks + 1023) / 1024));
+    const dim3 grid(static_cast<unsigned>((chunks + rpb - 1) / rpb)), blk(256);
+    const int Pi = static_cast<int>(P);
+#define PSTD_PROJ_K(TVV, SPV, KPV)                                                                                \
+  if (C == 32) hipLaunchKernelGGL((nop_projrows_kernel<TVV, SPV, true, KPV>), grid, blk, 0, s, Q1, q1b, Q2, q2b,    \
+                                  static_cast<const TVV*>(v), out, qpre, q, C, Hp, Pi, B, rpb);                   \
+  else hipLaunchKernelGGL((nop_projrows_kernel<TVV, SPV, false, KPV>), grid, blk, 0, s, Q1, q1b, Q2, q2b,          \
+                          static_cast<const TVV*>(v), out, qpre, q, C, Hp, Pi, B, rpb);
+    if (half) {        // the inference form: bf16 activations
+      PSTD_PROJ_K(__bf16, false, false)
+    } else if (split) {
+      if (keep) { PSTD_PROJ_K(float, true, true) } else { PSTD_PROJ_K(float, true, false) }
+    } else {
+      if (keep) { PSTD_PROJ_K(float, false, true) } else { PSTD_PROJ_K(float, false, false) }
+    }
+#undef PSTD_PROJ_K
+    return hipGetLastError();
+  }
   if (half)
     hipLaunchKernelGGL(nop_project_kernel<__bf16>, dim3(blocks_for(P, 128), B), dim3(256), lds, s, Q1, q1b, Q2, q2b,
                        static_cast<const __bf16*>(v), out, qpre, q, C, Hp, P, split ? 1 : 0);
