@@ -21,7 +21,10 @@ SMALL = dict(H=16, W=12, channels=4, modes=6, layers=2, hidden=8)
 MEDIUM = dict(H=16, W=16, channels=8, modes=8, layers=1, hidden=128)
 # three 16-mode tiles per axis and an odd number of 16-row blocks in the per-plane DCT kernel
 LARGE = dict(H=48, W=64, channels=4, modes=40, layers=1, hidden=16)
-SHAPES = {"small": SMALL, "medium": MEDIUM, "large": LARGE}
+# all 32 channels: the channel-mix and projection kernels take their full-channel forms (channel stride in
+# the scalar offset, bf16 channel pairs loaded as one dword in the inference form)
+WIDE = dict(H=16, W=20, channels=32, modes=16, layers=2, hidden=64)
+SHAPES = {"small": SMALL, "medium": MEDIUM, "large": LARGE, "wide": WIDE}
 
 
 def _setup(split, B=3, seed=0, shape=SMALL):
@@ -41,7 +44,7 @@ def _setup(split, B=3, seed=0, shape=SMALL):
     return torch, net, ocfg, theta, p0, c0, tgt
 
 
-@pytest.mark.parametrize("shape", ["small", "medium", "large"])
+@pytest.mark.parametrize("shape", ["small", "medium", "large", "wide"])
 @pytest.mark.parametrize("split,tol", [(True, 1e-4), (False, 3e-2)])
 def test_forward_and_gradients_match_reference(split, tol, shape):
     torch, net, ocfg, theta, p0, c0, tgt = _setup(split, shape=SHAPES[shape])
