@@ -1221,6 +1221,131 @@ __global__ __launch_bounds__(256) void nop_dct2_kernel(const TV* __restrict__ V,
       }
 }
 
+// Streaming form of the same transform (W % 4 == 0): each wave takes planes pl0, pl0 + stride, ... and
+// walks their 16-row blocks as one sequence, so the loads of the next two row blocks are in flight while
+// a block is multiplied, across plane boundaries too.  bf16 planes enter the MFMAs as loaded.  Same
+// products in the same order as nop_dct2_kernel, so both forms give the same bits.
+template <int NT, typename TV>
+__global__ __launch_bounds__(256) void nop_dct2w_kernel(const TV* __restrict__ V, float* __restrict__ A,
+                                                        const __bf16* __restrict__ img, int planes, int H, int W,
+                                                        int Mm, int split) {
+  constexpr int M16 = 16 * NT;
+  constexpr bool RAW = sizeof(TV) == 2;      // bf16 planes: the loaded words are the hi operand
+  extern __shared__ __attribute__((aligned(16))) __bf16 tb[];
+  const int H16 = (H + 15) & ~15, W16 = (W + 15) & ~15;
+  const int ldw = W16 + 4, ldh = H16 + 4;
+  const bool sp = split != 0;
+  __bf16* cwh = tb;
+  __bf16* cwl = cwh + M16 * ldw;
+  __bf16* chh = cwl + (sp ? M16 * ldw : 0);
+  __bf16* chl = chh + M16 * ldh;
+  const int tid = threadIdx.x;
+  stage_bytes(tb, img, static_cast<int>((sp ? 2 : 1) * M16 * (ldw + ldh) * sizeof(__bf16) / 16));
+  __syncthreads();
+  const int lane = tid & 63, g = lane >> 4, j = lane & 15;
+  const int wv = static_cast<int>(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int stride = static_cast<int>(gridDim.x) * 4;
+  if (wv >= planes) return;
+  const int np = (planes - 1 - wv) / stride + 1;   // planes of this wave
+  const int KS = W16 >> 4, MT = H16 >> 4;
+  const int n = np * MT;                           // row blocks of this wave
+  constexpr uint32_t ES = sizeof(TV);
+  f32x4 acc[NT][NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // three register sets: raw bf16 quads (RAW) or FP32 quads
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  u32x2 rb[3][8];
+  f32x4 rf[3][RAW ? 1 : 8];
+  auto load_blk = [&](int set, int it) {
+    const int q = it / MT, mt = it - q * MT;
+    const int pl = wv + q * stride;
+    const rsrc_t rv = wave_rsrc(V + static_cast<int64_t>(pl) * H * W, static_cast<uint32_t>(H * W) * ES);
+    const int h = 16 * mt + j;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int w0 = 16 * ks + 4 * g;
+      const uint32_t off = (ES * static_cast<uint32_t>(h * W + w0)) | ((h < H && w0 < W) ? 0u : kOOB);
+      if (RAW)
+        rb[set][ks] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rv, off, 0, 0));
+      else
+        rf[set][RAW ? 0 : ks] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rv, off, 0, 0));
+    }
+  };
+  auto process = [&](int set, int it, bool valid) {
+    if (!valid) return;
+    const int q = it / MT, mt = it - q * MT;
+    f32x4 c1[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) c1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      if (ks < KS) {
+        bf16x4 vh, vl;
+        if (RAW) {
+          vh = __builtin_bit_cast(bf16x4, rb[set][ks]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) vl[e] = static_cast<__bf16>(0.f);
+        } else {
+          const float x[4] = {rf[set][RAW ? 0 : ks][0], rf[set][RAW ? 0 : ks][1], rf[set][RAW ? 0 : ks][2],
+                              rf[set][RAW ? 0 : ks][3]};
+          to_bf16x4(x, vh, vl, sp);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int o = (16 * nt + j) * ldw + 16 * ks + 4 * g;
+          const bf16x4 qh = *reinterpret_cast<const bf16x4*>(cwh + o);
+          const bf16x4 ql = sp ? *reinterpret_cast<const bf16x4*>(cwl + o) : qh;
+          c1[nt] = mma16(vh, vl, qh, ql, c1[nt], sp);
+        }
+      }
+    }
+    bf16x4 yh[NT], yl[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const float y[4] = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
+      to_bf16x4(y, yh[nt], yl[nt], sp);
+    }
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const int o = (16 * a + j) * ldh + 16 * mt + 4 * g;
+      const bf16x4 ph = *reinterpret_cast<const bf16x4*>(chh + o);
+      const bf16x4 pq = sp ? *reinterpret_cast<const bf16x4*>(chl + o) : ph;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) acc[a][c] = mma16(ph, pq, yh[c], yl[c], acc[a][c], sp);
+    }
+    if (mt == MT - 1) {   // the plane is complete
+      float* ap = A + static_cast<int64_t>(wv + q * stride) * Mm * Mm;
+#pragma unroll
+      for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int kh = 16 * a + 4 * g + r, kw = 16 * c + j;
+            if (kh < Mm && kw < Mm) ap[kh * Mm + kw] = acc[a][c][r];
+          }
+          acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  };
+  // items past the wave's last are clamped to it (loaded again, not processed): the loads are
+  // unconditional, so each wait covers exactly the loads it needs
+  load_blk(0, 0);
+  load_blk(1, min(1, n - 1));
+  for (int it = 0; it < n; it += 3) {
+    load_blk(2, min(it + 2, n - 1));
+    process(0, it, true);
+    load_blk(0, min(it + 3, n - 1));
+    process(1, min(it + 1, n - 1), it + 1 < n);
+    load_blk(1, min(it + 4, n - 1));
+    process(2, min(it + 2, n - 1), it + 2 < n);
+  }
+}
+
 // First stage of the inverse DCT for every (b, c) plane: T[b][h][c][kw] = sum_kh Ch[kh][h] Z[b][c][kh][kw]
 // (Z in natural layout, T laid out for the channel-mixing kernel), one plane per wave on MFMA 16x16x16
 // bf16: P = Ch^T rows from LDS (bf16, remainders with split), Q = the plane's Mm x Mm coefficients,
@@ -1481,10 +1606,13 @@ hipError_t launch_nop_dct2(const void* V, float* A, const void* img, int planes,
   const __bf16* tab = static_cast<const __bf16*>(img);
   const float* Vf = static_cast<const float*>(V);
   const __bf16* Vh = static_cast<const __bf16*>(V);
+  // streaming form for rows of whole 4-element groups: about 512 blocks (two per CU), every wave walking
+  // its planes' row blocks with loads two blocks ahead
+  const dim3 sgrid(static_cast<unsigned>(std::min<int64_t>((planes + 3) / 4, 512)));
 #define PSTD_DCT2(NTV)                                                                                          \
-  if (half && vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true, __bf16>), grid, blk, lds, s, Vh, A, tab, planes, H, W, Mm, sp); \
+  if (half && vec) hipLaunchKernelGGL((nop_dct2w_kernel<NTV, __bf16>), sgrid, blk, lds, s, Vh, A, tab, planes, H, W, Mm, sp); \
   else if (half) hipLaunchKernelGGL((nop_dct2_kernel<NTV, false, __bf16>), grid, blk, lds, s, Vh, A, tab, planes, H, W, Mm, sp); \
-  else if (vec) hipLaunchKernelGGL((nop_dct2_kernel<NTV, true, float>), grid, blk, lds, s, Vf, A, tab, planes, H, W, Mm, sp); \
+  else if (vec) hipLaunchKernelGGL((nop_dct2w_kernel<NTV, float>), sgrid, blk, lds, s, Vf, A, tab, planes, H, W, Mm, sp); \
   else hipLaunchKernelGGL((nop_dct2_kernel<NTV, false, float>), grid, blk, lds, s, Vf, A, tab, planes, H, W, Mm, sp);
   switch (NT) {
     case 1: PSTD_DCT2(1) break;
