@@ -8,11 +8,11 @@
 // two contractions of the same shape,
 //   contraction 0:  out0[i][j] = sum_k A0[i][k] X0[k][j]   (operator rows, columns of a field)
 //   contraction 1:  out1[i][j] = sum_k X1[i][k] A1[j][k]   (rows of a field, operator rows)
-// and the four waves of a block split them as (contraction, half of k).  A box of a few hundred nodes a
+// and the eight waves of a block split them as (contraction, quarter of k).  A box of a few hundred nodes a
 // side is bound by latency, not by bandwidth or MFMA rate, so a block issues every load it needs (four
 // full-k operand slices and the old output values of its epilogue) before the first LDS store: one
 // round trip to memory per phase.  Small tiles give enough blocks to spread the MFMA work over the
-// whole GPU (256 blocks for 256 x 256).  The kernel boundary between the phases is the grid-wide
+// whole GPU (256 blocks of eight waves for 256 x 256).  The kernel boundary between the phases is the grid-wide
 // dependency of the scheme; graph replay keeps the launch gaps short.
 //
 // MFMA v_mfma_f32_16x16x4: lane l supplies P[l%16][kslot l/16] and Q[l%16][kslot l/16] and receives
@@ -29,7 +29,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
 constexpr int T = 16;                   // output tile edge
-constexpr int NT = 256;                 // four waves
+constexpr int NT = 512;                 // eight waves
 constexpr uint32_t kOOB = 0x80000000u;  // buffer offset past every range: the load returns zero
 
 struct Phase2DArgs {
@@ -56,67 +56,67 @@ __device__ __forceinline__ f32x4 ld_f32x4(rsrc_t r, uint32_t voff) {
 
 __host__ __device__ __forceinline__ int pad64(int k) { return (k + 63) & ~63; }
 
-// One phase's operands in registers between the loads and the LDS stores.
-//   op0, op1: operator rows r0 .. r0+15, k < Kpad, thread t holds k = 4 (t%16) + 64 j of row t/16
-//   col0:     X0[k][c0 + c], thread t holds c = t%16, k = t/16 + 16 u
-//   row1:     X1[r0 + r][k], thread t holds r = t/64 + 4 q, k = t%64 + 64 j
+// One phase's operands in registers between the loads and the LDS stores (512 threads).
+//   op0, op1: operator rows r0 .. r0+15, k < Kpad, thread t holds k = 4 (t%32) + 128 j of row t/32
+//   col0:     X0[k][c0 + c], thread t holds c = t%16, k = t/16 + 32 u
+//   row1:     X1[r0 + r][k], thread t holds r = t/64 + 8 q, k = t%64 + 64 j
 template <int KMAX>
 struct Slices {
   static constexpr int KC = KMAX / 64;
-  f32x4 op0[KC], op1[KC];
-  float col0[KMAX / 16];
-  float row1[4 * KC];
+  f32x4 op0[KMAX / 128], op1[KMAX / 128];
+  float col0[KMAX / 32];
+  float row1[2 * KC];
 };
 
 template <int KMAX>
-__device__ __forceinline__ void load_op(f32x4 (&v)[KMAX / 64], rsrc_t rs, int ld, int r0, int Kpad) {
+__device__ __forceinline__ void load_op(f32x4 (&v)[KMAX / 128], rsrc_t rs, int ld, int r0, int Kpad) {
   const int t = threadIdx.x;
-  const uint32_t base = 4u * static_cast<uint32_t>((r0 + (t >> 4)) * ld + 4 * (t & 15));
+  const uint32_t base = 4u * static_cast<uint32_t>((r0 + (t >> 5)) * ld + 4 * (t & 31));
 #pragma unroll
-  for (int j = 0; j < KMAX / 64; ++j)
-    if (64 * j < Kpad) v[j] = ld_f32x4(rs, base + 256u * j);
+  for (int j = 0; j < KMAX / 128; ++j)
+    if (128 * j < Kpad) v[j] = ld_f32x4(rs, base + 512u * j);
 }
 
 template <int KMAX>
-__device__ __forceinline__ void store_op(float* dst, const f32x4 (&v)[KMAX / 64], int Kpad) {
+__device__ __forceinline__ void store_op(float* dst, const f32x4 (&v)[KMAX / 128], int Kpad) {
   constexpr int LD = KMAX + 4;
   const int t = threadIdx.x;
-  float* d = dst + (t >> 4) * LD + 4 * (t & 15);
+  float* d = dst + (t >> 5) * LD + 4 * (t & 31);
 #pragma unroll
-  for (int j = 0; j < KMAX / 64; ++j)
-    if (64 * j < Kpad) *reinterpret_cast<f32x4*>(d + 64 * j) = v[j];
+  for (int j = 0; j < KMAX / 128; ++j)
+    if (128 * j < Kpad) *reinterpret_cast<f32x4*>(d + 128 * j) = v[j];
 }
 
 // columns c0 .. c0+15 of X (row stride ld; valid c < cols, k < K)
 template <int KMAX>
-__device__ __forceinline__ void load_cols(float (&v)[KMAX / 16], rsrc_t rs, int ld, int c0, int cols, int K, int Kpad) {
+__device__ __forceinline__ void load_cols(float (&v)[KMAX / 32], rsrc_t rs, int ld, int c0, int cols, int K, int Kpad) {
   const int t = threadIdx.x;
   const int c = c0 + (t & 15);
 #pragma unroll
-  for (int u = 0; u < KMAX / 16; ++u) {
-    const int k = (t >> 4) + 16 * u;
-    if (16 * u < Kpad) v[u] = ld_f32(rs, (c < cols && k < K) ? 4u * static_cast<uint32_t>(k * ld + c) : kOOB);
+  for (int u = 0; u < KMAX / 32; ++u) {
+    const int k = (t >> 4) + 32 * u;
+    if (32 * u < Kpad) v[u] = ld_f32(rs, (c < cols && k < K) ? 4u * static_cast<uint32_t>(k * ld + c) : kOOB);
   }
 }
 
 template <int KMAX>
-__device__ __forceinline__ void store_cols(float* dst, const float (&v)[KMAX / 16], int Kpad) {
+__device__ __forceinline__ void store_cols(float* dst, const float (&v)[KMAX / 32], int Kpad) {
   constexpr int LD = KMAX + 4;
   const int t = threadIdx.x;
   float* d = dst + (t & 15) * LD + (t >> 4);
 #pragma unroll
-  for (int u = 0; u < KMAX / 16; ++u)
-    if (16 * u < Kpad) d[16 * u] = v[u];
+  for (int u = 0; u < KMAX / 32; ++u)
+    if (32 * u < Kpad) d[32 * u] = v[u];
 }
 
 // rows r0 .. r0+15 of X (row stride ld; valid r < rows, k < K)
 template <int KMAX>
-__device__ __forceinline__ void load_rows(float (&v)[4 * (KMAX / 64)], rsrc_t rs, int ld, int r0, int rows, int K,
+__device__ __forceinline__ void load_rows(float (&v)[2 * (KMAX / 64)], rsrc_t rs, int ld, int r0, int rows, int K,
                                           int Kpad) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = r0 + (t >> 6) + 4 * q;
+  for (int q = 0; q < 2; ++q) {
+    const int r = r0 + (t >> 6) + 8 * q;
 #pragma unroll
     for (int j = 0; j < KMAX / 64; ++j) {
       const int k = (t & 63) + 64 * j;
@@ -127,12 +127,12 @@ __device__ __forceinline__ void load_rows(float (&v)[4 * (KMAX / 64)], rsrc_t rs
 }
 
 template <int KMAX>
-__device__ __forceinline__ void store_rows(float* dst, const float (&v)[4 * (KMAX / 64)], int Kpad) {
+__device__ __forceinline__ void store_rows(float* dst, const float (&v)[2 * (KMAX / 64)], int Kpad) {
   constexpr int LD = KMAX + 4;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float* d = dst + ((t >> 6) + 4 * q) * LD + (t & 63);
+  for (int q = 0; q < 2; ++q) {
+    float* d = dst + ((t >> 6) + 8 * q) * LD + (t & 63);
 #pragma unroll
     for (int j = 0; j < KMAX / 64; ++j)
       if (64 * j < Kpad) d[64 * j] = v[q * (KMAX / 64) + j];
@@ -170,7 +170,7 @@ __device__ __forceinline__ void mma_range(const float* P, const float* Q, int kb
 
 template <int KMAX>
 constexpr size_t lds_bytes() {
-  return sizeof(float) * 4 * T * (KMAX + 4) + sizeof(double) * 4 * 4 * 64;
+  return sizeof(float) * 4 * T * (KMAX + 4) + sizeof(double) * 8 * 4 * 64;
 }
 
 // PH 0: velocity phase, PH 1: pressure phase.
@@ -178,7 +178,7 @@ template <int KMAX, int PH>
 __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
   constexpr int SL = T * (KMAX + 4);
   extern __shared__ float lds[];
-  double* red = reinterpret_cast<double*>(lds + 4 * SL);   // [wave][reg][lane]
+  double* red = reinterpret_cast<double*>(lds + 4 * SL);   // [wave][reg][lane], eight waves
   const int nx = a.nx, ny = a.ny;
   const int tiles_y = (ny + T - 1) / T;
   const int nb = gridDim.x;
@@ -204,29 +204,25 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
   const rsrc_t rX0 = make_rsrc(X0, 4u * static_cast<uint32_t>(K0 * ny));
   const rsrc_t rX1 = make_rsrc(X1, 4u * static_cast<uint32_t>(nx * ld1));
 
-  // old output values of this wave's share of the epilogue, loaded with the operands
-  //   velocity: wave w finishes registers 2 (w%2), 2 (w%2) + 1 of the u_x (w < 2) or u_y (w >= 2) tile
-  //   pressure: wave w finishes register w of the p tile
-  float old[2];
-  float cfac[2] = {1.f, 1.f};
+  // old output value of this wave's share of the epilogue, loaded with the operands
+  //   velocity: wave w finishes register w%4 of the u_x (w < 4) or u_y (w >= 4) tile
+  //   pressure: wave w < 4 finishes register w of the p tile
+  float old = 0.f, cfac = 1.f;
   const int oj = j0 + (lane & 15);
   if (PH == 0) {
-    float* Y = wave < 2 ? a.ux : a.uy;
-    const int rows = wave < 2 ? nx - 1 : nx, cols = wave < 2 ? ny : ny - 1;
+    float* Y = wave < 4 ? a.ux : a.uy;
+    const int rows = wave < 4 ? nx - 1 : nx, cols = wave < 4 ? ny : ny - 1;
     const rsrc_t rY = make_rsrc(Y, 4u * static_cast<uint32_t>(rows * cols));
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int oi = i0 + 4 * (lane >> 4) + 2 * (wave & 1) + h;
-      old[h] = ld_f32(rY, (oi < rows && oj < cols) ? 4u * static_cast<uint32_t>(oi * cols + oj) : kOOB);
-    }
-  } else {
+    const int oi = i0 + 4 * (lane >> 4) + (wave & 3);
+    old = ld_f32(rY, (oi < rows && oj < cols) ? 4u * static_cast<uint32_t>(oi * cols + oj) : kOOB);
+  } else if (wave < 4) {
     const rsrc_t rP = make_rsrc(a.p, 4u * static_cast<uint32_t>(nx * ny));
     const int oi = i0 + 4 * (lane >> 4) + wave;
     const bool ok = oi < nx && oj < ny;
-    old[0] = ld_f32(rP, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
+    old = ld_f32(rP, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
     if (a.c2) {
       const rsrc_t rC = make_rsrc(a.c2, 4u * static_cast<uint32_t>(nx * ny));
-      cfac[0] = ld_f32(rC, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
+      cfac = ld_f32(rC, ok ? 4u * static_cast<uint32_t>(oi * ny + oj) : kOOB);
     }
   }
 
@@ -247,35 +243,32 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
 
   double acc[4] = {0, 0, 0, 0};
   {
-    const int c = wave >> 1, h = wave & 1;
-    const int Kp = c == 0 ? Kp0 : Kp1;
-    const int half = Kp >> 1;   // a multiple of 32
-    mma_range<KMAX>(c == 0 ? S0 : S2, c == 0 ? S1 : S3, h * half, (h + 1) * half, acc);
+    // wave w: contraction w / 4, quarter w % 4 of its 32-wide k chunks
+    const int c = wave >> 2, h = wave & 3;
+    const int nch = (c == 0 ? Kp0 : Kp1) >> 5;
+    mma_range<KMAX>(c == 0 ? S0 : S2, c == 0 ? S1 : S3, 32 * ((h * nch) >> 2), 32 * (((h + 1) * nch) >> 2), acc);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[(wave * 4 + r) * 64 + lane] = acc[r];
   __syncthreads();
 
+  auto part = [&](int w, int r) { return red[(w * 4 + r) * 64 + lane]; };
   if (PH == 0) {
-    const int c = wave >> 1;
+    const int c = wave >> 2, r = wave & 3;
     float* Y = c == 0 ? a.ux : a.uy;
     const int rows = c == 0 ? nx - 1 : nx, cols = c == 0 ? ny : ny - 1;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = 2 * (wave & 1) + h;
-      const double v = red[((2 * c) * 4 + r) * 64 + lane] + red[((2 * c + 1) * 4 + r) * 64 + lane];
-      const int oi = i0 + 4 * (lane >> 4) + r;
-      if (oi < rows && oj < cols)
-        Y[static_cast<int64_t>(oi) * cols + oj] = static_cast<float>(static_cast<double>(old[h]) + v);
-    }
-  } else {
+    const double v = (part(4 * c, r) + part(4 * c + 1, r)) + (part(4 * c + 2, r) + part(4 * c + 3, r));
+    const int oi = i0 + 4 * (lane >> 4) + r;
+    if (oi < rows && oj < cols)
+      Y[static_cast<int64_t>(oi) * cols + oj] = static_cast<float>(static_cast<double>(old) + v);
+  } else if (wave < 4) {
     const int r = wave;
-    const double v = (red[(0 * 4 + r) * 64 + lane] + red[(1 * 4 + r) * 64 + lane]) +
-                     (red[(2 * 4 + r) * 64 + lane] + red[(3 * 4 + r) * 64 + lane]);
+    const double v = ((part(0, r) + part(1, r)) + (part(2, r) + part(3, r))) +
+                     ((part(4, r) + part(5, r)) + (part(6, r) + part(7, r)));
     const int oi = i0 + 4 * (lane >> 4) + r;
     if (oi < nx && oj < ny)
       a.p[static_cast<int64_t>(oi) * ny + oj] =
-          static_cast<float>(static_cast<double>(old[0]) + v * static_cast<double>(cfac[0]));
+          static_cast<float>(static_cast<double>(old) + v * static_cast<double>(cfac));
   }
 }
 
