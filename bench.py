@@ -40,6 +40,7 @@ WORKLOADS = {
     "pstd3d": ("pstd3d", "split_bf16", 100, 50),
     "pstd1d": ("pstd1d", "fp64", 1000, 100),
     "batched": ("batched", "fp32", 1000, 10),
+    "faces": ("faces2d", "fp32", 1000, 10),
     "pstd2d_large": ("pstd2d_large", "fp32", 200, 50),
     "nop": ("nop", "bf16", 20, 3),
 }
@@ -53,6 +54,7 @@ SOURCES = {
     "pstd3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
     "pstd2d_large": ("common.h", "capi.hip", "fft_plan.cpp", "kernels_fft.hip"),
     "batched": ("common.h", "capi_batch.hip", "kernels_batch2d.hip"),
+    "faces": ("common.h", "capi.hip", "capi_batch.hip", "kernels_batch2d.hip", "kernels_misc.hip"),
     "nop": ("common.h", "capi_nop.hip", "kernels_nop.hip"),
 }
 
@@ -305,6 +307,87 @@ def run_batched(args, K, W):
     print(json.dumps(line))
 
 
+def run_faces(args, K, W):
+    """Per-face reflection coefficients: the 16 basic-wall solves in one batched launch plus their weighted sum."""
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import Batch, combine_fields, face_weights
+
+    case = workloads.faces2d(steps=K)
+    R = case.bcs
+    cases, w = face_weights(R)
+    solves = [{"shape": case.shape, "bcs": cs, "dx": case.dx, "dt": case.dt, "c0": case.c0} for cs in cases]
+    points = case.shape[0] * case.shape[1]
+    b = Batch(solves)
+    cfg = b.autotune(trial_steps=5, cache_path=os.path.join("/tmp", "pstd_batch_tune.json"))
+    st = b.new_states([case.p0] * len(solves))
+    b.init_states(st)
+    b.step(st, W)
+    out = torch.empty_like(st[0].p)
+    torch.cuda.synchronize()
+    stream = b._stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.step(st, K)
+    combine_fields([s.p for s in st], w, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = e0.elapsed_time(e1)
+    b.synchronize()
+    got = out.double().cpu().numpy()
+    b.close()
+    flops, bytes_ = batch_step_cost(solves)
+    launches = max(1, (K + 1023) // 1024)
+    tfs = flops * K / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s",
+            "frac": round(tfs / PEAK["fp32_TFs"], 4), "traffic": None, "kernel": "batch2d_kernel (persistent)",
+            "avg_ms": round(kernel_ms / launches, 3), "algorithmic_flops": int(flops * K / launches),
+            "algorithmic_bytes": int(bytes_ * K / launches), "arith_intensity": round(flops / bytes_, 2)}
+    cpu = err = None
+    if not args.no_cpu_baseline:
+        cpu, err = faces_cpu_leg(case, got, W + K)
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle",
+        "value": points * K / elapsed, "unit": "grid-point updates/s (of the per-face-R field)", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": case.name, "grid": list(case.shape), "R_faces": [list(r) for r in R],
+                   "basic_solves": len(solves), "basic_updates_per_s": points * len(solves) * K / elapsed,
+                   "precision": "fp32", "parallelism": "single-gpu", "launch": cfg},
+        "accuracy": {"rel_l2_vs_fp64_oracle": err, "after_steps": W + K, "tolerance": 1e-5},
+        "roofline": roof, "cpu_baseline": cpu, "kernel_source_hash": kernel_source_hash("faces"),
+    }
+    print(json.dumps(line))
+
+
+def faces_cpu_leg(case, got, total_steps, budget_s=12.0):
+    """Oracle: the 16 basic solves stepped on the host for a bounded time; the GPU field against the
+    weighted sum of the basic fields' FP64 closed forms."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import pstd as opstd
+
+    ws = opstd.combination_weights(case.bcs)
+    probs = [(opstd.Problem(case.shape, cs, case.dx, case.dt, case.c0), wi) for cs, wi in ws.items()]
+    pu = [(pr.project(case.p0), pr.initial_velocity(case.p0)) for pr, _ in probs]
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < total_steps:
+        pu = [pr.step(p, u) for (pr, _), (p, u) in zip(probs, pu)]
+        steps += 1
+    dt = time.perf_counter() - t0
+    threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
+    ref = sum(wi * pr.modal_solution(case.p0, total_steps) for pr, wi in probs)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    pts = case.shape[0] * case.shape[1]
+    cpu = {"value": pts * steps / dt, "unit": "grid-point updates/s (of the per-face-R field)", "cores": threads,
+           "kind": "oracle", "sample": "%d of %d time steps of all 16 basic solves, FP64 NumPy" % (steps, total_steps)}
+    return cpu, err
+
+
 def batched_cpu_leg(wl, solves, p0s, finals, combined, pairs, R, total_steps, budget_s=12.0):
     """Oracle: time stepping of sample solves on the host; check sample solves and combinations."""
     from threadpoolctl import threadpool_info
@@ -490,6 +573,10 @@ def main():
     if args.calibrate_copy:
         torch.cuda.set_device(0)
         calibration_copies()
+    if args.workload == "faces":
+        torch.cuda.set_device(0)
+        run_faces(args, K, W)
+        return
     if args.workload == "batched":
         torch.cuda.set_device(0)
         run_batched(args, K, W)

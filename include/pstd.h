@@ -139,6 +139,20 @@ int pstd_combine_R(const float* p_dirichlet, const float* p_neumann, double R,
 int pstd_combine_fields(const float* const* fields, const double* w, int32_t nfields,
                         float* p_out, int64_t count, void* hip_stream);
 
+/* Host only (no GPU needed): the basic fields and weights of §5 for an arbitrary real reflection
+ * coefficient on every face.  R: 2 ndim coefficients, (left, right) per axis (1 reflects like a rigid
+ * wall, -1 like a pressure-release wall, 0 absorbs; any finite value is accepted).  The solution for
+ * these faces is sum_f w_out[f] p_f over the 4^ndim solutions p_f of the same problem with the basic
+ * walls of field f: per axis the walls (N,N), (N,D), (D,N), (D,D) take the weights (1/4) M^T r with
+ * r = (R_L, 1, R_R, R_L R_R) and §5's image matrix M, and a field's weight is the product over its axes
+ * (separable image sources).  Field f = sum_a c_a 4^(ndim-1-a) with c_a the index of axis a's wall pair
+ * in that order.  bc_out: 4^ndim x 2 ndim pstd_bc values (field f, axis a, left then right) in the
+ * layout of pstd_plan_create's bc_per_face; w_out: 4^ndim weights.  Exact while no wave has been
+ * reflected twice by the same pair of walls (until t = 2 L / c0 on the shortest axis; 3 L / c0 where
+ * both walls absorb).  Returns PSTD_E_INVALID_ARG for ndim outside 1..3, a null pointer or a
+ * non-finite coefficient. */
+int pstd_face_weights(int32_t ndim, const double* R, int32_t* bc_out, double* w_out);
+
 /* Check that p and every u_a are finite.  Synchronises the plan's stream.  Returns PSTD_OK or
  * PSTD_E_NONFINITE. */
 int pstd_check_finite(pstd_plan plan, const pstd_state* state);

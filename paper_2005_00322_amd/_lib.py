@@ -59,6 +59,7 @@ SIGNATURES = {
     "pstd_plan_set_path": (C.c_int, [C.c_void_p, C.c_int32]),
     "pstd_apply_axis": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32, C.c_int32]),
     "pstd_combine_R": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "pstd_face_weights": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "pstd_combine_fields": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                       C.c_int64, C.c_void_p]),
     "pstd_check_finite": (C.c_int, [C.c_void_p, C.POINTER(State)]),

@@ -550,6 +550,41 @@ int pstd_combine_R(const float* p_dirichlet, const float* p_neumann, double R, f
   return PSTD_OK;
 }
 
+int pstd_face_weights(int32_t ndim, const double* R, int32_t* bc_out, double* w_out) {
+  if (ndim < 1 || ndim > 3) return fail(PSTD_E_INVALID_ARG, "ndim must be 1..3");
+  if (!R || !bc_out || !w_out) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  for (int i = 0; i < 2 * ndim; ++i)
+    if (!std::isfinite(R[i])) return fail(PSTD_E_INVALID_ARG, "R[%d] is not finite", i);
+  // per axis: the four basic walls (N,N), (N,D), (D,N), (D,D) are the columns of the image matrix; the
+  // weight of column c is (1/4) sum_j M[j][c] r[j] with r = (R_L, 1, R_R, R_L R_R)
+  static const int M[4][4] = {{1, 1, -1, -1}, {1, 1, 1, 1}, {1, -1, 1, -1}, {1, -1, -1, 1}};
+  static const int walls[4][2] = {{PSTD_NEUMANN, PSTD_NEUMANN}, {PSTD_NEUMANN, PSTD_DIRICHLET},
+                                  {PSTD_DIRICHLET, PSTD_NEUMANN}, {PSTD_DIRICHLET, PSTD_DIRICHLET}};
+  double w1[3][4];
+  for (int a = 0; a < ndim; ++a) {
+    const double RL = R[2 * a], RR = R[2 * a + 1];
+    const double r[4] = {RL, 1.0, RR, RL * RR};
+    for (int c = 0; c < 4; ++c) {
+      double acc = 0.0;
+      for (int j = 0; j < 4; ++j) acc += M[j][c] * r[j];
+      w1[a][c] = 0.25 * acc;
+    }
+  }
+  // field f = sum_a c_a 4^(ndim-1-a): its weight is the product of the axes' weights
+  const int nf = 1 << (2 * ndim);
+  for (int f = 0; f < nf; ++f) {
+    double w = 1.0;
+    for (int a = 0; a < ndim; ++a) {
+      const int c = (f >> (2 * (ndim - 1 - a))) & 3;
+      w *= w1[a][c];
+      bc_out[f * 2 * ndim + 2 * a] = walls[c][0];
+      bc_out[f * 2 * ndim + 2 * a + 1] = walls[c][1];
+    }
+    w_out[f] = w;
+  }
+  return PSTD_OK;
+}
+
 int pstd_combine_fields(const float* const* fields, const double* w, int32_t nfields, float* p_out, int64_t count,
                         void* hip_stream) {
   if (!fields || !w || !p_out) return fail(PSTD_E_INVALID_ARG, "null pointer");

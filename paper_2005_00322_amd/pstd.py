@@ -224,6 +224,38 @@ def combine_fields(fields, weights, out=None, stream=None):
     return out
 
 
+def face_weights(R_faces):
+    """Basic fields and weights of §5 for per-face reflection coefficients (pstd_face_weights, host only).
+
+    R_faces: one (R_left, R_right) pair per axis.  Returns (cases, weights): cases[f] is the tuple of
+    ((left, right), ...) wall pairs of basic field f, weights[f] its weight (float64 array).
+    """
+    nd = len(R_faces)
+    nf = 4 ** nd
+    r = (C.c_double * (2 * nd))(*[float(x) for pair in R_faces for x in pair])
+    bc = (C.c_int32 * (2 * nd * nf))()
+    w = (C.c_double * nf)()
+    check(load().pstd_face_weights(nd, r, bc, w), "pstd_face_weights")
+    cases = [tuple((int(bc[f * 2 * nd + 2 * a]), int(bc[f * 2 * nd + 2 * a + 1])) for a in range(nd)) for f in range(nf)]
+    return cases, np.array(list(w), dtype=np.float64)
+
+
+def solve_faces_2d(shape, dx, dt, c0, R_faces, p0, n_steps, rho0=1000.0, batch=None, out=None):
+    """The 2D field for per-face reflection coefficients: the 16 basic-wall solves of the same problem in one
+    batched launch (pstd_batch_*), then their weighted sum (pstd_combine_fields) with pstd_face_weights.
+
+    Returns (p, batch, states); pass the returned batch back to reuse it (same shape and constants).
+    """
+    cases, w = face_weights(R_faces)
+    if batch is None:
+        batch = Batch([{"shape": tuple(shape), "bcs": cs, "dx": dx, "dt": dt, "c0": c0} for cs in cases], rho0=rho0)
+    states = batch.new_states([p0] * len(cases))
+    batch.init_states(states)
+    batch.step(states, n_steps)
+    p = combine_fields([st.p for st in states], w, out=out, stream=batch._stream)
+    return p, batch, states
+
+
 class Batch:
     """Many independent 2D FP32 solves stepped by one persistent launch (include/pstd.h, pstd_batch_*).
 

@@ -111,6 +111,19 @@ def pstd2d(scale: float = 1.0, steps: int | None = None) -> Case:
                 extra={"centre": centre})
 
 
+def faces2d(n: int = 256, steps: int = 1000) -> Case:
+    """2D box with a real reflection coefficient per face, uniform in [-1, 1] from the seed: the disc of
+    pstd2d in a 256^2 box, CFL 0.3.  1000 steps keep c0 t = 300 dx below 2L/c0 (510 dx), where the
+    weighted sum of the 16 basic-wall solves is exact.  bcs holds the coefficients ((R_L, R_R) per axis)."""
+    rng = rng_for(6)
+    shape = (n, n)
+    c0 = 1500.0
+    centre = _centre(rng, shape, 9, DX)
+    p0 = tapered_disc(shape, DX, centre, 4 * DX, 8 * DX)
+    R = tuple(tuple(float(v) for v in rng.uniform(-1.0, 1.0, 2)) for _ in range(2))
+    return Case("faces2d_%dx%d_R" % shape, shape, R, DX, 0.3 * DX / c0, c0, steps, p0, extra={"centre": centre})
+
+
 def pstd3d(scale: float = 1.0, steps: int | None = None, shape=None) -> Case:
     rng = rng_for(2)
     faces = rng.integers(0, 2, size=6)
