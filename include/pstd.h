@@ -212,11 +212,14 @@ int pstd_batch_combine_R(pstd_batch batch, const pstd_state* states, const int32
 
 /* Launch configuration of pstd_batch_step: resident block count (0 = the occupancy maximum), tile
  * order within a phase (0 = longest contraction first, 1 = solve by solve) and output tile edge (32:
- * 32 x 32 tiles on FP32 MFMA 16x16x4; 64: 64 x 64 tiles on FP32 MFMA 32x32x2). */
+ * 32 x 32 tiles on FP32 MFMA 16x16x4; 64: 64 x 64 tiles on FP32 MFMA 32x32x2; 16: when every solve has
+ * one shape of at most 512 x 512 nodes, no persistent launch but two fused phase launches per step over
+ * all solves, each block one 16 x 16 tile of one solve, replayed from captured graphs; blocks and order
+ * are then unused).  Returns PSTD_E_UNSUPPORTED for tile 16 on other batches. */
 int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order, int32_t tile);
 
-/* Autotuner: time every candidate configuration (tile edge x block count x order) for trial_steps steps
- * on scratch state buffers (the caller's states are not touched), keep the fastest and, if cache_path is
+/* Autotuner: time every candidate configuration (tile edge x block count x order, and tile 16 where it
+ * applies) for trial_steps steps on scratch state buffers (the caller's states are not touched), keep the fastest and, if cache_path is
  * not NULL, store it in a small JSON file keyed by a signature of the batch; a later call with a matching
  * file skips the timing.  config_out (nullable, 4 ints): blocks, order, tile, 1 if taken from the cache.
  * Synchronous. */

@@ -206,6 +206,48 @@ int graph_for(pstd_batch_s* B, int64_t steps, int blocks, hipGraphExec_t* out) {
   return PSTD_OK;
 }
 
+// Tile 16: every solve has one shape of at most 512 x 512 nodes, so a step is two fused phase launches
+// over all solves (block = (16 x 16 tile, solve)), as for a single 2D plan; no tasks, counters or grid
+// barriers.  Graphs of up to kPhaseChunk steps are captured and replayed.
+constexpr int64_t kPhaseChunk = 64;
+
+bool phase_eligible(const pstd_batch_s* B) {
+  if (B->count < 1 || B->count > 65535 || B->solves.size() != static_cast<size_t>(B->count)) return false;
+  for (int s = 0; s < B->count; ++s) {
+    const BatchSolve& S = B->solves[s];
+    if (B->nx[s] != B->nx[0] || B->ny[s] != B->ny[0]) return false;
+    if (!batch2d_phase_fits(S.ldgx, S.ldgy, S.lddx, S.lddy, S.nx, S.ny)) return false;
+  }
+  return phase2d_supported(B->nx[0], B->ny[0]);
+}
+
+int launch_phase_steps(pstd_batch_s* B, int64_t n_steps, hipStream_t s) {
+  for (int64_t left = n_steps; left > 0; left -= kPhaseChunk) {
+    const int64_t steps = std::min(left, kPhaseChunk);
+    const auto key = std::make_tuple(steps, -1, 16);
+    auto it = B->graphs.find(key);
+    if (it == B->graphs.end()) {
+      if (!B->capture) PSTD_HIP(hipStreamCreateWithFlags(&B->capture, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      PSTD_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
+      hipError_t le = hipSuccess;
+      for (int64_t k = 0; k < steps && le == hipSuccess; ++k) {
+        le = launch_phase2d_batch(0, B->d_solves, B->count, B->nx[0], B->ny[0], B->capture);
+        if (le == hipSuccess) le = launch_phase2d_batch(1, B->d_solves, B->count, B->nx[0], B->ny[0], B->capture);
+      }
+      hipError_t e = hipStreamEndCapture(B->capture, &g);
+      if (le != hipSuccess) e = le;
+      hipGraphExec_t ex = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(PSTD_E_HIP, "capture of the phase launches failed: %s", hipGetErrorString(e));
+      it = B->graphs.emplace(key, ex).first;
+    }
+    PSTD_HIP(hipGraphLaunch(it->second, s));
+  }
+  return PSTD_OK;
+}
+
 int launch_steps(pstd_batch_s* B, int64_t n_steps, hipStream_t s) {
   int blocks = 0;
   int st = resident_blocks(B, &blocks);
@@ -449,8 +491,12 @@ int pstd_batch_step(pstd_batch B, pstd_state* st, int64_t n_steps) {
   if (n_steps < 0) return fail(PSTD_E_INVALID_ARG, "n_steps < 0");
   if (n_steps == 0) return PSTD_OK;
   int r = ensure_solves(B, st);
-  if (r == PSTD_OK) r = ensure_tasks(B);
-  if (r == PSTD_OK) r = launch_steps(B, n_steps, B->stream);
+  if (B->tile == 16) {
+    if (r == PSTD_OK) r = launch_phase_steps(B, n_steps, B->stream);
+  } else {
+    if (r == PSTD_OK) r = ensure_tasks(B);
+    if (r == PSTD_OK) r = launch_steps(B, n_steps, B->stream);
+  }
   if (r != PSTD_OK) return r;
   for (int s = 0; s < B->count; ++s) st[s].step += n_steps;
   return PSTD_OK;
@@ -472,8 +518,10 @@ int pstd_batch_combine_R(pstd_batch B, const pstd_state* st, const int32_t* pair
 }
 
 int pstd_batch_set_config(pstd_batch B, int32_t blocks, int32_t order, int32_t tile) {
-  if (!B || blocks < 0 || order < 0 || order > 1 || (tile != 32 && tile != 64))
+  if (!B || blocks < 0 || order < 0 || order > 1 || (tile != 16 && tile != 32 && tile != 64))
     return fail(PSTD_E_INVALID_ARG, "bad batch configuration");
+  if (tile == 16 && !phase_eligible(B))
+    return fail(PSTD_E_UNSUPPORTED, "tile 16 (fused phase launches) needs solves of one shape of at most 512 x 512");
   B->blocks = blocks;
   B->order = order;
   B->tile = tile;
@@ -531,6 +579,26 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (st == PSTD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     st = fail(PSTD_E_HIP, "event creation failed");
+  if (st == PSTD_OK && phase_eligible(B)) {
+    // the fused phase launches: one configuration
+    B->tile = 16;
+    B->blocks = 0;
+    B->order = 0;
+    st = ensure_solves(B, scratch.data());
+    if (st == PSTD_OK) st = launch_phase_steps(B, trial_steps, B->stream);   // warm (and capture the graph)
+    if (st == PSTD_OK && hipEventRecord(e0, B->stream) != hipSuccess) st = fail(PSTD_E_HIP, "event record failed");
+    if (st == PSTD_OK) st = launch_phase_steps(B, trial_steps, B->stream);
+    if (st == PSTD_OK && (hipEventRecord(e1, B->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      st = fail(PSTD_E_HIP, "event timing failed");
+    if (st == PSTD_OK) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = ms;
+      best_b = 0;
+      best_o = 0;
+      best_t = 16;
+    }
+  }
   for (int tile : {32, 64}) {
     if (st != PSTD_OK) break;
     int maxb = 0;

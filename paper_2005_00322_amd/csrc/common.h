@@ -120,6 +120,9 @@ struct BatchSolve {
   double sD;                // -dt rho0 c0^2 / dx, or -dt rho0 / dx with a c0^2 map
   const float* c2;          // nx x ny map of c0(x)^2, or null for a homogeneous medium
 };
+// One fused phase of many solves of one shape (kernels_phase2d.hip): grid (tiles, count).
+hipError_t launch_phase2d_batch(int which, const BatchSolve* solves, int count, int nx, int ny, hipStream_t s);
+bool batch2d_phase_fits(int ldgx, int ldgy, int lddx, int lddy, int nx, int ny);
 struct BatchTask {
   int solve;
   int kind;                 // 0 u_x tile, 1 u_y tile, 2 p tile

@@ -20,6 +20,8 @@
 // read and feeds component e to the e-th of four independent MFMAs, so MFMA e contracts the k set
 // {k0 + 4s + e}; the four together cover k0 .. k0+15 once.  FP32 chain sums are flushed into FP64
 // registers every 32 k, the halves and contractions are added in FP64, and the update is rounded once.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pstd {
@@ -42,6 +44,7 @@ struct Phase2DArgs {
   float* uy;                        // nx x (ny-1)
   const float* c2;                  // nx x ny or null
   int nx, ny;
+  double sv, sp;                    // velocity / pressure factors on the contractions (1 for folded operators)
 };
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* ptr, uint32_t bytes) {
@@ -168,17 +171,20 @@ __device__ __forceinline__ void mma_range(const float* P, const float* Q, int kb
   }
 }
 
-template <int KMAX>
+template <int KMAX, bool ALIAS>
 constexpr size_t lds_bytes() {
-  return sizeof(float) * 4 * T * (KMAX + 4) + sizeof(double) * 8 * 4 * 64;
+  return ALIAS ? std::max(sizeof(float) * 4 * T * (KMAX + 4), sizeof(double) * 8 * 4 * 64)
+               : sizeof(float) * 4 * T * (KMAX + 4) + sizeof(double) * 8 * 4 * 64;
 }
 
 // PH 0: velocity phase, PH 1: pressure phase.
-template <int KMAX, int PH>
-__global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
+// ALIAS: the partial tiles reuse the operand slices' LDS once every wave has finished its products (one
+// more barrier, less LDS: two blocks per CU where many blocks queue); otherwise they follow the slices.
+template <int KMAX, int PH, bool ALIAS>
+__device__ __forceinline__ void phase2d_body(const Phase2DArgs& a) {
   constexpr int SL = T * (KMAX + 4);
   extern __shared__ float lds[];
-  double* red = reinterpret_cast<double*>(lds + 4 * SL);   // [wave][reg][lane], eight waves
+  double* red = reinterpret_cast<double*>(ALIAS ? lds : lds + 4 * SL);   // [wave][reg][lane], eight waves
   const int nx = a.nx, ny = a.ny;
   const int tiles_y = (ny + T - 1) / T;
   const int nb = gridDim.x;
@@ -248,6 +254,7 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
     const int nch = (c == 0 ? Kp0 : Kp1) >> 5;
     mma_range<KMAX>(c == 0 ? S0 : S2, c == 0 ? S1 : S3, 32 * ((h * nch) >> 2), 32 * (((h + 1) * nch) >> 2), acc);
   }
+  if (ALIAS) __syncthreads();
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[(wave * 4 + r) * 64 + lane] = acc[r];
   __syncthreads();
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
     const double v = (part(4 * c, r) + part(4 * c + 1, r)) + (part(4 * c + 2, r) + part(4 * c + 3, r));
     const int oi = i0 + 4 * (lane >> 4) + r;
     if (oi < rows && oj < cols)
-      Y[static_cast<int64_t>(oi) * cols + oj] = static_cast<float>(static_cast<double>(old) + v);
+      Y[static_cast<int64_t>(oi) * cols + oj] = static_cast<float>(static_cast<double>(old) + a.sv * v);
   } else if (wave < 4) {
     const int r = wave;
     const double v = ((part(0, r) + part(1, r)) + (part(2, r) + part(3, r))) +
@@ -268,30 +275,61 @@ __global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
     const int oi = i0 + 4 * (lane >> 4) + r;
     if (oi < nx && oj < ny)
       a.p[static_cast<int64_t>(oi) * ny + oj] =
-          static_cast<float>(static_cast<double>(old) + v * static_cast<double>(cfac));
+          static_cast<float>(static_cast<double>(old) + a.sp * v * static_cast<double>(cfac));
   }
 }
 
 template <int KMAX, int PH>
-hipError_t configure() {
-  static int configured = -1;
+__global__ __launch_bounds__(NT) void phase2d_kernel(Phase2DArgs a) {
+  phase2d_body<KMAX, PH, false>(a);
+}
+
+// One phase of many solves of one shape: block (tile, solve), the solve's unscaled operators and
+// factors from the batch's solve table.
+template <int KMAX, int PH>
+__global__ __launch_bounds__(NT) void phase2d_batch_kernel(const BatchSolve* __restrict__ solves) {
+  const BatchSolve& S = solves[blockIdx.y];
+  const Phase2DArgs a{S.Gx, S.ldgx, S.mgx, S.Gy, S.ldgy, S.mgy, S.Dx, S.lddx, S.mdx, S.Dy, S.lddy, S.mdy,
+                      S.p, S.ux, S.uy, S.c2, S.nx, S.ny, S.sG, S.sD};
+  phase2d_body<KMAX, PH, true>(a);
+}
+
+// the dynamic LDS size above 64 KB is an attribute of each kernel instance, set once per device
+template <typename F>
+hipError_t configure(F* fn, size_t lds, int* configured) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (configured == dev) return hipSuccess;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(phase2d_kernel<KMAX, PH>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes<KMAX>()));
-  if (e == hipSuccess) configured = dev;
+  if (*configured == dev) return hipSuccess;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds));
+  if (e == hipSuccess) *configured = dev;
   return e;
 }
 
 template <int KMAX>
 hipError_t launch_one(int which, const Phase2DArgs& a, hipStream_t s) {
+  static int conf[2] = {-1, -1};
   const int nb = ((a.nx + T - 1) / T) * ((a.ny + T - 1) / T);
-  hipError_t e = which == 0 ? configure<KMAX, 0>() : configure<KMAX, 1>();
+  constexpr size_t lds = lds_bytes<KMAX, false>();
+  hipError_t e = which == 0 ? configure(phase2d_kernel<KMAX, 0>, lds, &conf[0])
+                            : configure(phase2d_kernel<KMAX, 1>, lds, &conf[1]);
   if (e != hipSuccess) return e;
-  if (which == 0) hipLaunchKernelGGL((phase2d_kernel<KMAX, 0>), dim3(nb), dim3(NT), lds_bytes<KMAX>(), s, a);
-  else hipLaunchKernelGGL((phase2d_kernel<KMAX, 1>), dim3(nb), dim3(NT), lds_bytes<KMAX>(), s, a);
+  if (which == 0) hipLaunchKernelGGL((phase2d_kernel<KMAX, 0>), dim3(nb), dim3(NT), lds, s, a);
+  else hipLaunchKernelGGL((phase2d_kernel<KMAX, 1>), dim3(nb), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KMAX>
+hipError_t launch_batch(int which, const BatchSolve* solves, int count, int nx, int ny, hipStream_t s) {
+  static int conf[2] = {-1, -1};
+  const int nb = ((nx + T - 1) / T) * ((ny + T - 1) / T);
+  constexpr size_t lds = lds_bytes<KMAX, true>();
+  hipError_t e = which == 0 ? configure(phase2d_batch_kernel<KMAX, 0>, lds, &conf[0])
+                            : configure(phase2d_batch_kernel<KMAX, 1>, lds, &conf[1]);
+  if (e != hipSuccess) return e;
+  if (which == 0) hipLaunchKernelGGL((phase2d_batch_kernel<KMAX, 0>), dim3(nb, count), dim3(NT), lds, s, solves);
+  else hipLaunchKernelGGL((phase2d_batch_kernel<KMAX, 1>), dim3(nb, count), dim3(NT), lds, s, solves);
   return hipGetLastError();
 }
 
@@ -299,7 +337,7 @@ Phase2DArgs make_args(const DevOperator& Gx, const DevOperator& Gy, const DevOpe
                       float* p, float* ux, float* uy, const float* c2, int nx, int ny) {
   return Phase2DArgs{static_cast<const float*>(Gx.data), Gx.Kp, Gx.Mp, static_cast<const float*>(Gy.data), Gy.Kp,
                      Gy.Mp, static_cast<const float*>(Dx.data), Dx.Kp, Dx.Mp, static_cast<const float*>(Dy.data), Dy.Kp,
-                     Dy.Mp, p, ux, uy, c2, nx, ny};
+                     Dy.Mp, p, ux, uy, c2, nx, ny, 1.0, 1.0};
 }
 
 // The operator slices are read as 16-byte rows of the zero-padded device matrices: every k < pad64(K)
@@ -334,6 +372,20 @@ hipError_t launch_phase2d(const DevOperator& Gx, const DevOperator& Gy, const De
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// One phase of `count` solves of one shape from the batch's device solve table (unscaled operators; the
+// factors sG, sD and the c0^2 maps of the table apply in the epilogue).  The caller checks that the
+// operators' padded rows cover pad64(K) columns (batch2d_phase_fits).
+hipError_t launch_phase2d_batch(int which, const BatchSolve* solves, int count, int nx, int ny, hipStream_t s) {
+  if (!phase2d_supported(nx, ny) || count < 1 || count > 65535) return hipErrorInvalidValue;
+  return (nx <= 256 && ny <= 256) ? launch_batch<256>(which, solves, count, nx, ny, s)
+                                  : launch_batch<512>(which, solves, count, nx, ny, s);
+}
+
+bool batch2d_phase_fits(int ldgx, int ldgy, int lddx, int lddy, int nx, int ny) {
+  return ldgx >= pad64(nx) && ldgy >= pad64(ny) && lddx >= pad64(nx - 1) && lddy >= pad64(ny - 1) && ldgx % 4 == 0 &&
+         ldgy % 4 == 0 && lddx % 4 == 0 && lddy % 4 == 0;
 }
 
 }  // namespace pstd

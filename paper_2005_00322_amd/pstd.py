@@ -249,6 +249,8 @@ def solve_faces_2d(shape, dx, dt, c0, R_faces, p0, n_steps, rho0=1000.0, batch=N
     cases, w = face_weights(R_faces)
     if batch is None:
         batch = Batch([{"shape": tuple(shape), "bcs": cs, "dx": dx, "dt": dt, "c0": c0} for cs in cases], rho0=rho0)
+        if max(shape) <= 512:
+            batch.set_config(tile=16)     # one shape: two fused phase launches per step over all 16 solves
     states = batch.new_states([p0] * len(cases))
     batch.init_states(states)
     batch.step(states, n_steps)

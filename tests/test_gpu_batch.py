@@ -152,3 +152,64 @@ def test_batched_workload_full():
         worst = max(worst, rel_l2(comb[i], opstd.combine_R(refs[0], refs[1], inst.R)))
     print("batched workload worst rel L2", worst, flush=True)
     assert worst < TOL["fp32"]
+
+
+def _uniform_solves(seed, count, shape):
+    rng = np.random.default_rng(seed)
+    solves, p0s = [], []
+    for _ in range(count):
+        faces = rng.integers(0, 2, size=4)
+        c0 = float(rng.uniform(1400, 1600))
+        solves.append({"shape": shape, "bcs": ((int(faces[0]), int(faces[1])), (int(faces[2]), int(faces[3]))),
+                       "dx": 1e-4, "dt": 0.3e-4 / c0, "c0": c0})
+        p0s.append(rng.standard_normal(shape))
+    return solves, p0s
+
+
+@pytest.mark.parametrize("seed,count,shape", [(11, 6, (40, 52)), (12, 3, (17, 9)), (13, 4, (300, 130))])
+def test_phase_path_matches_oracle(seed, count, shape):
+    """Tile 16: solves of one shape stepped by two fused phase launches per step."""
+    solves, p0s = _uniform_solves(seed, count, shape)
+    print("phase batch", shape, count, flush=True)
+    ps, us = _run(solves, p0s, 30, config={"tile": 16})
+    for s, p0, p, u in zip(solves, p0s, ps, us):
+        prob = opstd.Problem(s["shape"], s["bcs"], s["dx"], s["dt"], s["c0"])
+        po, uo = prob.run(p0, 30)
+        assert rel_l2(p, po) < TOL["fp32"]
+        for a in range(2):
+            assert rel_l2(u[a], uo[a]) < TOL["fp32"]
+
+
+def test_phase_path_sound_speed_maps():
+    import torch
+    from paper_2005_00322_amd import Batch
+    rng = np.random.default_rng(21)
+    shape, dx = (36, 44), 1e-4
+    solves, p0s, maps = [], [], []
+    for bc in (((1, 1), (0, 0)), ((0, 1), (1, 0)), ((0, 0), (0, 0))):
+        cm = workloads.smooth_c0_map(rng, shape, corr_nodes=6.0)
+        dt = 0.25 * dx / cm.max()
+        solves.append({"shape": shape, "bcs": bc, "dx": dx, "dt": dt, "c0": float(cm.max())})
+        p0s.append(workloads.gaussian(shape, dx, (shape[0] * dx / 2, shape[1] * dx / 2.5), 4 * dx))
+        maps.append(cm)
+    maps[2] = None                              # one homogeneous solve among them
+    with Batch(solves) as b:
+        b.set_c0_maps([None if m is None else torch.from_numpy(m.astype(np.float32)) for m in maps])
+        b.set_config(tile=16)
+        st = b.new_states(p0s)
+        b.init_states(st)
+        b.step(st, 80)
+        b.synchronize()
+        for i, (s, m) in enumerate(zip(solves, maps)):
+            kw = {} if m is None else {"c0_map": m.astype(np.float32).astype(np.float64)}
+            ref, _ = opstd.Problem(s["shape"], s["bcs"], dx, s["dt"], s["c0"], **kw).run(p0s[i], 80)
+            assert rel_l2(st[i].p.double().cpu().numpy(), ref) < TOL["fp32"]
+
+
+def test_phase_path_needs_one_shape():
+    from paper_2005_00322_amd import Batch, PstdError
+    solves, _ = _random_solves(14, 3, 20, 40)
+    solves[1]["shape"] = (21, 33)
+    with Batch(solves) as b:
+        with pytest.raises(PstdError):
+            b.set_config(tile=16)
