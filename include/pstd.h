@@ -219,9 +219,9 @@ int pstd_batch_combine_R(pstd_batch batch, const pstd_state* states, const int32
 int pstd_batch_set_config(pstd_batch batch, int32_t blocks, int32_t order, int32_t tile);
 
 /* Autotuner: time every candidate configuration (tile edge x block count x order, and tile 16 where it
- * applies) for trial_steps steps on scratch state buffers (the caller's states are not touched), keep the fastest and, if cache_path is
- * not NULL, store it in a small JSON file keyed by a signature of the batch; a later call with a matching
- * file skips the timing.  config_out (nullable, 4 ints): blocks, order, tile, 1 if taken from the cache.
+ * applies) for trial_steps steps on scratch state buffers (the caller's states are not touched), keep
+ * the fastest and, if cache_path is not NULL, store it in a small JSON file keyed by a signature of the
+ * batch; a later call with a matching file skips the timing.  config_out (nullable, 4 ints): blocks, order, tile, 1 if taken from the cache.
  * Synchronous. */
 int pstd_batch_autotune(pstd_batch batch, int32_t trial_steps, const char* cache_path, int32_t* config_out);
 
