@@ -20,6 +20,7 @@ from . import dtt
 
 NEUMANN = 0
 DIRICHLET = 1
+PERIODIC = 2   # both faces of an axis (last row of Table transform_choices: the Fourier basis)
 
 # Table transform_choices (§4.1): boundary pair (left, right) -> sequence types of p and u, the forward
 # transforms T1 (acts on p) and T2 (acts on u), and the signs of the k-space coefficients a1 = ±k, a2 = ±k.
@@ -149,6 +150,58 @@ class Axis:
         return self.div(np.eye(self.n - 1)).T
 
 
+class PeriodicAxis:
+    """A periodic axis (Fourier basis, last row of Table transform_choices): p on the n nodes j dx and u on
+    the n staggered points (j + 1/2) dx, one period n dx.  The staggered derivatives are those of
+    Eq. (fourier_pstd_solution) (§2) with the DFT: grad multiplies the spectrum by i k e^{+i k dx/2} (p
+    nodes to u points, the shift property Eq. (fourier_shift_property) with a = dx/2), div by
+    i k e^{-i k dx/2} (u points back to p nodes); k_m = 2 pi m / (n dx) over the signed indices of §2
+    (m = -n/2 .. n/2 - 1 for even n).  The Nyquist factor i k e^{i k dx/2} = -pi/dx is real, so both maps
+    are real.
+    """
+
+    def __init__(self, n: int, dx: float):
+        if n < 3:
+            raise ValueError("an axis needs at least 3 nodes")
+        self.n, self.dx = int(n), float(dx)
+        self.bc_left = self.bc_right = PERIODIC
+        self.p_lo, self.p_hi = 0, self.n - 1
+        self.M = self.n
+        self.periodic = True
+        self.k = 2.0 * np.pi * np.fft.fftfreq(self.n, d=self.dx)
+        self.k1 = np.abs(self.k)
+        # the DFT as a matrix (for the modal closed form): T1 x = fft(x), T1inv its inverse
+        j = np.arange(self.n)
+        self.T1 = np.exp(-2j * np.pi * np.outer(j, j) / self.n)
+        self.T1inv = np.conj(self.T1) / self.n
+
+    def grad(self, p: np.ndarray) -> np.ndarray:
+        f = 1j * self.k * np.exp(0.5j * self.k * self.dx)
+        return np.fft.ifft(np.fft.fft(p, axis=-1) * f, axis=-1).real
+
+    def div(self, u: np.ndarray) -> np.ndarray:
+        f = 1j * self.k * np.exp(-0.5j * self.k * self.dx)
+        return np.fft.ifft(np.fft.fft(u, axis=-1) * f, axis=-1).real
+
+    def node_weights(self) -> np.ndarray:
+        return np.ones(self.n)
+
+    def grad_matrix(self) -> np.ndarray:
+        """``grad`` as an n x n matrix."""
+        return self.grad(np.eye(self.n)).T
+
+    def div_matrix(self) -> np.ndarray:
+        """``div`` as an n x n matrix."""
+        return self.div(np.eye(self.n)).T
+
+
+def make_axis(n: int, bc_left: int, bc_right: int, dx: float):
+    """The axis object of a boundary pair: periodic needs both faces periodic."""
+    if (bc_left == PERIODIC) != (bc_right == PERIODIC):
+        raise ValueError("a periodic axis has both faces periodic")
+    return PeriodicAxis(n, dx) if bc_left == PERIODIC else Axis(n, bc_left, bc_right, dx)
+
+
 def _along(fn, x: np.ndarray, axis: int) -> np.ndarray:
     return np.moveaxis(fn(np.moveaxis(x, axis, -1)), -1, axis)
 
@@ -174,15 +227,17 @@ class Problem:
         self.bcs = tuple((int(a), int(b)) for a, b in self.bcs)
         if len(self.shape) != len(self.bcs):
             raise ValueError("one boundary pair per axis")
-        self.axes = [Axis(n, bl, br, self.dx) for n, (bl, br) in zip(self.shape, self.bcs)]
+        self.axes = [make_axis(n, bl, br, self.dx) for n, (bl, br) in zip(self.shape, self.bcs)]
 
     @property
     def ndim(self) -> int:
         return len(self.shape)
 
     def u_shape(self, a: int) -> tuple:
+        """n - 1 staggered points along a wall-bounded axis, n along a periodic one."""
         s = list(self.shape)
-        s[a] -= 1
+        if self.bcs[a][0] != PERIODIC:
+            s[a] -= 1
         return tuple(s)
 
     def project(self, p: np.ndarray) -> np.ndarray:
@@ -258,7 +313,7 @@ class Problem:
         for a in range(self.ndim):
             Wa = np.ones(1)
             for b in range(self.ndim):
-                Wa = np.multiply.outer(Wa, np.ones(self.shape[a] - 1) if b == a else ws[b])
+                Wa = np.multiply.outer(Wa, np.ones(self.u_shape(a)[a]) if b == a else ws[b])
             Wa = Wa.reshape(self.u_shape(a))
             F += self.rho0 * float(np.sum(Wa * u_prev[a] * u_next[a]))
         return F
@@ -295,7 +350,7 @@ class Problem:
         for a, ax in enumerate(self.axes):
             Q = dtt.apply(ax.T1inv, Q, a)
         out = np.zeros(self.shape)
-        out[tuple(slice(ax.p_lo, ax.p_hi + 1) for ax in self.axes)] = Q
+        out[tuple(slice(ax.p_lo, ax.p_hi + 1) for ax in self.axes)] = np.real(Q)   # periodic axes: the DFT
         return out
 
     def cfl_limit(self) -> float:
