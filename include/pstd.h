@@ -46,7 +46,10 @@ typedef enum {
 } pstd_status;
 
 /* Boundary condition of one face (§1: Neumann = sound-hard, Dirichlet = sound-soft). */
-typedef enum { PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1 } pstd_bc;
+/* Boundary of one face.  PERIODIC (both faces of an axis, the Fourier basis of Eq. (fourier_pstd_solution),
+ * §2): the axis is one period of n nodes and its particle velocity has n staggered points instead of
+ * n - 1; such axes run on the dense contraction path (not the fused 2D, FFT, 1D or batched paths). */
+typedef enum { PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1, PSTD_PERIODIC = 2 } pstd_bc;
 
 /* Arithmetic of the transform contractions.  FP64: state and operators in double.  FP32: state and
  * operators in float, FP32 accumulation.  SPLIT_BF16: float state; each contraction is
@@ -166,8 +169,9 @@ int pstd_plan_get_operator(pstd_plan plan, int32_t axis, int32_t which, double* 
 /* Host only (no GPU needed): the unscaled FP64 operator of one axis, exactly as the plan builder forms
  * it before folding the time-step constants in.  n nodes, boundary pair (bc_left, bc_right), spacing dx.
  * which 0: velocity operator T2^{-1} diag(a1) T1, (n-1) x n row-major (derivative of p on the
- * staggered points); which 1: pressure operator T1^{-1} diag(a2) T2, n x (n-1) row-major.  out must
- * hold the matrix.  Synchronous. */
+ * staggered points); which 1: pressure operator T1^{-1} diag(a2) T2, n x (n-1) row-major.  A periodic
+ * pair (both PSTD_PERIODIC) gives the n x n operators of Eq. (fourier_pstd_solution).  out must hold the
+ * matrix.  Synchronous. */
 int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out);
 
 /* Number of elements of p / of u[axis] for this plan. */

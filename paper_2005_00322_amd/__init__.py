@@ -4,8 +4,8 @@ The computation runs in the HIP kernels of ``libpstd.so`` (built from ``csrc/`` 
 package only marshals arguments across its C ABI (``include/pstd.h``).  PyTorch supplies device memory
 and the current stream.  There is no CPU fallback: every call raises if the library is missing.
 """
-from .pstd import (DIRICHLET, NEUMANN, Batch, Plan, PstdError, State, axis_operator, combine_R, combine_fields,
-                   face_weights, lib_path, load_library, solve_faces_2d)
+from .pstd import (DIRICHLET, NEUMANN, PERIODIC, Batch, Plan, PstdError, State, axis_operator, combine_R,
+                   combine_fields, face_weights, lib_path, load_library, solve_faces_2d)
 
 __all__ = ["Plan", "Batch", "State", "PstdError", "combine_R", "combine_fields", "face_weights", "solve_faces_2d",
-           "axis_operator", "NEUMANN", "DIRICHLET", "load_library", "lib_path"]
+           "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "load_library", "lib_path"]

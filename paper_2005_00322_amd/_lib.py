@@ -17,6 +17,7 @@ E_NONFINITE = -6
 
 NEUMANN = 0
 DIRICHLET = 1
+PERIODIC = 2   # both faces of an axis: the Fourier basis, n staggered points
 
 FP64 = 0
 FP32 = 1

@@ -109,7 +109,13 @@ void free_plan(pstd_plan_s* P) {
 }
 
 int64_t numel_p(const pstd_plan_s* P) { return P->n[0] * P->n[1] * P->n[2]; }
-int64_t numel_u(const pstd_plan_s* P, int a) { return numel_p(P) / P->n[a] * (P->n[a] - 1); }
+bool axis_periodic(const pstd_plan_s* P, int a) { return P->bc[2 * a] == PSTD_PERIODIC; }
+int64_t numel_u(const pstd_plan_s* P, int a) { return numel_p(P) / P->n[a] * (P->n[a] - (axis_periodic(P, a) ? 0 : 1)); }
+bool any_periodic(const pstd_plan_s* P) {
+  for (int a = 0; a < P->ndim; ++a)
+    if (axis_periodic(P, a)) return true;
+  return false;
+}
 
 // Geometry of the contraction along axis a for a field whose extent along a is `len`.
 void axis_geometry(const pstd_plan_s* P, int a, int64_t* outer, int64_t* inner) {
@@ -130,9 +136,11 @@ int ensure_dense(pstd_plan_s* P, int a) {
   if (P->G[a].data) return PSTD_OK;
   const int n = static_cast<int>(P->n[a]);
   if (n > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: dense operators are limited to 4097 nodes", a);
-  const AxisTables& t = axis_tables(n, axis_case(P->bc[2 * a], P->bc[2 * a + 1]));
-  int st = upload_operator(P, t.G, n - 1, n, const_G(P), &P->G[a]);
-  if (st == PSTD_OK) st = upload_operator(P, t.D, n, n - 1, const_D(P), &P->D[a]);
+  const AxisCase c = axis_case(P->bc[2 * a], P->bc[2 * a + 1]);
+  const AxisTables& t = axis_tables(n, c);
+  const int m = staggered_points(n, c);
+  int st = upload_operator(P, t.G, m, n, const_G(P), &P->G[a]);
+  if (st == PSTD_OK) st = upload_operator(P, t.D, n, m, const_D(P), &P->D[a]);
   return st;
 }
 
@@ -247,6 +255,7 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
 
 bool use_fused2d(const pstd_plan_s* P) {
   return P->ndim == 2 && P->prec == PSTD_FP32 && (P->path == PSTD_PATH_AUTO || P->path == PSTD_PATH_FUSED) &&
+         !any_periodic(P) &&
          phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]));
 }
 
@@ -318,8 +327,13 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
                   (long long)grid->n[a], fft_capacity(precision == PSTD_FP64),
                   precision == PSTD_FP64 ? "FP64" : "FP32 state");
     for (int f = 0; f < 2; ++f)
-      if (bc_per_face[2 * a + f] != PSTD_NEUMANN && bc_per_face[2 * a + f] != PSTD_DIRICHLET)
+      if (bc_per_face[2 * a + f] != PSTD_NEUMANN && bc_per_face[2 * a + f] != PSTD_DIRICHLET &&
+          bc_per_face[2 * a + f] != PSTD_PERIODIC)
         return fail(PSTD_E_INVALID_ARG, "bad boundary condition on face %d", 2 * a + f);
+    if ((bc_per_face[2 * a] == PSTD_PERIODIC) != (bc_per_face[2 * a + 1] == PSTD_PERIODIC))
+      return fail(PSTD_E_INVALID_ARG, "axis %d: a periodic axis has both faces periodic", a);
+    if (bc_per_face[2 * a] == PSTD_PERIODIC && grid->n[a] > 4097)
+      return fail(PSTD_E_UNSUPPORTED, "axis %d: periodic axes run on the dense path (at most 4097 nodes)", a);
   }
   if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
     return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
@@ -437,7 +451,7 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
   if (n_steps == 0) return PSTD_OK;
   const int pst = prepare_axes(P);
   if (pst != PSTD_OK) return pst;
-  if (P->ndim == 1 && !axis_fft(P, 0)) {
+  if (P->ndim == 1 && !axis_fft(P, 0) && !axis_periodic(P, 0)) {
     PSTD_HIP(launch_step1d(P->prec, P->G[0], P->D[0], st->p, st->u[0], static_cast<int>(P->n[0]), n_steps,
                            P->c2map, P->stream));
     st->step += n_steps;
@@ -490,7 +504,7 @@ int pstd_plan_set_path(pstd_plan P, int32_t path) {
     if (!any) return fail(PSTD_E_UNSUPPORTED, "no axis has 2(n-1) = 16 x 2^a 3^b 5^c within the FFT capacity");
   }
   if (path == PSTD_PATH_FUSED &&
-      !(P->ndim == 2 && P->prec == PSTD_FP32 &&
+      !(P->ndim == 2 && P->prec == PSTD_FP32 && !any_periodic(P) &&
         phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]))))
     return fail(PSTD_E_UNSUPPORTED, "the fused path needs a 2D FP32 plan of at most 512 x 512 nodes");
   const int old = P->path;
@@ -614,7 +628,9 @@ int pstd_check_finite(pstd_plan P, const pstd_state* st) {
 int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out) {
   if (!out) return fail(PSTD_E_INVALID_ARG, "out is null");
   if (n < 3 || n > 4097) return fail(PSTD_E_INVALID_ARG, "n must be in [3, 4097]");
-  if ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) || (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET))
+  const bool per = bc_left == PSTD_PERIODIC && bc_right == PSTD_PERIODIC;
+  if (!per &&
+      ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) || (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET)))
     return fail(PSTD_E_INVALID_ARG, "bad boundary condition");
   if (!(dx > 0) || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad dx or which");
   const AxisTables& t = axis_tables(static_cast<int>(n), axis_case(bc_left, bc_right));

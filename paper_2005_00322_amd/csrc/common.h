@@ -25,15 +25,20 @@ int fail(int status, const char* fmt, ...);
 
 // ---- host operator tables (tables.cpp) ------------------------------------------------------------
 // Per-axis boundary case of Table transform_choices.
-enum AxisCase { CASE_NN = 0, CASE_ND = 1, CASE_DN = 2, CASE_DD = 3 };
+// CASE_PP: a periodic axis (the Fourier basis).
+enum AxisCase { CASE_NN = 0, CASE_ND = 1, CASE_DN = 2, CASE_DD = 3, CASE_PP = 4 };
 
 inline AxisCase axis_case(int left, int right) {
+  if (left == PSTD_PERIODIC) return CASE_PP;
   return static_cast<AxisCase>(2 * (left == PSTD_DIRICHLET) + (right == PSTD_DIRICHLET));
 }
 
-// Unscaled FP64 operators of one axis for dx = 1 (scale by 1/dx):
-//   G: (n-1) x n row-major, velocity operator T2^{-1} diag(a1) T1
-//   D: n x (n-1) row-major, pressure operator T1^{-1} diag(a2) T2
+// Staggered points of an axis: n - 1 between two walls, n on a periodic axis.
+inline int staggered_points(int n, AxisCase c) { return c == CASE_PP ? n : n - 1; }
+
+// Unscaled FP64 operators of one axis for dx = 1 (scale by 1/dx), with m = staggered_points(n, case):
+//   G: m x n row-major, velocity operator T2^{-1} diag(a1) T1 (periodic: F^{-1} diag(i k e^{i k/2}) F)
+//   D: n x m row-major, pressure operator T1^{-1} diag(a2) T2 (periodic: F^{-1} diag(i k e^{-i k/2}) F)
 struct AxisTables {
   int n = 0;
   AxisCase c = CASE_NN;

@@ -155,7 +155,40 @@ std::map<std::pair<int, int>, AxisTables> g_cache;
 
 }  // namespace
 
+// A periodic axis, Eq. (fourier_pstd_solution): both operators are circulant.  With k_m = 2 pi m / n
+// over the signed indices of §2 (m = -n/2 .. n/2 - 1 for even n), entry (j, l) of G is
+// (1/n) sum_m Re(i k_m e^{i k_m (j - l + 1/2)}) = -(1/n) sum_m k_m sin(k_m (j - l + 1/2)), and of D the same
+// with j - l - 1/2 (the Nyquist term is real, so the sums are exact).
+static AxisTables periodic_tables(int n) {
+  std::vector<double> g(n), d(n);
+  const int m_lo = -(n / 2), m_hi = (n - 1) / 2;
+  for (int r = 0; r < n; ++r) {
+    double sg = 0.0, sd = 0.0;
+    for (int m = m_lo; m <= m_hi; ++m) {
+      const double k = 2.0 * M_PI * m / n;
+      sg -= k * std::sin(k * (r + 0.5));
+      sd -= k * std::sin(k * (r - 0.5));
+    }
+    g[r] = sg / n;
+    d[r] = sd / n;
+  }
+  AxisTables t;
+  t.n = n;
+  t.c = CASE_PP;
+  t.G.assign(static_cast<size_t>(n) * n, 0.0);
+  t.D.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < n; ++l) {
+      const int r = ((j - l) % n + n) % n;
+      t.G[static_cast<size_t>(j) * n + l] = g[r];
+      t.D[static_cast<size_t>(j) * n + l] = d[r];
+    }
+  t.kmax = 2.0 * M_PI * (n / 2) / n;
+  return t;
+}
+
 double axis_kmax(int n, AxisCase c) {
+  if (c == CASE_PP) return 2.0 * M_PI * (n / 2) / n;
   const CaseInfo ci = case_info(c);
   const bool left_d = (c == CASE_DN || c == CASE_DD);
   const bool right_d = (c == CASE_ND || c == CASE_DD);
@@ -169,6 +202,7 @@ const AxisTables& axis_tables(int n, AxisCase c) {
   auto key = std::make_pair(n, static_cast<int>(c));
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
+  if (c == CASE_PP) return g_cache.emplace(key, periodic_tables(n)).first->second;
 
   const CaseInfo ci = case_info(c);
   const bool left_d = (c == CASE_DN || c == CASE_DD);

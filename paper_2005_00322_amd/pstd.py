@@ -7,7 +7,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import DIRICHLET, NEUMANN, PRECISIONS, PstdError, check, load
+from ._lib import DIRICHLET, NEUMANN, PERIODIC, PRECISIONS, PstdError, check, load
 
 lib_path = _lib.LIB_PATH
 
@@ -41,7 +41,8 @@ def _faces(bcs, ndim):
 def axis_operator(n: int, bc_left: int, bc_right: int, dx: float, which: int) -> np.ndarray:
     """Unscaled FP64 operator of one axis as the library builds it (host only, no GPU needed)."""
     lib = load()
-    shape = (n - 1, n) if which == 0 else (n, n - 1)
+    m = n if int(bc_left) == PERIODIC else n - 1           # staggered points
+    shape = (m, n) if which == 0 else (n, m)
     out = np.zeros(shape, dtype=np.float64)
     check(lib.pstd_axis_operator(int(n), int(bc_left), int(bc_right), float(dx), int(which),
                                  out.ctypes.data_as(C.POINTER(C.c_double))), "pstd_axis_operator")
@@ -102,8 +103,10 @@ class Plan:
 
     # -- state -------------------------------------------------------------------------------------
     def u_shape(self, a):
+        """n - 1 staggered points along a wall-bounded axis, n along a periodic one."""
         s = list(self.shape)
-        s[a] -= 1
+        if int(self.bcs[a][0]) != PERIODIC:
+            s[a] -= 1
         return tuple(s)
 
     def new_state(self, p0=None) -> State:

@@ -1,0 +1,75 @@
+"""GPU parity of periodic (Fourier) axes, Eq. (fourier_pstd_solution), alone and mixed with wall-bounded
+axes, through the dense contraction path, against the FP64 oracle; a wrapped pulse against the sum of
+its periodic free-space images."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import TOL, oracle_problem, rel_l2, run_gpu
+from oracle import images
+from oracle import pstd as opstd
+
+pytestmark = pytest.mark.gpu
+P, N, D = opstd.PERIODIC, opstd.NEUMANN, opstd.DIRICHLET
+
+
+def _case(seed, shape, bcs, steps, precision):
+    rng = np.random.default_rng(seed)
+    dx, c0 = 1e-4, float(rng.uniform(1400, 1600))
+    dt = 0.3 * dx / c0
+    p0 = rng.standard_normal(shape)
+    return workloads.Case("periodic_%d" % seed, shape, bcs, dx, dt, c0, steps, p0, precision=precision)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [64, 65])
+def test_1d(prec, n):
+    case = _case(n, (n,), ((P, P),), 200, prec)
+    print("periodic 1d", n, prec, flush=True)
+    p, u = run_gpu(case)
+    po, uo = oracle_problem(case).run(case.p0, case.steps)
+    assert u[0].shape == (n,)
+    assert rel_l2(p, po) < TOL[prec]
+    assert rel_l2(u[0], uo[0]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16"])
+@pytest.mark.parametrize("seed,shape,bcs", [
+    (1, (36, 28), ((P, P), (N, D))),
+    (2, (30, 41), ((D, D), (P, P))),
+    (3, (24, 24), ((P, P), (P, P))),
+    (4, (14, 18, 16), ((D, N), (P, P), (N, N))),
+    (5, (12, 10, 17), ((P, P), (D, D), (P, P))),
+])
+def test_mixed(prec, seed, shape, bcs):
+    case = _case(seed, shape, bcs, 40, prec)
+    print("periodic", shape, bcs, prec, flush=True)
+    p, u = run_gpu(case)
+    prob = oracle_problem(case)
+    po, uo = prob.run(case.p0, case.steps)
+    assert rel_l2(p, po) < TOL[prec]
+    for a in range(len(shape)):
+        assert u[a].shape == prob.u_shape(a)
+        assert rel_l2(u[a], uo[a]) < TOL[prec]
+
+
+def test_wrapped_pulse_fp64():
+    n, dx, c0 = 160, 1e-4, 1500.0
+    L = n * dx
+    dt = 0.2 * dx / c0
+    xs, sigma, m = 0.3 * L, 4 * dx, 1700               # c0 t = 340 dx: wrapped twice
+    x = np.arange(n) * dx
+    p0 = sum(np.exp(-0.5 * (x - xs - j * L) ** 2 / sigma ** 2) for j in range(-2, 3))
+    case = workloads.Case("wrap1d", (n,), ((P, P),), dx, dt, c0, m, p0, precision="fp64")
+    p, _ = run_gpu(case)
+    reach = c0 * m * dt + 12 * sigma
+    js = range(-int(reach / L) - 2, int(reach / L) + 3)
+    ref = sum(images.free_space_gaussian(np.abs(x - xs - j * L), 1, 1.0, sigma, c0, dt, m) for j in js)
+    assert np.max(np.abs(p - ref)) < 1e-9
+
+
+def test_fused_path_refused():
+    from paper_2005_00322_amd import Plan, PstdError
+    with Plan((32, 32), 1e-4, 1e-8, 1500.0, ((P, P), (N, N)), precision="fp32") as plan:
+        with pytest.raises(PstdError):
+            plan.set_path("fused")
