@@ -42,6 +42,7 @@ WORKLOADS = {
     "batched": ("batched", "fp32", 1000, 10),
     "faces": ("faces2d", "fp32", 1000, 10),
     "pstd2d_large": ("pstd2d_large", "fp32", 200, 50),
+    "periodic2d": ("periodic2d", "fp32", 2000, 200),
     "nop": ("nop", "bf16", 20, 3),
 }
 
@@ -53,6 +54,7 @@ SOURCES = {
     "pstd2d": ("common.h", "capi.hip", "kernels_phase2d.hip"),
     "pstd3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
     "pstd2d_large": ("common.h", "capi.hip", "fft_plan.cpp", "kernels_fft.hip"),
+    "periodic2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
     "batched": ("common.h", "capi_batch.hip", "kernels_batch2d.hip"),
     "faces": ("common.h", "capi.hip", "capi_batch.hip", "kernels_batch2d.hip", "kernels_misc.hip"),
     "nop": ("common.h", "capi_nop.hip", "kernels_nop.hip"),
@@ -81,29 +83,32 @@ def fft_factorable(n):
     return L == 1
 
 
-def uses_fft(shape, axis, precision):
-    """Mirrors the library's automatic choice: axes above 512 nodes (1D: above 1365) with 2(n-1) =
-    16 x 2^a 3^b 5^c run on the FFT path."""
+def uses_fft(shape, axis, precision, periodic=False):
+    """Mirrors the library's automatic choice: wall-bounded axes above 512 nodes (1D: above 1365) with
+    2(n-1) = 16 x 2^a 3^b 5^c run on the FFT path; periodic axes always take the dense path."""
+    if periodic:
+        return False
     n = shape[axis]
     lim = 1365 if len(shape) == 1 else 512
     cap = 8192 if precision == "fp64" else 16384
     return n > lim and fft_factorable(n) and 2 * (n - 1) <= cap
 
 
-def contraction_cost(shape, axis, which, precision):
+def contraction_cost(shape, axis, which, precision, periodic=False):
     """Algorithmic flops and bytes of one launch along an axis (kernel table).
 
     Dense path: 2*n_in flops per output point (a dense n_out x n_in operator applied along the axis;
     three bf16 products for split-bf16).  FFT path: 2 x 5 L log2(L) / 2 flops per line (a forward and an
     inverse complex transform of length L = 2(n-1) shared by two lines).  Bytes: the input field read
-    once, the output field read and written once.
+    once, the output field read and written once.  A periodic axis holds n pressure and n velocity
+    points (an n x n circulant operator).
     """
     n = shape[axis]
-    n_in = n if which == 0 else n - 1
-    n_out = n - 1 if which == 0 else n
+    n_in = n if (which == 0 or periodic) else n - 1
+    n_out = n if (which == 1 or periodic) else n - 1
     lines = int(np.prod(shape)) // n
     esz = 8 if precision == "fp64" else 4
-    if uses_fft(shape, axis, precision):
+    if uses_fft(shape, axis, precision, periodic):
         L = 2 * (n - 1)
         flops = 5.0 * L * np.log2(L) * lines
     else:
@@ -112,18 +117,19 @@ def contraction_cost(shape, axis, which, precision):
     return flops, bytes_
 
 
-def phase_cost(shape, which, precision):
+def phase_cost(shape, which, precision, periodic=None):
     """Algorithmic flops and bytes of one fused phase launch (every axis at once).
 
     Velocity phase: every axis's contraction; p read once, each u_a read and written once.
     Pressure phase: every axis's contraction; each u_a read once, p read and written once.
     """
+    periodic = periodic or [False] * len(shape)
     flops = 0.0
     esz = 8 if precision == "fp64" else 4
     pts = int(np.prod(shape))
-    u_pts = [pts // n * (n - 1) for n in shape]
+    u_pts = [pts // n * (n if per else n - 1) for n, per in zip(shape, periodic)]
     for a in range(len(shape)):
-        flops += contraction_cost(shape, a, which, precision)[0]
+        flops += contraction_cost(shape, a, which, precision, periodic[a])[0]
     if which == 0:
         bytes_ = esz * (pts + 2 * sum(u_pts))
     else:
@@ -205,7 +211,8 @@ def cpu_baseline_leg(case, gpu_p, total_steps, budget_s=12.0):
     err = float(np.linalg.norm(gpu_p - ref) / np.linalg.norm(ref))
     base = {"value": case.points * steps / dt, "unit": "grid-point updates/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": "%d of %d time steps of the same %s workload, FP64 NumPy, direct DST/DCT matrices"
+            "sample": "%d of %d time steps of the same %s workload, FP64 NumPy (direct DST/DCT matrices on "
+                      "wall-bounded axes, FFTs on periodic axes)"
                       % (steps, case.steps, case.name)}
     return base, err
 
@@ -604,23 +611,24 @@ def main():
     # dominant kernel: the single contraction launch with the largest average duration
     state_copy = plan.new_state(case.p0)
     plan.init_state(state_copy)
+    periodic = [l == 2 for l, _ in case.bcs]
     fused = uses_fused_path(case.shape, precision)
     durs = time_dominant_kernel(plan, state_copy, fused)
     (axis, which), dur_ms = max(durs.items(), key=lambda kv: kv[1])
     if axis < 0:
-        flops, bytes_ = phase_cost(case.shape, which, precision)
+        flops, bytes_ = phase_cost(case.shape, which, precision, periodic)
     else:
-        flops, bytes_ = contraction_cost(case.shape, axis, which, precision)
+        flops, bytes_ = contraction_cost(case.shape, axis, which, precision, periodic[axis])
     gbs = bytes_ / (dur_ms * 1e-3) / 1e9
     tfs = flops / (dur_ms * 1e-3) / 1e12
     peak_c = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"], "split_bf16": PEAK["bf16_TFs"]}[precision]
-    if axis >= 0 and uses_fft(case.shape, axis, precision):
+    if axis >= 0 and uses_fft(case.shape, axis, precision, periodic[axis]):
         peak_c = PEAK["fp64_TFs"] if precision == "fp64" else PEAK["fp32_TFs"]   # FFT butterflies: vector ALU
     ai = flops / bytes_
     ridge = peak_c * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     src_hash = kernel_source_hash(args.workload)
     key = ("fused" if axis < 0 else "axis%d" % axis) + "_" + ("velocity" if which == 0 else "pressure")
-    if axis >= 0 and uses_fft(case.shape, axis, precision):
+    if axis >= 0 and uses_fft(case.shape, axis, precision, periodic[axis]):
         key += "_fft"
     traffic = load_traffic(args.workload, key, src_hash)
     if ai < ridge:
@@ -652,7 +660,7 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": case.name, "grid": list(case.shape),
-                   "bc": ["%s%s" % ("ND"[l], "ND"[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
+                   "bc": ["%s%s" % ("NDP"[l], "NDP"[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
                    "precision": precision, "parallelism": "single-gpu"},
         "accuracy": {"rel_l2_vs_fp64_oracle": err, "after_steps": W + K,
                      "tolerance": {"fp32": 1e-5, "fp64": 1e-10, "split_bf16": 1e-3}[precision]},

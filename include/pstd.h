@@ -48,7 +48,8 @@ typedef enum {
 /* Boundary condition of one face (§1: Neumann = sound-hard, Dirichlet = sound-soft). */
 /* Boundary of one face.  PERIODIC (both faces of an axis, the Fourier basis of Eq. (fourier_pstd_solution),
  * §2): the axis is one period of n nodes and its particle velocity has n staggered points instead of
- * n - 1; such axes run on the dense contraction path (not the fused 2D, FFT, 1D or batched paths). */
+ * n - 1; such axes run on the dense contraction path or, in 2D FP32 plans, the fused path (not the FFT,
+ * 1D or batched paths). */
 typedef enum { PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1, PSTD_PERIODIC = 2 } pstd_bc;
 
 /* Arithmetic of the transform contractions.  FP64: state and operators in double.  FP32: state and
@@ -106,8 +107,8 @@ int pstd_step(pstd_plan plan, pstd_state* state, int64_t n_steps);
 
 /* Execution path of pstd_step.
  *   PER_AXIS: one dense contraction kernel per axis and half step (axes up to 4097 nodes).
- *   FUSED:    2D FP32 grids of at most 512 x 512 nodes: two kernels per step (every velocity tile, then
- *             every pressure tile with both axes' terms).
+ *   FUSED:    2D FP32 grids of at most 512 x 512 nodes, walls or periodic axes: two kernels per step
+ *             (every velocity tile, then every pressure tile with both axes' terms).
  *   FFT:      every axis whose extended period 2(n-1) is 16 x 2^a 3^b 5^c (up to 16384 for a float state,
  *             8192 for FP64) applies its operators as LDS-resident FFTs of the field's symmetric
  *             extension (§3.2: each DTT is a DFT of an evenly or oddly extended sequence), one kernel per

@@ -111,11 +111,6 @@ void free_plan(pstd_plan_s* P) {
 int64_t numel_p(const pstd_plan_s* P) { return P->n[0] * P->n[1] * P->n[2]; }
 bool axis_periodic(const pstd_plan_s* P, int a) { return P->bc[2 * a] == PSTD_PERIODIC; }
 int64_t numel_u(const pstd_plan_s* P, int a) { return numel_p(P) / P->n[a] * (P->n[a] - (axis_periodic(P, a) ? 0 : 1)); }
-bool any_periodic(const pstd_plan_s* P) {
-  for (int a = 0; a < P->ndim; ++a)
-    if (axis_periodic(P, a)) return true;
-  return false;
-}
 
 // Geometry of the contraction along axis a for a field whose extent along a is `len`.
 void axis_geometry(const pstd_plan_s* P, int a, int64_t* outer, int64_t* inner) {
@@ -255,7 +250,6 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
 
 bool use_fused2d(const pstd_plan_s* P) {
   return P->ndim == 2 && P->prec == PSTD_FP32 && (P->path == PSTD_PATH_AUTO || P->path == PSTD_PATH_FUSED) &&
-         !any_periodic(P) &&
          phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]));
 }
 
@@ -504,7 +498,7 @@ int pstd_plan_set_path(pstd_plan P, int32_t path) {
     if (!any) return fail(PSTD_E_UNSUPPORTED, "no axis has 2(n-1) = 16 x 2^a 3^b 5^c within the FFT capacity");
   }
   if (path == PSTD_PATH_FUSED &&
-      !(P->ndim == 2 && P->prec == PSTD_FP32 && !any_periodic(P) &&
+      !(P->ndim == 2 && P->prec == PSTD_FP32 &&
         phase2d_supported(static_cast<int>(P->n[0]), static_cast<int>(P->n[1]))))
     return fail(PSTD_E_UNSUPPORTED, "the fused path needs a 2D FP32 plan of at most 512 x 512 nodes");
   const int old = P->path;

@@ -34,16 +34,17 @@ constexpr int T = 16;                   // output tile edge
 constexpr int NT = 512;                 // eight waves
 constexpr uint32_t kOOB = 0x80000000u;  // buffer offset past every range: the load returns zero
 
+// mx, my: staggered points along x and y, n - 1 between two walls and n on a periodic axis
 struct Phase2DArgs {
-  const float* Gx; int ldgx, mgx;   // (nx-1) x nx operator, row stride ldgx, mgx rows allocated (zero padded)
-  const float* Gy; int ldgy, mgy;   // (ny-1) x ny
-  const float* Dx; int lddx, mdx;   // nx x (nx-1)
-  const float* Dy; int lddy, mdy;   // ny x (ny-1)
+  const float* Gx; int ldgx, mgx;   // mx x nx operator, row stride ldgx, mgx rows allocated (zero padded)
+  const float* Gy; int ldgy, mgy;   // my x ny
+  const float* Dx; int lddx, mdx;   // nx x mx
+  const float* Dy; int lddy, mdy;   // ny x my
   float* p;                         // nx x ny
-  float* ux;                        // (nx-1) x ny
-  float* uy;                        // nx x (ny-1)
+  float* ux;                        // mx x ny
+  float* uy;                        // nx x my
   const float* c2;                  // nx x ny or null
-  int nx, ny;
+  int nx, ny, mx, my;
   double sv, sp;                    // velocity / pressure factors on the contractions (1 for folded operators)
 };
 
@@ -185,7 +186,7 @@ __device__ __forceinline__ void phase2d_body(const Phase2DArgs& a) {
   constexpr int SL = T * (KMAX + 4);
   extern __shared__ float lds[];
   double* red = reinterpret_cast<double*>(ALIAS ? lds : lds + 4 * SL);   // [wave][reg][lane], eight waves
-  const int nx = a.nx, ny = a.ny;
+  const int nx = a.nx, ny = a.ny, mx = a.mx, my = a.my;
   const int tiles_y = (ny + T - 1) / T;
   const int nb = gridDim.x;
   int b = blockIdx.x;
@@ -201,8 +202,8 @@ __device__ __forceinline__ void phase2d_body(const Phase2DArgs& a) {
   const int lda1 = PH == 0 ? a.ldgy : a.lddy, ma1 = PH == 0 ? a.mgy : a.mdy;
   const float* X0 = PH == 0 ? a.p : a.ux;                   // ld ny, K0 rows
   const float* X1 = PH == 0 ? a.p : a.uy;                   // nx rows of K1
-  const int K0 = PH == 0 ? nx : nx - 1, K1 = PH == 0 ? ny : ny - 1;
-  const int ld1 = PH == 0 ? ny : ny - 1;
+  const int K0 = PH == 0 ? nx : mx, K1 = PH == 0 ? ny : my;
+  const int ld1 = PH == 0 ? ny : my;
   const int Kp0 = pad64(K0), Kp1 = pad64(K1);
 
   const rsrc_t rA0 = make_rsrc(A0, 4u * static_cast<uint32_t>(ma0 * lda0));
@@ -217,7 +218,7 @@ __device__ __forceinline__ void phase2d_body(const Phase2DArgs& a) {
   const int oj = j0 + (lane & 15);
   if (PH == 0) {
     float* Y = wave < 4 ? a.ux : a.uy;
-    const int rows = wave < 4 ? nx - 1 : nx, cols = wave < 4 ? ny : ny - 1;
+    const int rows = wave < 4 ? mx : nx, cols = wave < 4 ? ny : my;
     const rsrc_t rY = make_rsrc(Y, 4u * static_cast<uint32_t>(rows * cols));
     const int oi = i0 + 4 * (lane >> 4) + (wave & 3);
     old = ld_f32(rY, (oi < rows && oj < cols) ? 4u * static_cast<uint32_t>(oi * cols + oj) : kOOB);
@@ -263,7 +264,7 @@ __device__ __forceinline__ void phase2d_body(const Phase2DArgs& a) {
   if (PH == 0) {
     const int c = wave >> 2, r = wave & 3;
     float* Y = c == 0 ? a.ux : a.uy;
-    const int rows = c == 0 ? nx - 1 : nx, cols = c == 0 ? ny : ny - 1;
+    const int rows = c == 0 ? mx : nx, cols = c == 0 ? ny : my;
     const double v = (part(4 * c, r) + part(4 * c + 1, r)) + (part(4 * c + 2, r) + part(4 * c + 3, r));
     const int oi = i0 + 4 * (lane >> 4) + r;
     if (oi < rows && oj < cols)
@@ -290,7 +291,7 @@ template <int KMAX, int PH>
 __global__ __launch_bounds__(NT) void phase2d_batch_kernel(const BatchSolve* __restrict__ solves) {
   const BatchSolve& S = solves[blockIdx.y];
   const Phase2DArgs a{S.Gx, S.ldgx, S.mgx, S.Gy, S.ldgy, S.mgy, S.Dx, S.lddx, S.mdx, S.Dy, S.lddy, S.mdy,
-                      S.p, S.ux, S.uy, S.c2, S.nx, S.ny, S.sG, S.sD};
+                      S.p, S.ux, S.uy, S.c2, S.nx, S.ny, S.nx - 1, S.ny - 1, S.sG, S.sD};
   phase2d_body<KMAX, PH, true>(a);
 }
 
@@ -337,15 +338,19 @@ Phase2DArgs make_args(const DevOperator& Gx, const DevOperator& Gy, const DevOpe
                       float* p, float* ux, float* uy, const float* c2, int nx, int ny) {
   return Phase2DArgs{static_cast<const float*>(Gx.data), Gx.Kp, Gx.Mp, static_cast<const float*>(Gy.data), Gy.Kp,
                      Gy.Mp, static_cast<const float*>(Dx.data), Dx.Kp, Dx.Mp, static_cast<const float*>(Dy.data), Dy.Kp,
-                     Dy.Mp, p, ux, uy, c2, nx, ny, 1.0, 1.0};
+                     Dy.Mp, p, ux, uy, c2, nx, ny, Gx.M, Gy.M, 1.0, 1.0};
 }
 
 // The operator slices are read as 16-byte rows of the zero-padded device matrices: every k < pad64(K)
-// lies inside a row, and rows past the allocation read as zero.
+// lies inside a row, and rows past the allocation read as zero.  The staggered extent of an axis (the
+// rows of G, the columns of D) is n - 1 between walls or n on a periodic axis.
 bool operators_fit(const DevOperator& Gx, const DevOperator& Gy, const DevOperator& Dx, const DevOperator& Dy,
                    int nx, int ny) {
-  return Gx.Kp >= pad64(nx) && Gy.Kp >= pad64(ny) && Dx.Kp >= pad64(nx - 1) && Dy.Kp >= pad64(ny - 1) &&
-         Gx.Kp % 4 == 0 && Gy.Kp % 4 == 0 && Dx.Kp % 4 == 0 && Dy.Kp % 4 == 0;
+  const int mx = Gx.M, my = Gy.M;
+  return Gx.K == nx && Gy.K == ny && Dx.M == nx && Dy.M == ny && Dx.K == mx && Dy.K == my &&
+         (mx == nx - 1 || mx == nx) && (my == ny - 1 || my == ny) && Gx.Kp >= pad64(nx) && Gy.Kp >= pad64(ny) &&
+         Dx.Kp >= pad64(mx) && Dy.Kp >= pad64(my) && Gx.Kp % 4 == 0 && Gy.Kp % 4 == 0 && Dx.Kp % 4 == 0 &&
+         Dy.Kp % 4 == 0;
 }
 
 }  // namespace

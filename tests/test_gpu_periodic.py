@@ -1,6 +1,6 @@
 """GPU parity of periodic (Fourier) axes, Eq. (fourier_pstd_solution), alone and mixed with wall-bounded
 axes, through the dense contraction path, against the FP64 oracle; a wrapped pulse against the sum of
-its periodic free-space images."""
+its periodic free-space images; 2D FP32 plans on the fused path and on the per-axis path."""
 import numpy as np
 import pytest
 
@@ -68,8 +68,42 @@ def test_wrapped_pulse_fp64():
     assert np.max(np.abs(p - ref)) < 1e-9
 
 
-def test_fused_path_refused():
-    from paper_2005_00322_amd import Plan, PstdError
-    with Plan((32, 32), 1e-4, 1e-8, 1500.0, ((P, P), (N, N)), precision="fp32") as plan:
-        with pytest.raises(PstdError):
-            plan.set_path("fused")
+@pytest.mark.parametrize("path", ["fused", "per_axis"])
+@pytest.mark.parametrize("seed,shape,bcs", [
+    (11, (36, 28), ((P, P), (N, D))),
+    (12, (30, 41), ((D, N), (P, P))),
+    (13, (24, 40), ((P, P), (P, P))),
+    (14, (300, 70), ((P, P), (D, D))),    # nx > 256: the 512-wide instance, ragged tiles
+    (15, (17, 259), ((N, N), (P, P))),
+])
+def test_2d_fp32_paths(path, seed, shape, bcs):
+    """The fused two-kernel step and the per-axis contractions of a 2D FP32 plan with periodic axes."""
+    case = _case(seed, shape, bcs, 60, "fp32")
+    print("periodic 2d", path, shape, bcs, flush=True)
+    p, u = run_gpu(case, path=path)
+    prob = oracle_problem(case)
+    po, uo = prob.run(case.p0, case.steps)
+    assert rel_l2(p, po) < TOL["fp32"]
+    for a in range(2):
+        assert u[a].shape == prob.u_shape(a)
+        assert rel_l2(u[a], uo[a]) < TOL["fp32"]
+
+
+def test_fused_apply_axis_matches_per_axis():
+    """One fused phase launch (axis -1) equals the per-axis launches of the same phase."""
+    import torch
+
+    from paper_2005_00322_amd import Plan
+    case = _case(16, (40, 33), ((P, P), (N, D)), 1, "fp32")
+    outs = []
+    for path in ("fused", "per_axis"):
+        with Plan(case.shape, case.dx, case.dt, case.c0, case.bcs, precision="fp32") as plan:
+            plan.set_path(path)
+            st = plan.new_state(case.p0)
+            plan.init_state(st)
+            for which in (0, 1, 0):
+                plan.apply_axis(st, -1, which)
+            torch.cuda.synchronize()
+            outs.append([st.p.double().cpu().numpy()] + [u.double().cpu().numpy() for u in st.u])
+    for a, b in zip(*outs):
+        assert rel_l2(a, b) < TOL["fp32"]

@@ -35,6 +35,7 @@ import numpy as np
 SEED_BASE = 200500322
 NEUMANN = 0
 DIRICHLET = 1
+PERIODIC = 2
 RHO0 = 1000.0
 DX = 1e-4
 
@@ -108,6 +109,20 @@ def pstd2d(scale: float = 1.0, steps: int | None = None) -> Case:
     bcs = ((DIRICHLET, DIRICHLET), (NEUMANN, NEUMANN))
     st = 2000 if steps is None else steps
     return Case("pstd2d_%dx%d_xDD_yNN" % shape, shape, bcs, DX, 0.3 * DX / c0, c0, st, p0,
+                extra={"centre": centre})
+
+
+def periodic2d(n: int = 256, steps: int = 2000) -> Case:
+    """The disc of pstd2d in a 256^2 domain that is periodic along x (a Fourier axis) and bounded by a
+    Neumann and a Dirichlet wall along y, CFL 0.3: the wall-bounded and the Fourier discretisations of
+    the method side by side in one solve."""
+    rng = rng_for(7)
+    shape = (n, n)
+    c0 = 1500.0
+    centre = _centre(rng, shape, 9, DX)
+    p0 = tapered_disc(shape, DX, centre, 4 * DX, 8 * DX)
+    bcs = ((PERIODIC, PERIODIC), (NEUMANN, DIRICHLET))
+    return Case("periodic2d_%dx%d_xPP_yND" % shape, shape, bcs, DX, 0.3 * DX / c0, c0, steps, p0,
                 extra={"centre": centre})
 
 
