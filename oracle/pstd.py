@@ -149,6 +149,62 @@ class Axis:
         """The linear map ``div`` as an n x (n-1) matrix (rows of Dirichlet nodes are zero)."""
         return self.div(np.eye(self.n - 1)).T
 
+    # -- collocated differentiation and staggered interpolation (§3.3, §3.4) ------------------------
+    # Differentiation turns a symmetric sequence into an antisymmetric one and back; interpolation by
+    # half a grid step keeps the symmetry and swaps whole-sample for half-sample ends.  On the p nodes
+    # the sequence of the other symmetry is taken by the transform of the other kind and the same type
+    # as T1 (the antisymmetric end of a Neumann wall excludes its node, the symmetric end of a Dirichlet
+    # wall includes it); on the staggered points by the other kind and the same type as T2.
+    def _dual_range(self) -> tuple[int, int]:
+        lo = 1 if self.bc_left == NEUMANN else 0
+        hi = self.n - 2 if self.bc_right == NEUMANN else self.n - 1
+        return lo, hi
+
+    def _dual_inverse(self, tid, L):
+        kind, typ = tid
+        other = ("S" if kind == "C" else "C", typ)
+        idx, _ = wavenumber_indices(*other, self.M)
+        return idx, dtt.inverse_matrix(*other, L)
+
+    def _to_nodes(self, coef, src_idx):
+        """Inverse transform onto the p nodes with the symmetry opposite to p's (zero outside its sample)."""
+        lo, hi = self._dual_range()
+        idx, inv = self._dual_inverse(self.T1_id, hi - lo + 1)
+        out = np.zeros(coef.shape[:-1] + (self.n,), dtype=np.float64)
+        out[..., lo:hi + 1] = _reindex(coef, src_idx, idx) @ inv.T
+        return out
+
+    def _to_staggered(self, coef, src_idx):
+        """Inverse transform onto the staggered points with the symmetry opposite to u's."""
+        idx, inv = self._dual_inverse(self.T2_id, self.n - 1)
+        return _reindex(coef, src_idx, idx) @ inv.T
+
+    def collocated_grad_p(self, p: np.ndarray) -> np.ndarray:
+        """dp/dx on the p nodes (§3.3): forward T1, multiply by a1 = ±k, inverse of the other kind."""
+        coef = p[..., self.p_lo:self.p_hi + 1] @ self.T1.T
+        return self._to_nodes(coef * (self.a1_sign * self.k1), self.n1)
+
+    def collocated_grad_u(self, u: np.ndarray) -> np.ndarray:
+        """du/dx on the staggered points (§3.3): forward T2, multiply by a2 = ±k, inverse of the other kind."""
+        coef = u @ self.T2.T
+        return self._to_staggered(coef * (self.a2_sign * self.k2), self.n2)
+
+    def interp_p_to_u(self, p: np.ndarray) -> np.ndarray:
+        """p resampled on the staggered points (§3.4): forward T1, no k factor, half-sample inverse."""
+        coef = p[..., self.p_lo:self.p_hi + 1] @ self.T1.T
+        return self._to_staggered(coef, self.n1)
+
+    def interp_u_to_p(self, u: np.ndarray) -> np.ndarray:
+        """u resampled on the p nodes (§3.4): forward T2, no k factor, whole-sample inverse."""
+        return self._to_nodes(u @ self.T2.T, self.n2)
+
+    def resample_matrix(self, which: int) -> np.ndarray:
+        """2: collocated d/dx on the nodes (n x n); 3: collocated d/dx on the staggered points
+        ((n-1) x (n-1)); 4: nodes -> staggered points ((n-1) x n); 5: staggered points -> nodes (n x (n-1))."""
+        fn, size = {2: (self.collocated_grad_p, self.n), 3: (self.collocated_grad_u, self.n - 1),
+                    4: (self.interp_p_to_u, self.n), 5: (self.interp_u_to_p, self.n - 1)}[which]
+        return fn(np.eye(size)).T
+
 
 class PeriodicAxis:
     """A periodic axis (Fourier basis, last row of Table transform_choices): p on the n nodes j dx and u on
