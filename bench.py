@@ -43,6 +43,7 @@ WORKLOADS = {
     "faces": ("faces2d", "fp32", 1000, 10),
     "pstd2d_large": ("pstd2d_large", "fp32", 200, 50),
     "periodic2d": ("periodic2d", "fp32", 2000, 200),
+    "resample3d": ("pstd3d", "split_bf16", 20, 3),
     "nop": ("nop", "bf16", 20, 3),
 }
 
@@ -55,6 +56,7 @@ SOURCES = {
     "pstd3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
     "pstd2d_large": ("common.h", "capi.hip", "fft_plan.cpp", "kernels_fft.hip"),
     "periodic2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
+    "resample3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
     "batched": ("common.h", "capi_batch.hip", "kernels_batch2d.hip"),
     "faces": ("common.h", "capi.hip", "capi_batch.hip", "kernels_batch2d.hip", "kernels_misc.hip"),
     "nop": ("common.h", "capi_nop.hip", "kernels_nop.hip"),
@@ -407,7 +409,142 @@ def run_faces(args, K, W):
     print(json.dumps(line))
 
 
-def faces_cpu_leg(case, got, total_steps, budget_s=12.0):
+def resample_cost(shape, axis, which, precision):
+    """Algorithmic flops and bytes of one launch of a collocated-derivative / interpolation operator along
+    an axis: a dense n_out x n_in operator per line (three bf16 products for split-bf16), the input read
+    once and the output written once."""
+    n = shape[axis]
+    n_in = n if which in (2, 4) else n - 1
+    n_out = n if which in (2, 5) else n - 1
+    lines = int(np.prod(shape)) // n
+    esz = 8 if precision == "fp64" else 4
+    flops = 2.0 * n_in * n_out * lines * (3 if precision == "split_bf16" else 1)
+    return flops, esz * lines * (n_in + n_out)
+
+
+def run_resample(args, K, W):
+    """Velocity output on the pressure grid (§3.4): the three particle-velocity fields of the 384^3
+    split-bf16 3D workload resampled half a step onto the nodes, one launch per axis."""
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import STAG_TO_NODES, Plan
+
+    case = workloads.pstd3d()
+    prec = "split_bf16"
+    plan = Plan(case.shape, case.dx, case.dt, case.c0, case.bcs, rho0=case.rho0, precision=prec)
+    st = plan.new_state(case.p0)
+    plan.init_state(st)
+    plan.step(st, 2)
+    outs = [torch.empty(case.shape, device="cuda", dtype=torch.float32) for _ in range(3)]
+
+    def one():
+        for a in range(3):
+            plan.apply_operator(a, STAG_TO_NODES, st.u[a], outs[a])
+
+    for _ in range(max(W, 1)):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        one()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = 3 * case.points * K / elapsed
+
+    # per-axis launch durations with events on the plan's stream
+    stream = plan._stream
+    durs = {}
+    for a in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            plan.apply_operator(a, STAG_TO_NODES, st.u[a], outs[a])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        durs[a] = e0.elapsed_time(e1) / 10
+    axis, dur_ms = max(durs.items(), key=lambda kv: kv[1])
+    flops, bytes_ = resample_cost(case.shape, axis, STAG_TO_NODES, prec)
+    gbs = bytes_ / (dur_ms * 1e-3) / 1e9
+    tfs = flops / (dur_ms * 1e-3) / 1e12
+    src_hash = kernel_source_hash("resample3d")
+    key = "axis%d_stag_to_nodes" % axis
+    traffic = load_traffic("resample3d", key, src_hash)
+    ridge = PEAK["bf16_TFs"] * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    if flops / bytes_ < ridge:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK["bf16_TFs"], "unit": "TFLOP/s",
+                "frac": round(tfs / PEAK["bf16_TFs"], 4), "traffic": traffic}
+    roof.update({"kernel": key, "avg_ms": round(dur_ms, 5), "algorithmic_bytes": int(bytes_),
+                 "algorithmic_flops": int(flops), "arith_intensity": round(flops / bytes_, 2)})
+
+    # accuracy: 64 sampled lines of each output against the oracle's interpolation of the same input lines
+    u_host = [u.double().cpu().numpy() for u in st.u]
+    got = [o.double().cpu().numpy() for o in outs]
+    plan.close()
+    cpu = err = None
+    if not args.no_cpu_baseline:
+        cpu, err = resample_cpu_leg(case, u_host, got)
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle",
+        "value": value, "unit": "velocity values resampled onto the nodes /s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3->f32", "data": "synthetic",
+        "config": {"workload": "resample3d_384^3_u_to_nodes", "grid": list(case.shape),
+                   "bc": ["%s%s" % ("ND"[l], "ND"[r]) for l, r in case.bcs], "operator": "staggered -> nodes",
+                   "precision": prec, "parallelism": "single-gpu"},
+        "accuracy": {"rel_l2_vs_fp64_oracle_sampled_lines": err, "lines": "64 per axis (32 of largest energy, 32 random)",
+                     "tolerance": 1e-3},
+        "roofline": roof, "cpu_baseline": cpu, "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line))
+
+
+def resample_cpu_leg(case, u_host, got, budget_s=12.0):
+    """The oracle's interpolation (FP64 NumPy) on whole planes of lines: times as many planes as fit the
+    budget and compares 64 sampled GPU lines per axis with it."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import pstd as opstd
+
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    done = 0
+    for a in range(3):
+        # the 32 lines of largest energy and 32 random ones; relative L2 over all of them (far from the
+        # pulses a line holds only values below the field's FP32 resolution)
+        ax = opstd.Axis(case.shape[a], case.bcs[a][0], case.bcs[a][1], case.dx)
+        um = np.moveaxis(u_host[a], a, -1)
+        gm = np.moveaxis(got[a], a, -1)
+        energy = np.einsum("ijk,ijk->ij", um, um)
+        top = np.argsort(energy, axis=None)[-32:]
+        picks = [divmod(int(t), um.shape[1]) for t in top]
+        picks += [tuple(int(v) for v in rng.integers(0, um.shape[:2])) for _ in range(32)]
+        num = den = 0.0
+        for i, j in picks:
+            ref = ax.interp_u_to_p(um[i, j])
+            num += float(np.sum((gm[i, j] - ref) ** 2))
+            den += float(np.sum(ref ** 2))
+        worst = max(worst, float(np.sqrt(num / den)))
+    t0 = time.perf_counter()
+    planes = 0
+    while time.perf_counter() - t0 < budget_s and planes < case.shape[0]:
+        for a in range(3):
+            ax = opstd.Axis(case.shape[a], case.bcs[a][0], case.bcs[a][1], case.dx)
+            um = np.moveaxis(u_host[a], a, -1)
+            ax.interp_u_to_p(um[planes])
+            done += um.shape[1] * case.shape[a]
+        planes += 1
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    base = {"value": done / dt, "unit": "velocity values resampled onto the nodes /s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d of %d planes of lines of each of the three velocity fields, FP64 NumPy (forward "
+                      "transform, inverse of the other symmetry)" % (planes, case.shape[0])}
+    return base, worst
+
     """Oracle: the 16 basic solves stepped on the host for a bounded time; the GPU field against the
     weighted sum of the basic fields' FP64 closed forms."""
     from threadpoolctl import threadpool_info
@@ -624,6 +761,10 @@ def main():
     if args.workload == "batched":
         torch.cuda.set_device(0)
         run_batched(args, K, W)
+        return
+    if args.workload == "resample3d":
+        torch.cuda.set_device(0)
+        run_resample(args, K, W)
         return
     if args.workload == "nop":
         torch.cuda.set_device(0)

@@ -175,6 +175,29 @@ int pstd_plan_get_operator(pstd_plan plan, int32_t axis, int32_t which, double* 
  * matrix.  Synchronous. */
 int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out);
 
+/* Collocated differentiation (§3.3) and half-step interpolation (§3.4) of a wall-bounded axis: which
+ *   2 = PSTD_OP_GRAD_NODES   d/dx on the n nodes (n x n): forward T1, times a1 k, inverse of the
+ *                            symmetry opposite to p's (the DC / Nyquist entries dropped or zero-filled);
+ *   3 = PSTD_OP_GRAD_STAG    d/dx on the n - 1 staggered points ((n-1) x (n-1)), from T2 and a2 k;
+ *   4 = PSTD_OP_NODES_TO_STAG a field of p's symmetry resampled half a step onto the staggered points
+ *                            ((n-1) x n), forward T1 and the half-sample inverse of the same parity;
+ *   5 = PSTD_OP_STAG_TO_NODES a field of u's symmetry (a particle velocity) resampled onto the nodes
+ *                            (n x (n-1)), forward T2 and the whole-sample inverse of the same parity.
+ * pstd_axis_operator with these values returns the FP64 matrix (derivatives include 1/dx); a periodic
+ * pair gives PSTD_E_UNSUPPORTED.  Columns / rows of nodes outside a sequence's sample (a Dirichlet node
+ * of p, a Neumann node of the derivative of p) are zero. */
+enum { PSTD_OP_GRAD_NODES = 2, PSTD_OP_GRAD_STAG = 3, PSTD_OP_NODES_TO_STAG = 4, PSTD_OP_STAG_TO_NODES = 5 };
+
+/* Apply one of the operators above along `axis` of a device field: out = A in, on the plan's stream
+ * with the dense contraction kernels in the plan's precision (double for FP64, float otherwise; the
+ * SPLIT_BF16 plan uses the split products).  in and out are row-major, contiguous, distinct, with the
+ * plan's extents on every other axis and the operator's column / row count on `axis` (for example
+ * PSTD_OP_STAG_TO_NODES along axis a maps u[a] onto the p grid).  The operator is built in FP64 and kept
+ * by the plan on first use (synchronous then); later calls are asynchronous.  Errors: PSTD_E_INVALID_ARG
+ * for null pointers, in == out, a bad axis or which; PSTD_E_UNSUPPORTED for a periodic axis or one above
+ * 4097 nodes. */
+int pstd_apply_axis_operator(pstd_plan plan, int32_t axis, int32_t which, const void* in, void* out);
+
 /* Number of elements of p / of u[axis] for this plan. */
 int64_t pstd_plan_numel(pstd_plan plan, int32_t field /* -1 = p, 0..2 = u[axis] */);
 

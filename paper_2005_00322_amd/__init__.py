@@ -4,8 +4,10 @@ The computation runs in the HIP kernels of ``libpstd.so`` (built from ``csrc/`` 
 package only marshals arguments across its C ABI (``include/pstd.h``).  PyTorch supplies device memory
 and the current stream.  There is no CPU fallback: every call raises if the library is missing.
 """
-from .pstd import (DIRICHLET, NEUMANN, PERIODIC, Batch, Plan, PstdError, State, axis_operator, combine_R,
+from .pstd import (DIRICHLET, GRAD_NODES, GRAD_STAG, NEUMANN, NODES_TO_STAG, PERIODIC, STAG_TO_NODES, Batch,
+                   Plan, PstdError, State, axis_operator, combine_R,
                    combine_fields, face_weights, lib_path, load_library, solve_faces_2d)
 
 __all__ = ["Plan", "Batch", "State", "PstdError", "combine_R", "combine_fields", "face_weights", "solve_faces_2d",
-           "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "load_library", "lib_path"]
+           "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "GRAD_NODES", "GRAD_STAG", "NODES_TO_STAG",
+           "STAG_TO_NODES", "load_library", "lib_path"]

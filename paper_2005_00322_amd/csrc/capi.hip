@@ -100,6 +100,10 @@ void free_plan(pstd_plan_s* P) {
     if (P->D[a].data) (void)hipFree(P->D[a].data);
     if (P->D[a].dataT) (void)hipFree(P->D[a].dataT);
     fft_axis_free(&P->fft[a]);
+    for (int k = 0; k < 4; ++k) {
+      if (P->R[a][k].data) (void)hipFree(P->R[a][k].data);
+      if (P->R[a][k].dataT) (void)hipFree(P->R[a][k].dataT);
+    }
   }
   if (P->c2map) (void)hipFree(P->c2map);
   if (P->flag) (void)hipFree(P->flag);
@@ -626,10 +630,38 @@ int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, 
   if (!per &&
       ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) || (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET)))
     return fail(PSTD_E_INVALID_ARG, "bad boundary condition");
-  if (!(dx > 0) || which < 0 || which > 1) return fail(PSTD_E_INVALID_ARG, "bad dx or which");
+  if (!(dx > 0) || which < 0 || which > 5) return fail(PSTD_E_INVALID_ARG, "bad dx or which");
+  if (which >= 2) {
+    if (per) return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need a wall-bounded axis");
+    int rows = 0, cols = 0;
+    const std::vector<double> m = resample_table(static_cast<int>(n), axis_case(bc_left, bc_right), which, &rows, &cols);
+    const double s = which <= 3 ? 1.0 / dx : 1.0;
+    for (size_t i = 0; i < m.size(); ++i) out[i] = m[i] * s;
+    return PSTD_OK;
+  }
   const AxisTables& t = axis_tables(static_cast<int>(n), axis_case(bc_left, bc_right));
   const std::vector<double>& m = which == 0 ? t.G : t.D;
   for (size_t i = 0; i < m.size(); ++i) out[i] = m[i] / dx;
+  return PSTD_OK;
+}
+
+int pstd_apply_axis_operator(pstd_plan P, int32_t axis, int32_t which, const void* in, void* out) {
+  if (!P || !in || !out) return fail(PSTD_E_INVALID_ARG, "null plan/in/out");
+  if (axis < 0 || axis >= P->ndim || which < 2 || which > 5) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
+  if (in == out) return fail(PSTD_E_INVALID_ARG, "in and out must be different buffers");
+  if (axis_periodic(P, axis))
+    return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need a wall-bounded axis");
+  const int n = static_cast<int>(P->n[axis]);
+  if (n > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: dense operators are limited to 4097 nodes", axis);
+  DevOperator& op = P->R[axis][which - 2];
+  if (!op.data) {
+    int rows = 0, cols = 0;
+    const std::vector<double> m =
+        resample_table(n, axis_case(P->bc[2 * axis], P->bc[2 * axis + 1]), which, &rows, &cols);
+    const int st = upload_operator(P, m, rows, cols, which <= 3 ? 1.0 / P->dx : 1.0, &op);
+    if (st != PSTD_OK) return st;
+  }
+  PSTD_HIP(contract(P, op, axis, in, out, 1.0, 0.0, nullptr, P->stream));
   return PSTD_OK;
 }
 

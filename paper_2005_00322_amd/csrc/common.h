@@ -53,6 +53,11 @@ const AxisTables& axis_tables(int n, AxisCase c);
 // tables.
 double axis_kmax(int n, AxisCase c);
 
+// Collocated differentiation and half-step interpolation along one wall-bounded axis (not CASE_PP),
+// dx = 1, row-major, m = n - 1 staggered points.  kind 2: d/dx on the nodes (n x n); 3: d/dx on the
+// staggered points (m x m); 4: nodes -> staggered points (m x n); 5: staggered points -> nodes (n x m).
+std::vector<double> resample_table(int n, AxisCase c, int kind, int* rows, int* cols);
+
 // ---- device helpers ------------------------------------------------------------------------------
 // Block barrier ordering only LDS accesses.  __syncthreads() also orders global memory, which makes the
 // compiler drain every outstanding global load (s_waitcnt vmcnt(0)) at each barrier and so defeats
@@ -269,6 +274,7 @@ struct pstd_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   pstd::DevOperator G[3], D[3];  // dense operators (built when an axis runs the dense path)
+  pstd::DevOperator R[3][4];     // collocated-derivative and interpolation operators (built on first use)
   pstd::FftAxis fft[3];
   void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
   int* flag = nullptr;         // device int for reductions (owned)

@@ -128,8 +128,10 @@ void matmul(const std::vector<double>& A, const std::vector<double>& B, std::vec
   for (auto& x : th) x.join();
 }
 
-// Build  Out = Tout^{-1} * Reindex(diag(sign*k) * Tin)  as an (Lout x Lin) matrix.
-std::vector<double> collapsed(Transform Tin, int Lin, Transform Tout, int Lout, double sign, int M) {
+// Build  Out = Tout^{-1} * Reindex(diag(sign*k) * Tin)  as an (Lout x Lin) matrix (without the k factor
+// when with_k is false: a change of sampling grid only).
+std::vector<double> collapsed(Transform Tin, int Lin, Transform Tout, int Lout, double sign, int M,
+                              bool with_k = true) {
   std::vector<double> Fin = dense(Tin, Lin);
   // k-space matrix with the rows re-indexed from Tin's wavenumber range onto Tout's.
   std::vector<double> S(static_cast<size_t>(Lout) * Lin, 0.0);
@@ -140,7 +142,7 @@ std::vector<double> collapsed(Transform Tin, int Lin, Transform Tout, int Lout, 
     for (int m = 0; m < Lin; ++m)
       if (wave_index(Tin, m) == nw) { mi = m; break; }
     if (mi < 0) continue;  // wavenumber absent from the forward range: zero entry
-    const double k = 2.0 * M_PI * (nw + shift) / M;  // dx = 1
+    const double k = with_k ? 2.0 * M_PI * (nw + shift) / M : 1.0;  // dx = 1
     for (int j = 0; j < Lin; ++j) S[static_cast<size_t>(mo) * Lin + j] = sign * k * Fin[static_cast<size_t>(mi) * Lin + j];
   }
   std::vector<double> Inv = dense(inverse_partner(Tout), Lout);
@@ -195,6 +197,51 @@ double axis_kmax(int n, AxisCase c) {
   const int Lp = (right_d ? n - 2 : n - 1) - (left_d ? 1 : 0) + 1;
   const double shift = antiperiodic(ci.T1) ? 0.5 : 0.0;
   return 2.0 * M_PI * (wave_index(ci.T1, Lp - 1) + shift) / (2.0 * (n - 1));
+}
+
+// Collocated differentiation (§3.3) and half-step interpolation (§3.4).  Differentiating swaps a
+// sequence's symmetry (symmetric <-> antisymmetric), shifting by half a step swaps whole-sample and
+// half-sample ends; either way the inverse transform is the one of the resulting symmetry.  On the nodes
+// the sequence of the symmetry opposite to p's is transformed by the other kind of T1 (same type); its
+// sample includes the node of a Dirichlet wall and excludes the node of a Neumann wall.  On the staggered
+// points the opposite symmetry to u's is transformed by the other kind of T2.
+std::vector<double> resample_table(int n, AxisCase c, int kind, int* rows, int* cols) {
+  const CaseInfo ci = case_info(c);
+  const bool left_d = (c == CASE_DN || c == CASE_DD);
+  const bool right_d = (c == CASE_ND || c == CASE_DD);
+  const int p_lo = left_d ? 1 : 0, Lp = (right_d ? n - 2 : n - 1) - p_lo + 1;
+  const int q_lo = left_d ? 0 : 1, Lq = (right_d ? n - 1 : n - 2) - q_lo + 1;
+  const int m = n - 1, M = 2 * (n - 1);
+  const Transform Q1{ci.T1.kind == COS ? SIN : COS, ci.T1.type};
+  const Transform Q2{ci.T2.kind == COS ? SIN : COS, ci.T2.type};
+  std::vector<double> out;
+  if (kind == 2) {  // d/dx on the nodes: n x n
+    *rows = n;
+    *cols = n;
+    const std::vector<double> s = collapsed(ci.T1, Lp, Q1, Lq, ci.a1, M);
+    out.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < Lq; ++i)
+      for (int j = 0; j < Lp; ++j) out[static_cast<size_t>(q_lo + i) * n + p_lo + j] = s[static_cast<size_t>(i) * Lp + j];
+  } else if (kind == 3) {  // d/dx on the staggered points: m x m
+    *rows = m;
+    *cols = m;
+    out = collapsed(ci.T2, m, Q2, m, ci.a2, M);
+  } else if (kind == 4) {  // nodes -> staggered points: m x n
+    *rows = m;
+    *cols = n;
+    const std::vector<double> s = collapsed(ci.T1, Lp, Q2, m, 1.0, M, false);
+    out.assign(static_cast<size_t>(m) * n, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < Lp; ++j) out[static_cast<size_t>(i) * n + p_lo + j] = s[static_cast<size_t>(i) * Lp + j];
+  } else {  // staggered points -> nodes: n x m
+    *rows = n;
+    *cols = m;
+    const std::vector<double> s = collapsed(ci.T2, m, Q1, Lq, 1.0, M, false);
+    out.assign(static_cast<size_t>(n) * m, 0.0);
+    for (int i = 0; i < Lq; ++i)
+      for (int j = 0; j < m; ++j) out[static_cast<size_t>(q_lo + i) * m + j] = s[static_cast<size_t>(i) * m + j];
+  }
+  return out;
 }
 
 const AxisTables& axis_tables(int n, AxisCase c) {

@@ -38,11 +38,22 @@ def _faces(bcs, ndim):
     return arr
 
 
+# Collocated differentiation and half-step interpolation operators (pstd_apply_axis_operator)
+GRAD_NODES, GRAD_STAG, NODES_TO_STAG, STAG_TO_NODES = 2, 3, 4, 5
+
+
+def operator_shape(n: int, m: int, which: int) -> tuple:
+    """(rows, cols) of operator `which` of an axis with n nodes and m staggered points."""
+    return {0: (m, n), 1: (n, m), GRAD_NODES: (n, n), GRAD_STAG: (m, m), NODES_TO_STAG: (m, n),
+            STAG_TO_NODES: (n, m)}[which]
+
+
 def axis_operator(n: int, bc_left: int, bc_right: int, dx: float, which: int) -> np.ndarray:
-    """Unscaled FP64 operator of one axis as the library builds it (host only, no GPU needed)."""
+    """FP64 operator of one axis as the library builds it (host only, no GPU needed): 0 / 1 the
+    unscaled velocity / pressure operators, 2..5 the collocated derivatives and interpolations."""
     lib = load()
     m = n if int(bc_left) == PERIODIC else n - 1           # staggered points
-    shape = (m, n) if which == 0 else (n, m)
+    shape = operator_shape(n, m, which) if which in range(6) else (1, 1)   # the library rejects others
     out = np.zeros(shape, dtype=np.float64)
     check(lib.pstd_axis_operator(int(n), int(bc_left), int(bc_right), float(dx), int(which),
                                  out.ctypes.data_as(C.POINTER(C.c_double))), "pstd_axis_operator")
@@ -166,6 +177,30 @@ class Plan:
             return False
         check(r, "pstd_check_finite")
         return True
+
+    def apply_operator(self, axis: int, which: int, x, out=None):
+        """out = A x along `axis` on the GPU, A one of GRAD_NODES, GRAD_STAG, NODES_TO_STAG, STAG_TO_NODES:
+        x has the plan's extents on the other axes and A's column count on `axis` (e.g. STAG_TO_NODES
+        along a maps u[a] onto the p grid)."""
+        import torch
+        n = self.shape[axis]
+        rows, cols = operator_shape(n, n - 1, which)
+        in_shape = list(self.shape)
+        in_shape[axis] = cols
+        out_shape = list(self.shape)
+        out_shape[axis] = rows
+        if (not isinstance(x, torch.Tensor) or tuple(x.shape) != tuple(in_shape) or x.dtype != self.dtype
+                or x.device != self.device or not x.is_contiguous()):
+            raise ValueError("x must be a contiguous %s tensor of shape %s on %s" % (self.dtype, tuple(in_shape),
+                                                                                    self.device))
+        if out is None:
+            out = torch.empty(out_shape, device=self.device, dtype=self.dtype)
+        elif (tuple(out.shape) != tuple(out_shape) or out.dtype != self.dtype or out.device != self.device
+              or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (self.dtype, tuple(out_shape)))
+        check(load().pstd_apply_axis_operator(self._h, int(axis), int(which), C.c_void_p(x.data_ptr()),
+                                              C.c_void_p(out.data_ptr())), "pstd_apply_axis_operator")
+        return out
 
     def operator(self, axis: int, which: int) -> np.ndarray:
         n = self.shape[axis]
