@@ -21,6 +21,10 @@ from . import dtt
 NEUMANN = 0
 DIRICHLET = 1
 PERIODIC = 2   # both faces of an axis (last row of Table transform_choices: the Fourier basis)
+# Right face only: the wall lies half a grid step beyond the last node, on the last staggered point
+# (groups III and IV of Table DTT_wavenumber_groups, odd implied period M = 2n - 1).
+NEUMANN_HALF = 3
+DIRICHLET_HALF = 4
 
 # Table transform_choices (§4.1): boundary pair (left, right) -> sequence types of p and u, the forward
 # transforms T1 (acts on p) and T2 (acts on u), and the signs of the k-space coefficients a1 = ±k, a2 = ±k.
@@ -141,6 +145,14 @@ class Axis:
         w[-1] = 0.5 if self.bc_right == NEUMANN else 0.0
         return w
 
+    @property
+    def m(self) -> int:
+        """Staggered points."""
+        return self.n - 1
+
+    def stag_weights(self) -> np.ndarray:
+        return np.ones(self.n - 1)
+
     def grad_matrix(self) -> np.ndarray:
         """The linear map ``grad`` as an (n-1) x n matrix (columns of Dirichlet nodes are zero)."""
         return self.grad(np.eye(self.n)).T
@@ -222,6 +234,7 @@ class PeriodicAxis:
         self.n, self.dx = int(n), float(dx)
         self.bc_left = self.bc_right = PERIODIC
         self.p_lo, self.p_hi = 0, self.n - 1
+        self.m = self.n
         self.M = self.n
         self.periodic = True
         self.k = 2.0 * np.pi * np.fft.fftfreq(self.n, d=self.dx)
@@ -239,6 +252,9 @@ class PeriodicAxis:
         f = 1j * self.k * np.exp(-0.5j * self.k * self.dx)
         return np.fft.ifft(np.fft.fft(u, axis=-1) * f, axis=-1).real
 
+    def stag_weights(self) -> np.ndarray:
+        return np.ones(self.n)
+
     def node_weights(self) -> np.ndarray:
         return np.ones(self.n)
 
@@ -251,10 +267,96 @@ class PeriodicAxis:
         return self.div(np.eye(self.n)).T
 
 
+class HalfWallAxis:
+    """An axis whose left wall is on node 0 and whose right wall is half a step beyond node n-1, at
+    x = (n - 1/2) dx, on the last of the n staggered points (groups III/IV of Table
+    DTT_wavenumber_groups: p is WSHS / WSHA / WAHS / WAHA, types V-VIII, and M = 2n - 1).
+
+    The forward and inverse DTTs of these types are the sampled cosine / sine modes of the box and their
+    inverses, so the operators of Eq. (dtt_pstd_solution) are written here from that definition: forward
+    transform (the inverse of the sampled-mode matrix), multiplication by ±k, evaluation of the
+    differentiated modes on the other grid.  Wavenumbers follow the group: k = 2 pi m / (M dx) when both
+    walls are of one kind (group III), k = 2 pi (m + 1/2) / (M dx) otherwise (group IV).  Mode indices
+    m cover as many modes as samples: a mode that vanishes on every sample of a sequence (k = pi/dx on
+    an antisymmetric sequence) is not part of it.
+    """
+
+    def __init__(self, n: int, bc_left: int, bc_right: int, dx: float):
+        if n < 3:
+            raise ValueError("an axis needs at least 3 nodes")
+        if bc_left not in (NEUMANN, DIRICHLET) or bc_right not in (NEUMANN_HALF, DIRICHLET_HALF):
+            raise ValueError("a half-step wall is a right face, with a Neumann or Dirichlet left face")
+        self.n, self.bc_left, self.bc_right, self.dx = n, bc_left, bc_right, dx
+        self.M = 2 * n - 1
+        left_n, right_n = bc_left == NEUMANN, bc_right == NEUMANN_HALF
+        self.periodic = left_n == right_n                       # group III, else group IV
+        shift = 0.0 if self.periodic else 0.5
+        # p is a cosine series with a Neumann left wall, a sine series with a Dirichlet one; u the other
+        self.pf, self.uf = (np.cos, np.sin) if left_n else (np.sin, np.cos)
+        self.s1 = -1.0 if left_n else 1.0                       # d/dx of a p mode = s1 k (u mode)
+        self.s2 = -self.s1                                      # d/dx of a u mode = s2 k (p mode)
+        if left_n and right_n:
+            m1, m2 = np.arange(0, n), np.arange(1, n)
+        elif left_n:
+            m1, m2 = np.arange(0, n), np.arange(0, n)
+        elif right_n:
+            m1, m2 = np.arange(0, n - 1), np.arange(0, n - 1)
+        else:
+            m1, m2 = np.arange(1, n), np.arange(0, n)
+        self.n1, self.n2 = m1, m2
+        self.k1 = 2.0 * np.pi * (m1 + shift) / (self.M * dx)
+        self.k2 = 2.0 * np.pi * (m2 + shift) / (self.M * dx)
+        self.p_lo, self.p_hi = (0 if left_n else 1), n - 1
+        self.u_count = n - 1 if right_n else n                  # u = 0 on a Neumann half wall
+        self.m = n                                              # staggered points stored
+        self.xn = np.arange(n) * dx
+        self.xs = (np.arange(n) + 0.5) * dx
+        self.T1inv = self.pf(np.outer(self.xn[self.p_lo:], self.k1))
+        self.T2inv = self.uf(np.outer(self.xs[:self.u_count], self.k2))
+        if self.T1inv.shape[0] != len(m1) or self.T2inv.shape[0] != len(m2):
+            raise AssertionError("as many modes as samples")
+        self.T1 = np.linalg.inv(self.T1inv)
+        self.T2 = np.linalg.inv(self.T2inv)
+
+    def grad(self, p: np.ndarray) -> np.ndarray:
+        """dp/dx on the n staggered points: forward transform of p, times s1 k, u modes evaluated."""
+        coef = p[..., self.p_lo:] @ self.T1.T * (self.s1 * self.k1)
+        coef = _reindex(coef, self.n1, self.n2)
+        return coef @ self.uf(np.outer(self.xs, self.k2)).T
+
+    def div(self, u: np.ndarray) -> np.ndarray:
+        """du/dx on the n nodes: forward transform of u's samples, times s2 k, p modes evaluated."""
+        coef = u[..., :self.u_count] @ self.T2.T * (self.s2 * self.k2)
+        coef = _reindex(coef, self.n2, self.n1)
+        return coef @ self.pf(np.outer(self.xn, self.k1)).T
+
+    def node_weights(self) -> np.ndarray:
+        w = np.ones(self.n)
+        w[0] = 0.5 if self.bc_left == NEUMANN else 0.0
+        return w
+
+    def stag_weights(self) -> np.ndarray:
+        """Weights of the staggered points: 1/2 on the wall point of a Dirichlet half wall (where u is
+        symmetric), 0 on that of a Neumann one (where u = 0)."""
+        w = np.ones(self.n)
+        w[-1] = 0.5 if self.bc_right == DIRICHLET_HALF else 0.0
+        return w
+
+    def grad_matrix(self) -> np.ndarray:
+        return self.grad(np.eye(self.n)).T
+
+    def div_matrix(self) -> np.ndarray:
+        return self.div(np.eye(self.n)).T
+
+
 def make_axis(n: int, bc_left: int, bc_right: int, dx: float):
     """The axis object of a boundary pair: periodic needs both faces periodic."""
     if (bc_left == PERIODIC) != (bc_right == PERIODIC):
         raise ValueError("a periodic axis has both faces periodic")
+    if bc_left in (NEUMANN_HALF, DIRICHLET_HALF):
+        raise ValueError("a half-step wall is a right face")
+    if bc_right in (NEUMANN_HALF, DIRICHLET_HALF):
+        return HalfWallAxis(n, bc_left, bc_right, dx)
     return PeriodicAxis(n, dx) if bc_left == PERIODIC else Axis(n, bc_left, bc_right, dx)
 
 
@@ -290,10 +392,10 @@ class Problem:
         return len(self.shape)
 
     def u_shape(self, a: int) -> tuple:
-        """n - 1 staggered points along a wall-bounded axis, n along a periodic one."""
+        """n - 1 staggered points between two walls on nodes, n along a periodic axis or one with a
+        half-step wall."""
         s = list(self.shape)
-        if self.bcs[a][0] != PERIODIC:
-            s[a] -= 1
+        s[a] = self.axes[a].m
         return tuple(s)
 
     def project(self, p: np.ndarray) -> np.ndarray:
@@ -369,7 +471,7 @@ class Problem:
         for a in range(self.ndim):
             Wa = np.ones(1)
             for b in range(self.ndim):
-                Wa = np.multiply.outer(Wa, np.ones(self.u_shape(a)[a]) if b == a else ws[b])
+                Wa = np.multiply.outer(Wa, self.axes[a].stag_weights() if b == a else ws[b])
             Wa = Wa.reshape(self.u_shape(a))
             F += self.rho0 * float(np.sum(Wa * u_prev[a] * u_next[a]))
         return F
