@@ -50,7 +50,12 @@ typedef enum {
  * §2): the axis is one period of n nodes and its particle velocity has n staggered points instead of
  * n - 1; such axes run on the dense contraction path or, in 2D FP32 plans, the fused path (not the FFT,
  * 1D or batched paths). */
-typedef enum { PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1, PSTD_PERIODIC = 2 } pstd_bc;
+/* NEUMANN_HALF / DIRICHLET_HALF (right faces only): the wall lies half a step beyond the last node, at
+ * (n - 1/2) dx, on the last of n staggered points (groups III/IV of Table DTT_wavenumber_groups: DTT types
+ * V-VIII, implied period 2n - 1).  Such axes run on the dense contraction path or the fused 2D path. */
+typedef enum {
+  PSTD_NEUMANN = 0, PSTD_DIRICHLET = 1, PSTD_PERIODIC = 2, PSTD_NEUMANN_HALF = 3, PSTD_DIRICHLET_HALF = 4
+} pstd_bc;
 
 /* Arithmetic of the transform contractions.  FP64: state and operators in double.  FP32: state and
  * operators in float, FP32 accumulation.  SPLIT_BF16: float state; each contraction is
@@ -171,8 +176,8 @@ int pstd_plan_get_operator(pstd_plan plan, int32_t axis, int32_t which, double* 
  * it before folding the time-step constants in.  n nodes, boundary pair (bc_left, bc_right), spacing dx.
  * which 0: velocity operator T2^{-1} diag(a1) T1, (n-1) x n row-major (derivative of p on the
  * staggered points); which 1: pressure operator T1^{-1} diag(a2) T2, n x (n-1) row-major.  A periodic
- * pair (both PSTD_PERIODIC) gives the n x n operators of Eq. (fourier_pstd_solution).  out must hold the
- * matrix.  Synchronous. */
+ * pair (both PSTD_PERIODIC) gives the n x n operators of Eq. (fourier_pstd_solution), a half-step right
+ * wall the n x n operators of its DTT types V-VIII.  out must hold the matrix.  Synchronous. */
 int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out);
 
 /* Collocated differentiation (§3.3) and half-step interpolation (§3.4) of a wall-bounded axis: which

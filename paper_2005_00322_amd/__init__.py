@@ -4,10 +4,11 @@ The computation runs in the HIP kernels of ``libpstd.so`` (built from ``csrc/`` 
 package only marshals arguments across its C ABI (``include/pstd.h``).  PyTorch supplies device memory
 and the current stream.  There is no CPU fallback: every call raises if the library is missing.
 """
-from .pstd import (DIRICHLET, GRAD_NODES, GRAD_STAG, NEUMANN, NODES_TO_STAG, PERIODIC, STAG_TO_NODES, Batch,
+from .pstd import (DIRICHLET, DIRICHLET_HALF, GRAD_NODES, GRAD_STAG, NEUMANN, NEUMANN_HALF, NODES_TO_STAG,
+                   PERIODIC, STAG_TO_NODES, Batch,
                    Plan, PstdError, State, axis_operator, combine_R,
                    combine_fields, face_weights, lib_path, load_library, solve_faces_2d)
 
 __all__ = ["Plan", "Batch", "State", "PstdError", "combine_R", "combine_fields", "face_weights", "solve_faces_2d",
-           "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "GRAD_NODES", "GRAD_STAG", "NODES_TO_STAG",
+           "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "NEUMANN_HALF", "DIRICHLET_HALF", "GRAD_NODES", "GRAD_STAG", "NODES_TO_STAG",
            "STAG_TO_NODES", "load_library", "lib_path"]

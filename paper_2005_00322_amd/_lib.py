@@ -18,6 +18,8 @@ E_NONFINITE = -6
 NEUMANN = 0
 DIRICHLET = 1
 PERIODIC = 2   # both faces of an axis: the Fourier basis, n staggered points
+NEUMANN_HALF = 3     # right face half a step beyond the last node (DTT types V-VIII), n staggered points
+DIRICHLET_HALF = 4
 
 FP64 = 0
 FP32 = 1

@@ -114,7 +114,11 @@ void free_plan(pstd_plan_s* P) {
 
 int64_t numel_p(const pstd_plan_s* P) { return P->n[0] * P->n[1] * P->n[2]; }
 bool axis_periodic(const pstd_plan_s* P, int a) { return P->bc[2 * a] == PSTD_PERIODIC; }
-int64_t numel_u(const pstd_plan_s* P, int a) { return numel_p(P) / P->n[a] * (P->n[a] - (axis_periodic(P, a) ? 0 : 1)); }
+bool axis_half_wall(const pstd_plan_s* P, int a) { return half_wall(P->bc[2 * a + 1]); }
+// n staggered points on a periodic axis and on one with a half-step wall, n - 1 otherwise
+int64_t numel_u(const pstd_plan_s* P, int a) {
+  return numel_p(P) / P->n[a] * (P->n[a] - (axis_periodic(P, a) || axis_half_wall(P, a) ? 0 : 1));
+}
 
 // Geometry of the contraction along axis a for a field whose extent along a is `len`.
 void axis_geometry(const pstd_plan_s* P, int a, int64_t* outer, int64_t* inner) {
@@ -326,8 +330,13 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
                   precision == PSTD_FP64 ? "FP64" : "FP32 state");
     for (int f = 0; f < 2; ++f)
       if (bc_per_face[2 * a + f] != PSTD_NEUMANN && bc_per_face[2 * a + f] != PSTD_DIRICHLET &&
-          bc_per_face[2 * a + f] != PSTD_PERIODIC)
-        return fail(PSTD_E_INVALID_ARG, "bad boundary condition on face %d", 2 * a + f);
+          bc_per_face[2 * a + f] != PSTD_PERIODIC && !(f == 1 && half_wall(bc_per_face[2 * a + f])))
+        return fail(PSTD_E_INVALID_ARG, "bad boundary condition on face %d (half-step walls are right faces)",
+                    2 * a + f);
+    if (half_wall(bc_per_face[2 * a + 1]) && bc_per_face[2 * a] == PSTD_PERIODIC)
+      return fail(PSTD_E_INVALID_ARG, "axis %d: a periodic axis has both faces periodic", a);
+    if (half_wall(bc_per_face[2 * a + 1]) && grid->n[a] > 4097)
+      return fail(PSTD_E_UNSUPPORTED, "axis %d: half-step walls run on the dense path (at most 4097 nodes)", a);
     if ((bc_per_face[2 * a] == PSTD_PERIODIC) != (bc_per_face[2 * a + 1] == PSTD_PERIODIC))
       return fail(PSTD_E_INVALID_ARG, "axis %d: a periodic axis has both faces periodic", a);
     if (bc_per_face[2 * a] == PSTD_PERIODIC && grid->n[a] > 4097)
@@ -449,7 +458,7 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
   if (n_steps == 0) return PSTD_OK;
   const int pst = prepare_axes(P);
   if (pst != PSTD_OK) return pst;
-  if (P->ndim == 1 && !axis_fft(P, 0) && !axis_periodic(P, 0)) {
+  if (P->ndim == 1 && !axis_fft(P, 0) && !axis_periodic(P, 0) && !axis_half_wall(P, 0)) {
     PSTD_HIP(launch_step1d(P->prec, P->G[0], P->D[0], st->p, st->u[0], static_cast<int>(P->n[0]), n_steps,
                            P->c2map, P->stream));
     st->step += n_steps;
@@ -627,12 +636,13 @@ int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, 
   if (!out) return fail(PSTD_E_INVALID_ARG, "out is null");
   if (n < 3 || n > 4097) return fail(PSTD_E_INVALID_ARG, "n must be in [3, 4097]");
   const bool per = bc_left == PSTD_PERIODIC && bc_right == PSTD_PERIODIC;
-  if (!per &&
-      ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) || (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET)))
+  const bool half = half_wall(bc_right);
+  if (!per && ((bc_left != PSTD_NEUMANN && bc_left != PSTD_DIRICHLET) ||
+               (bc_right != PSTD_NEUMANN && bc_right != PSTD_DIRICHLET && !half)))
     return fail(PSTD_E_INVALID_ARG, "bad boundary condition");
   if (!(dx > 0) || which < 0 || which > 5) return fail(PSTD_E_INVALID_ARG, "bad dx or which");
   if (which >= 2) {
-    if (per) return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need a wall-bounded axis");
+    if (per || half) return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need walls on nodes");
     int rows = 0, cols = 0;
     const std::vector<double> m = resample_table(static_cast<int>(n), axis_case(bc_left, bc_right), which, &rows, &cols);
     const double s = which <= 3 ? 1.0 / dx : 1.0;
@@ -649,8 +659,8 @@ int pstd_apply_axis_operator(pstd_plan P, int32_t axis, int32_t which, const voi
   if (!P || !in || !out) return fail(PSTD_E_INVALID_ARG, "null plan/in/out");
   if (axis < 0 || axis >= P->ndim || which < 2 || which > 5) return fail(PSTD_E_INVALID_ARG, "bad axis/which");
   if (in == out) return fail(PSTD_E_INVALID_ARG, "in and out must be different buffers");
-  if (axis_periodic(P, axis))
-    return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need a wall-bounded axis");
+  if (axis_periodic(P, axis) || axis_half_wall(P, axis))
+    return fail(PSTD_E_UNSUPPORTED, "collocated and interpolation operators need walls on nodes");
   const int n = static_cast<int>(P->n[axis]);
   if (n > 4097) return fail(PSTD_E_UNSUPPORTED, "axis %d: dense operators are limited to 4097 nodes", axis);
   DevOperator& op = P->R[axis][which - 2];

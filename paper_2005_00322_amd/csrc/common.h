@@ -25,16 +25,25 @@ int fail(int status, const char* fmt, ...);
 
 // ---- host operator tables (tables.cpp) ------------------------------------------------------------
 // Per-axis boundary case of Table transform_choices.
-// CASE_PP: a periodic axis (the Fourier basis).
-enum AxisCase { CASE_NN = 0, CASE_ND = 1, CASE_DN = 2, CASE_DD = 3, CASE_PP = 4 };
+// CASE_PP: a periodic axis (the Fourier basis).  CASE_NNH .. CASE_DDH: a Neumann or Dirichlet wall on
+// node 0 and a Neumann or Dirichlet wall half a step beyond node n-1 (groups III/IV, types V-VIII).
+enum AxisCase {
+  CASE_NN = 0, CASE_ND = 1, CASE_DN = 2, CASE_DD = 3, CASE_PP = 4,
+  CASE_NNH = 5, CASE_NDH = 6, CASE_DNH = 7, CASE_DDH = 8
+};
+
+inline bool half_wall(int face) { return face == PSTD_NEUMANN_HALF || face == PSTD_DIRICHLET_HALF; }
 
 inline AxisCase axis_case(int left, int right) {
   if (left == PSTD_PERIODIC) return CASE_PP;
+  if (half_wall(right))
+    return static_cast<AxisCase>(CASE_NNH + 2 * (left == PSTD_DIRICHLET) + (right == PSTD_DIRICHLET_HALF));
   return static_cast<AxisCase>(2 * (left == PSTD_DIRICHLET) + (right == PSTD_DIRICHLET));
 }
 
-// Staggered points of an axis: n - 1 between two walls, n on a periodic axis.
-inline int staggered_points(int n, AxisCase c) { return c == CASE_PP ? n : n - 1; }
+// Staggered points of an axis: n - 1 between two walls on nodes, n on a periodic axis or one whose right
+// wall lies on the last staggered point.
+inline int staggered_points(int n, AxisCase c) { return c >= CASE_PP ? n : n - 1; }
 
 // Unscaled FP64 operators of one axis for dx = 1 (scale by 1/dx), with m = staggered_points(n, case):
 //   G: m x n row-major, velocity operator T2^{-1} diag(a1) T1 (periodic: F^{-1} diag(i k e^{i k/2}) F)

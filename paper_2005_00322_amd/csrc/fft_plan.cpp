@@ -57,7 +57,8 @@ int upload_complex(const std::vector<std::complex<double>>& h, void** out) {
 int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   FftAxis& f = P->fft[a];
   const int n = static_cast<int>(P->n[a]);
-  if (!fft_axis_possible(n, P->prec) || P->bc[2 * a] == PSTD_PERIODIC) return PSTD_OK;  // dense path only
+  if (!fft_axis_possible(n, P->prec) || P->bc[2 * a] == PSTD_PERIODIC || half_wall(P->bc[2 * a + 1]))
+    return PSTD_OK;  // dense path only
   const int N = n - 1, L = 2 * N;
   f.N = N;
   f.L = L;

@@ -189,8 +189,75 @@ static AxisTables periodic_tables(int n) {
   return t;
 }
 
+// A wall on node 0 and a wall half a step beyond node n-1 (groups III/IV of Table
+// DTT_wavenumber_groups, types V-VIII, implied period M = 2n - 1).  The forward DTT of each sequence is
+// the matrix of its sampled modes, cos(k x) or sin(k x) with k = 2 pi (m + s) / M (s = 0 when both walls
+// are of one kind, 1/2 otherwise); the symmetric extension over one period makes the modes orthogonal
+// under the weights w = 1/2 on a sample lying on a wall, 1 elsewhere, with squared norm M/4 (M/2 for
+// k = 0 and k = pi), so the inverse is the transposed, weighted mode matrix divided by the norms.  Then
+//   G = Psi diag(s1 k) Phi^{-1},  D = Phi diag(s2 k) Psi^{-1}
+// with Phi the p modes on the nodes and Psi the u modes on the staggered points.
+struct HalfWallModes {
+  bool left_n, right_n;
+  double shift;
+  int p_lo, u_count;                 // first p sample, number of u samples
+  int m1_lo, m1_hi, m2_lo, m2_hi;    // mode index ranges of p and u
+};
+
+HalfWallModes half_wall_modes(int n, AxisCase c) {
+  HalfWallModes h{};
+  h.left_n = (c == CASE_NNH || c == CASE_NDH);
+  h.right_n = (c == CASE_NNH || c == CASE_DNH);
+  h.shift = (h.left_n == h.right_n) ? 0.0 : 0.5;
+  h.p_lo = h.left_n ? 0 : 1;
+  h.u_count = h.right_n ? n - 1 : n;
+  if (h.left_n && h.right_n) { h.m1_lo = 0; h.m1_hi = n - 1; h.m2_lo = 1; h.m2_hi = n - 1; }
+  else if (h.left_n)         { h.m1_lo = 0; h.m1_hi = n - 1; h.m2_lo = 0; h.m2_hi = n - 1; }
+  else if (h.right_n)        { h.m1_lo = 0; h.m1_hi = n - 2; h.m2_lo = 0; h.m2_hi = n - 2; }
+  else                       { h.m1_lo = 1; h.m1_hi = n - 1; h.m2_lo = 0; h.m2_hi = n - 1; }
+  return h;
+}
+
+static AxisTables half_wall_tables(int n, AxisCase c) {
+  const HalfWallModes h = half_wall_modes(n, c);
+  const double M = 2.0 * n - 1.0;
+  auto kof = [&](int m) { return 2.0 * M_PI * (m + h.shift) / M; };
+  auto norm = [&](int m) { return (2.0 * (m + h.shift) == 0.0 || 2.0 * (m + h.shift) == M) ? M / 2.0 : M / 4.0; };
+  auto pmode = [&](int m, double x) { return h.left_n ? std::cos(kof(m) * x) : std::sin(kof(m) * x); };
+  auto umode = [&](int m, double x) { return h.left_n ? std::sin(kof(m) * x) : std::cos(kof(m) * x); };
+  const double s1 = h.left_n ? -1.0 : 1.0, s2 = -s1;
+  // modes shared by p and u (a mode with k = 0 has no derivative)
+  const int lo = std::max(h.m1_lo, h.m2_lo), hi = std::min(h.m1_hi, h.m2_hi), nm = hi - lo + 1;
+  // G = A (n x nm) * B (nm x n): A = u modes on all n staggered points times s1 k / norm, B = weighted p modes
+  std::vector<double> A(static_cast<size_t>(n) * nm), B(static_cast<size_t>(nm) * n, 0.0);
+  std::vector<double> Cm(static_cast<size_t>(n) * nm), Em(static_cast<size_t>(nm) * n, 0.0);
+  for (int q = 0; q < nm; ++q) {
+    const int m = lo + q;
+    const double k = kof(m), nr = norm(m);
+    for (int r = 0; r < n; ++r) {
+      A[static_cast<size_t>(r) * nm + q] = umode(m, r + 0.5) * s1 * k / nr;
+      Cm[static_cast<size_t>(r) * nm + q] = pmode(m, r) * s2 * k / nr;
+    }
+    for (int j = h.p_lo; j < n; ++j)
+      B[static_cast<size_t>(q) * n + j] = (j == 0 ? 0.5 : 1.0) * pmode(m, j);
+    for (int j = 0; j < h.u_count; ++j)
+      Em[static_cast<size_t>(q) * n + j] = (j == n - 1 ? 0.5 : 1.0) * umode(m, j + 0.5);
+  }
+  AxisTables t;
+  t.n = n;
+  t.c = c;
+  matmul(A, B, t.G, n, nm, n);
+  matmul(Cm, Em, t.D, n, nm, n);
+  t.kmax = kof(h.m1_hi);
+  return t;
+}
+
 double axis_kmax(int n, AxisCase c) {
   if (c == CASE_PP) return 2.0 * M_PI * (n / 2) / n;
+  if (c >= CASE_NNH) {
+    const HalfWallModes h = half_wall_modes(n, c);
+    return 2.0 * M_PI * (h.m1_hi + h.shift) / (2.0 * n - 1.0);
+  }
   const CaseInfo ci = case_info(c);
   const bool left_d = (c == CASE_DN || c == CASE_DD);
   const bool right_d = (c == CASE_ND || c == CASE_DD);
@@ -250,6 +317,7 @@ const AxisTables& axis_tables(int n, AxisCase c) {
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
   if (c == CASE_PP) return g_cache.emplace(key, periodic_tables(n)).first->second;
+  if (c >= CASE_NNH) return g_cache.emplace(key, half_wall_tables(n, c)).first->second;
 
   const CaseInfo ci = case_info(c);
   const bool left_d = (c == CASE_DN || c == CASE_DD);

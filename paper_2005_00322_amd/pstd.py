@@ -7,7 +7,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import DIRICHLET, NEUMANN, PERIODIC, PRECISIONS, PstdError, check, load
+from ._lib import DIRICHLET, DIRICHLET_HALF, NEUMANN, NEUMANN_HALF, PERIODIC, PRECISIONS, PstdError, check, load
 
 lib_path = _lib.LIB_PATH
 
@@ -52,7 +52,7 @@ def axis_operator(n: int, bc_left: int, bc_right: int, dx: float, which: int) ->
     """FP64 operator of one axis as the library builds it (host only, no GPU needed): 0 / 1 the
     unscaled velocity / pressure operators, 2..5 the collocated derivatives and interpolations."""
     lib = load()
-    m = n if int(bc_left) == PERIODIC else n - 1           # staggered points
+    m = n if (int(bc_left) == PERIODIC or int(bc_right) in (NEUMANN_HALF, DIRICHLET_HALF)) else n - 1
     shape = operator_shape(n, m, which) if which in range(6) else (1, 1)   # the library rejects others
     out = np.zeros(shape, dtype=np.float64)
     check(lib.pstd_axis_operator(int(n), int(bc_left), int(bc_right), float(dx), int(which),
@@ -114,9 +114,10 @@ class Plan:
 
     # -- state -------------------------------------------------------------------------------------
     def u_shape(self, a):
-        """n - 1 staggered points along a wall-bounded axis, n along a periodic one."""
+        """n - 1 staggered points between walls on nodes, n along a periodic axis or one whose right wall
+        lies half a step beyond the last node."""
         s = list(self.shape)
-        if int(self.bcs[a][0]) != PERIODIC:
+        if int(self.bcs[a][0]) != PERIODIC and int(self.bcs[a][1]) not in (NEUMANN_HALF, DIRICHLET_HALF):
             s[a] -= 1
         return tuple(s)
 
@@ -203,8 +204,8 @@ class Plan:
         return out
 
     def operator(self, axis: int, which: int) -> np.ndarray:
-        n = self.shape[axis]
-        shape = (n - 1, n) if which == 0 else (n, n - 1)
+        n, m = self.shape[axis], self.u_shape(axis)[axis]
+        shape = (m, n) if which == 0 else (n, m)
         out = np.zeros(shape, dtype=np.float64)
         check(load().pstd_plan_get_operator(self._h, axis, which, out.ctypes.data_as(C.POINTER(C.c_double))),
               "pstd_plan_get_operator")
