@@ -44,6 +44,7 @@ WORKLOADS = {
     "pstd2d_large": ("pstd2d_large", "fp32", 200, 50),
     "periodic2d": ("periodic2d", "fp32", 2000, 200),
     "resample3d": ("pstd3d", "split_bf16", 20, 3),
+    "halfwall2d": ("halfwall2d", "fp32", 2000, 200),
     "nop": ("nop", "bf16", 20, 3),
 }
 
@@ -57,6 +58,7 @@ SOURCES = {
     "pstd2d_large": ("common.h", "capi.hip", "fft_plan.cpp", "kernels_fft.hip"),
     "periodic2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
     "resample3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
+    "halfwall2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
     "batched": ("common.h", "capi_batch.hip", "kernels_batch2d.hip"),
     "faces": ("common.h", "capi.hip", "capi_batch.hip", "kernels_batch2d.hip", "kernels_misc.hip"),
     "nop": ("common.h", "capi_nop.hip", "kernels_nop.hip"),
@@ -787,7 +789,8 @@ def main():
     value = case.points * K / elapsed
 
     # dominant kernel: the single contraction launch with the largest average duration
-    periodic = [l == 2 for l, _ in case.bcs]
+    # axes with n staggered points: periodic, or a right wall half a step beyond the last node
+    periodic = [l == 2 or r in (3, 4) for l, r in case.bcs]
     fused = uses_fused_path(case.shape, precision)
     if fused:
         durs = time_fused_phases(case, precision)
@@ -841,7 +844,7 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": case.name, "grid": list(case.shape),
-                   "bc": ["%s%s" % ("NDP"[l], "NDP"[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
+                   "bc": ["%s%s" % (("N", "D", "P", "Nh", "Dh")[l], ("N", "D", "P", "Nh", "Dh")[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
                    "precision": precision, "parallelism": "single-gpu"},
         "accuracy": {"rel_l2_vs_fp64_oracle": err, "after_steps": W + K,
                      "tolerance": {"fp32": 1e-5, "fp64": 1e-10, "split_bf16": 1e-3}[precision]},

@@ -36,6 +36,8 @@ SEED_BASE = 200500322
 NEUMANN = 0
 DIRICHLET = 1
 PERIODIC = 2
+NEUMANN_HALF = 3     # right face half a step beyond the last node
+DIRICHLET_HALF = 4
 RHO0 = 1000.0
 DX = 1e-4
 
@@ -123,6 +125,20 @@ def periodic2d(n: int = 256, steps: int = 2000) -> Case:
     p0 = tapered_disc(shape, DX, centre, 4 * DX, 8 * DX)
     bcs = ((PERIODIC, PERIODIC), (NEUMANN, DIRICHLET))
     return Case("periodic2d_%dx%d_xPP_yND" % shape, shape, bcs, DX, 0.3 * DX / c0, c0, steps, p0,
+                extra={"centre": centre})
+
+
+def halfwall2d(n: int = 256, steps: int = 2000) -> Case:
+    """The disc of pstd2d in 256 x 256 nodes whose right walls lie half a step beyond the last node:
+    x Neumann then Dirichlet-half (DTT types VII/VIII), y Dirichlet then Neumann-half (types VII/VIII of
+    the other kind), CFL 0.3."""
+    rng = rng_for(8)
+    shape = (n, n)
+    c0 = 1500.0
+    centre = _centre(rng, shape, 9, DX)
+    p0 = tapered_disc(shape, DX, centre, 4 * DX, 8 * DX)
+    bcs = ((NEUMANN, DIRICHLET_HALF), (DIRICHLET, NEUMANN_HALF))
+    return Case("halfwall2d_%dx%d_xNDh_yDNh" % shape, shape, bcs, DX, 0.3 * DX / c0, c0, steps, p0,
                 extra={"centre": centre})
 
 
