@@ -547,6 +547,8 @@ def resample_cpu_leg(case, u_host, got, budget_s=12.0):
                       "transform, inverse of the other symmetry)" % (planes, case.shape[0])}
     return base, worst
 
+
+def faces_cpu_leg(case, got, total_steps, budget_s=12.0):
     """Oracle: the 16 basic solves stepped on the host for a bounded time; the GPU field against the
     weighted sum of the basic fields' FP64 closed forms."""
     from threadpoolctl import threadpool_info
