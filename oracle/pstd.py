@@ -317,18 +317,20 @@ class HalfWallAxis:
             raise AssertionError("as many modes as samples")
         self.T1 = np.linalg.inv(self.T1inv)
         self.T2 = np.linalg.inv(self.T2inv)
+        self.U_all = self.uf(np.outer(self.xs, self.k2))       # u modes on all n staggered points
+        self.P_all = self.pf(np.outer(self.xn, self.k1))       # p modes on all n nodes
 
     def grad(self, p: np.ndarray) -> np.ndarray:
         """dp/dx on the n staggered points: forward transform of p, times s1 k, u modes evaluated."""
         coef = p[..., self.p_lo:] @ self.T1.T * (self.s1 * self.k1)
         coef = _reindex(coef, self.n1, self.n2)
-        return coef @ self.uf(np.outer(self.xs, self.k2)).T
+        return coef @ self.U_all.T
 
     def div(self, u: np.ndarray) -> np.ndarray:
         """du/dx on the n nodes: forward transform of u's samples, times s2 k, p modes evaluated."""
         coef = u[..., :self.u_count] @ self.T2.T * (self.s2 * self.k2)
         coef = _reindex(coef, self.n2, self.n1)
-        return coef @ self.pf(np.outer(self.xn, self.k1)).T
+        return coef @ self.P_all.T
 
     def node_weights(self) -> np.ndarray:
         w = np.ones(self.n)

@@ -11,6 +11,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU-side case")
+    if os.environ.get("PYTEST_XDIST_WORKER"):
+        # several workers each running a multithreaded BLAS oversubscribe the host's cores
+        from threadpoolctl import threadpool_limits
+        config._blas_limit = threadpool_limits(limits=1)
 
 
 @pytest.fixture(scope="session")
