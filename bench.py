@@ -99,7 +99,7 @@ def uses_fft(shape, axis, precision, periodic=False):
 
 
 def contraction_cost(shape, axis, which, precision, periodic=False):
-    """Algorithmic flops and bytes of one launch along an axis (kernel table).
+    """Algorithmic flops and bytes of one launch along an axis.
 
     Dense path: 2*n_in flops per output point (a dense n_out x n_in operator applied along the axis;
     three bf16 products for split-bf16).  FFT path: 2 x 5 L log2(L) / 2 flops per line (a forward and an
