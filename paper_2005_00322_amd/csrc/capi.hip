@@ -344,7 +344,10 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   }
   if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
     return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
-  if (grid->ndim == 1 && grid->n[0] > 1365 && !fft_axis_possible(static_cast<int>(grid->n[0]), precision))
+  // walls on nodes: the single-workgroup 1D kernel (up to 1365 nodes) or the FFT path; periodic and
+  // half-step-wall axes run on the dense contraction path (up to 4097 nodes, checked above)
+  if (grid->ndim == 1 && grid->n[0] > 1365 && bc_per_face[0] != PSTD_PERIODIC && !half_wall(bc_per_face[1]) &&
+      !fft_axis_possible(static_cast<int>(grid->n[0]), precision))
     return fail(PSTD_E_UNSUPPORTED, "1D grids above 1365 nodes need the FFT path (2(n-1) = 16 x 2^a 3^b 5^c)");
   int64_t total = 1;
   for (int a = 0; a < grid->ndim; ++a) total *= grid->n[a];

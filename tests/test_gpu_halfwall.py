@@ -86,6 +86,17 @@ def test_pulse_equals_images_fp64(bcl, bcr):
     assert np.max(np.abs(p - ref)) < 1e-9
 
 
+@pytest.mark.parametrize("seed,shape,bcs,prec,steps", [
+    (21, (3, 5), ((N, DH), (D, NH)), "fp32", 30),        # minimal axes, fused path
+    (22, (3,), ((D, NH),), "fp64", 30),                  # minimal 1D axis: one p sample, two u samples
+    (23, (513, 20), ((D, DH), (N, N)), "fp32", 10),      # just above the fused limit: per-axis contractions
+    (24, (1400,), ((N, NH),), "fp64", 10),               # 1D above the single-workgroup size: dense path
+])
+def test_edge_sizes(seed, shape, bcs, prec, steps):
+    print("halfwall edge", shape, bcs, prec, flush=True)
+    _check(_case(seed, shape, bcs, steps, prec))
+
+
 def test_left_face_rejected():
     from paper_2005_00322_amd import Plan, PstdError
     with pytest.raises(PstdError):

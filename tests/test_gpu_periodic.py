@@ -22,7 +22,7 @@ def _case(seed, shape, bcs, steps, precision):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [64, 65])
+@pytest.mark.parametrize("n", [64, 65, 1400])         # 1400: above the 1D single-workgroup size
 def test_1d(prec, n):
     case = _case(n, (n,), ((P, P),), 200, prec)
     print("periodic 1d", n, prec, flush=True)

@@ -51,6 +51,8 @@ GRIDS = [
     (5, (300, 70), ((D, N), (N, D))),
     (6, (14, 18, 16), ((D, D), (N, N), (N, D))),
     (7, (9, 33, 65), ((N, D), (D, N), (D, D))),
+    (8, (3, 3), ((D, D), (N, D))),                       # minimal axes
+    (9, (3,), ((N, N),)),
 ]
 
 
