@@ -388,11 +388,15 @@ def run_faces(args, K, W):
     got = out.double().cpu().numpy()
     b.close()
     flops, bytes_ = batch_step_cost(solves)
-    launches = max(1, (K + 1023) // 1024)
+    # tile 16: two fused phase launches per step over all solves (the launch time here also holds the final
+    # weighted sum); otherwise one persistent launch per up to 1024 steps
+    phase_path = cfg.get("tile") == 16
+    launches = 2 * K if phase_path else max(1, (K + 1023) // 1024)
+    kernel = "phase2d_batch_kernel (velocity + pressure per step)" if phase_path else "batch2d_kernel (persistent)"
     tfs = flops * K / (kernel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s",
-            "frac": round(tfs / PEAK["fp32_TFs"], 4), "traffic": None, "kernel": "batch2d_kernel (persistent)",
-            "avg_ms": round(kernel_ms / launches, 3), "algorithmic_flops": int(flops * K / launches),
+            "frac": round(tfs / PEAK["fp32_TFs"], 4), "traffic": None, "kernel": kernel,
+            "avg_ms": round(kernel_ms / launches, 5), "algorithmic_flops": int(flops * K / launches),
             "algorithmic_bytes": int(bytes_ * K / launches), "arith_intensity": round(flops / bytes_, 2)}
     cpu = err = None
     if not args.no_cpu_baseline:
