@@ -1,16 +1,19 @@
 """Benchmark of the PSTD time-step hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd2d|pstd3d|pstd1d|batched|pstd2d_large|nop]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pstd3d|pstd2d|pstd1d|batched|...]
 
 One bench step is one PSTD time step over the whole grid: every axis's velocity update (forward DTT,
 k-space multiply with the type switch, inverse DTT, leapfrog update; one fused contraction kernel per
-axis) followed by every axis's share of the pressure update.  The default workload is the 2D
-256 x 256 box (Dirichlet x faces, Neumann y faces, FP32, CFL 0.3).  The state is resident in HBM before
-the timed region; K steps are timed between device synchronisations.
+axis) followed by every axis's share of the pressure update.  The default workload is the 3D box of
+384^3 nodes (faces drawn from the seed, c0 = 1540 m/s, CFL 0.3, FP32 state, split-bf16 contractions on
+the matrix cores).  The state is resident in HBM before the timed region; the K steps replay a captured
+HIP graph (captured before the timed region) between device synchronisations.
 
-Printed: one JSON line with grid-point updates/s, the relative L2 error of the final field against the
-FP64 oracle's closed form, the roofline of the dominant kernel (its average duration measured with
-HIP events on the plan's stream) and the FP64 CPU oracle timed on a bounded sample on the host.
+Printed: one JSON line with grid-point updates/s, the relative L2 error of the field after the
+workload's full step count against the FP64 oracle's closed form, the roofline of the step (the
+method's compulsory bytes over the step time measured with HIP events on the plan's stream, with the
+dense design's bytes and the dominant kernel beside it), the FP64 CPU oracle timed on a bounded sample
+on the host, and the batched and surrogate speedups measured in the same run outside the timed region.
 """
 from __future__ import annotations
 
@@ -37,7 +40,7 @@ WORKLOADS = {
     # name: (builder, precision, default steps, default warmup); a warmup of at least 50 steps
     # captures the plan's 50-step graph before the timed region
     "pstd2d": ("pstd2d", "fp32", 2000, 200),
-    "pstd3d": ("pstd3d", "split_bf16", 100, 50),
+    "pstd3d": ("pstd3d", "split_bf16", 20, 5),
     "pstd1d": ("pstd1d", "fp64", 1000, 100),
     "batched": ("batched", "fp32", 1000, 10),
     "faces": ("faces2d", "fp32", 1000, 10),
@@ -258,6 +261,181 @@ def cpu_baseline_leg(case, gpu_p, total_steps, budget_s=12.0):
     return base, err
 
 
+def host_info():
+    """CPU model (from /proc/cpuinfo), the cores this process may run on and the BLAS thread count."""
+    from threadpoolctl import threadpool_info
+
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    return model, len(os.sched_getaffinity(0)), int(threads)
+
+
+def cpu_baseline_step(case, budget_s=12.0):
+    """The FP64 oracle on the host at the workload's full size: the velocity half of one time step
+    (u_a <- u_a - (dt/rho0) grad_a p for every axis, as the oracle's step forms it) is timed; if it
+    took less than ``budget_s`` the pressure half is timed too (a whole step), otherwise the step is
+    taken as twice the velocity half (the pressure half applies transforms of the same sizes)."""
+    from oracle import pstd as opstd
+
+    prob = opstd.Problem(case.shape, case.bcs, case.dx, case.dt, case.c0, rho0=case.rho0)
+    p = prob.project(case.p0)
+    u = [np.zeros(prob.u_shape(a)) for a in range(prob.ndim)]
+    t0 = time.perf_counter()
+    u_new = [u[a] - (prob.dt / prob.rho0) * prob.grad(p, a) for a in range(prob.ndim)]
+    t_half = time.perf_counter() - t0
+    whole = t_half < budget_s
+    if whole:
+        t1 = time.perf_counter()
+        acc = np.zeros(prob.shape)
+        for a in range(prob.ndim):
+            acc += prob.div(u_new[a], a)
+        p = p - prob.dt * prob.rho0 * prob.c2() * acc
+        t_step = t_half + time.perf_counter() - t1
+    else:
+        t_step = 2.0 * t_half
+    del u, u_new, p
+    model, cores, threads = host_info()
+    sample = ("one full time step of the %s workload at full size, FP64 NumPy (direct DST/DCT matrices), timed"
+              % case.name if whole else
+              "the velocity half of one time step of the %s workload at full size (three of the six transform "
+              "applications), FP64 NumPy, timed; the step is taken as twice that (extrapolated)" % case.name)
+    return {"value": case.points / t_step, "unit": "grid-point updates/s", "cores": cores, "blas_threads": threads,
+            "cpu_model": model, "kind": "oracle", "sample": sample, "extrapolated": not whole,
+            "seconds_per_step": t_step}
+
+
+def step_events_ms(plan, st, n, stream):
+    """Average time (ms) of one step over n steps replayed from the plan's captured graph, measured with
+    HIP events on the plan's stream (the graph is captured before the first event)."""
+    import torch
+    plan.prepare(st, n)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.step(st, n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def headline_roofline(case, precision, step_ms, durs, src_hash, workload):
+    """Roofline of the 3D step.
+
+    The method's compulsory traffic is every state field read and written once per step: p and the
+    three u_a, 4 bytes each, 8 x 4 = 32 bytes per grid point (u_a has (n_a - 1)/n_a as many points; the
+    figure counts p's points).  ``achieved`` is that traffic over the step time measured with events;
+    ``dense_design`` puts the six dense contractions' own bytes (input read, output read and written:
+    12 bytes per point each, 72 per step) over the same time; ``dominant_kernel`` is the slowest single
+    contraction launch with its algorithmic bytes over its own event-timed duration.
+    """
+    pts = case.points
+    comp = 32.0 * pts
+    gbs = comp / (step_ms * 1e-3) / 1e9
+    dense = 0.0
+    for a in range(len(case.shape)):
+        for which in (0, 1):
+            dense += contraction_cost(case.shape, a, which, precision)[1]
+    dgbs = dense / (step_ms * 1e-3) / 1e9
+    (axis, which), dur_ms = max(durs.items(), key=lambda kv: kv[1])
+    flops, bytes_ = contraction_cost(case.shape, axis, which, precision)
+    key = "axis%d_%s" % (axis, "velocity" if which == 0 else "pressure")
+    kgbs = bytes_ / (dur_ms * 1e-3) / 1e9
+    step_traffic = load_traffic(workload, "step", src_hash, field="hbm_bytes_per_step")
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+            "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": step_traffic,
+            "launch": "one time step (the captured graph of its six contraction launches)",
+            "algorithmic_bytes": int(comp), "bytes_per_point": 32, "step_ms": round(step_ms, 5),
+            "dense_design": {"bytes_per_point": 72, "algorithmic_bytes": int(dense), "achieved": round(dgbs, 1),
+                             "frac": round(dgbs / PEAK["hbm_GBs"], 4)},
+            "dominant_kernel": {"kernel": key, "avg_ms": round(dur_ms, 5), "algorithmic_bytes": int(bytes_),
+                                "algorithmic_flops": int(flops), "achieved": round(kgbs, 1),
+                                "frac": round(kgbs / PEAK["hbm_GBs"], 4),
+                                "mfma_tflops": round(flops / (dur_ms * 1e-3) / 1e12, 1),
+                                "mfma_frac_bf16": round(flops / (dur_ms * 1e-3) / 1e12 / PEAK["bf16_TFs"], 4),
+                                "traffic": load_traffic(workload, key, src_hash)}}
+
+
+def run_headline(args, K, W):
+    """The 3D 384^3 split-bf16 workload: K timed steps, then the batched and surrogate speedups."""
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import Plan
+
+    precision = "split_bf16"
+    case = workloads.pstd3d()
+    stream = torch.cuda.Stream()
+    plan = Plan(case.shape, case.dx, case.dt, case.c0, case.bcs, rho0=case.rho0, precision=precision, stream=stream)
+    st = plan.new_state(case.p0)
+    plan.init_state(st)
+    plan.prepare(st, W)
+    plan.step(st, W)
+    plan.prepare(st, K)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.step(st, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / K
+    value = case.points * K / elapsed
+
+    # outside the timed region: per-launch durations, the full-length accuracy run, the baselines
+    durs = time_dominant_kernel(plan, st, False, reps=20)
+    src_hash = kernel_source_hash("pstd3d")
+    roof = headline_roofline(case, precision, step_ms, durs, src_hash, "pstd3d")
+    st2 = plan.new_state(case.p0)
+    plan.init_state(st2)
+    plan.prepare(st2, case.steps)
+    plan.step(st2, case.steps)
+    torch.cuda.synchronize()
+    p_final = st2.p.double().cpu().numpy()
+    del st2
+    plan.close()
+    del st
+    torch.cuda.empty_cache()
+    err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pstd as opstd
+        ref = opstd.Problem(case.shape, case.bcs, case.dx, case.dt, case.c0, rho0=case.rho0).modal_solution(
+            case.p0, case.steps)
+        err = float(np.linalg.norm(p_final - ref) / np.linalg.norm(ref))
+        del ref
+        cpu = cpu_baseline_step(case)
+    del p_final
+    batched = surrogate = None
+    if not args.no_speedups:
+        batched = batched_speedup(args)
+        surrogate = surrogate_speedup(args)
+    line = {
+        "metric": "grid-point updates/s at stated L2 err vs FP64 oracle; batched & surrogate speedup",
+        "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3->f32", "data": "synthetic",
+        "config": {"workload": case.name, "grid": list(case.shape),
+                   "bc": ["%s%s" % ("ND"[l], "ND"[r]) for l, r in case.bcs], "cfl": round(case.c0 * case.dt / case.dx, 4),
+                   "precision": precision, "state": "f32", "parallelism": "single-gpu",
+                   "launch": "captured HIP graph of the K steps (six split-bf16 contraction launches per step)"},
+        "accuracy": {"rel_l2_vs_fp64_oracle": err, "after_steps": case.steps,
+                     "reference": "FP64 discrete modal closed form of the same problem (oracle)", "tolerance": 1e-3},
+        "roofline": roof, "cpu_baseline": cpu,
+        "batched_speedup": batched, "surrogate_speedup": surrogate,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line))
+
+
 def batched_solves():
     import workloads
     wl = workloads.batched()
@@ -270,6 +448,152 @@ def batched_solves():
         pairs.append((2 * i, 2 * i + 1))
         R.append(inst.R)
     return wl, solves, p0s, pairs, R
+
+
+def batched_accuracy(solves, p0s, finals, combined, pairs, R, total_steps, every=16):
+    """Worst relative L2 of sample solves and of their combination against the oracle's closed form."""
+    from oracle import pstd as opstd
+
+    worst = 0.0
+    for k in range(0, len(pairs), every):
+        d, n = pairs[k]
+        refs = []
+        for idx in (d, n):
+            s = solves[idx]
+            ref = opstd.Problem(s["shape"], s["bcs"], s["dx"], s["dt"], s["c0"]).modal_solution(p0s[idx], total_steps)
+            refs.append(ref)
+            worst = max(worst, float(np.linalg.norm(finals[idx] - ref) / np.linalg.norm(ref)))
+        cref = opstd.combine_R(refs[0], refs[1], R[k])
+        worst = max(worst, float(np.linalg.norm(combined[k] - cref) / np.linalg.norm(cref)))
+    return worst
+
+
+def batched_speedup(args, seq_steps=50):
+    """The batched workload (128 instances x Neumann/Dirichlet = 256 uneven 2D FP32 solves, 1000 steps, one
+    persistent launch from a captured graph) against the same solves run one after another through the
+    single-solve FP32 path (each replaying its own captured graph on one shared stream): both timed with
+    events on their streams, the single-solve path on a sample of steps of every solve."""
+    import torch
+
+    from paper_2005_00322_amd import Batch, Plan
+
+    wl, solves, p0s, pairs, R = batched_solves()
+    steps = wl["steps"] if "steps" in wl else 1000
+    points = sum(s["shape"][0] * s["shape"][1] for s in solves)
+    stream = torch.cuda.Stream()
+    b = Batch(solves, stream=stream)
+    cfg = b.autotune(trial_steps=5, cache_path=os.path.join("/tmp", "pstd_batch_tune.json"))
+    st = b.new_states(p0s)
+    b.init_states(st)
+    b.step(st, steps)                      # warm: captures the launch graph of this step count
+    b.synchronize()
+    st = b.new_states(p0s)
+    b.init_states(st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(st, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1)
+    b.synchronize()
+    outs = b.combine_R(st, pairs, R)
+    torch.cuda.synchronize()
+    finals = [x.p.double().cpu().numpy() for x in st]
+    combined = [o.double().cpu().numpy() for o in outs]
+    del st, outs
+    b.close()
+    # one after another: every solve on the single-solve path, graphs captured before the timed region
+    seq_stream = torch.cuda.Stream()
+    plans, states = [], []
+    for s, p0 in zip(solves, p0s):
+        pl = Plan(s["shape"], s["dx"], s["dt"], s["c0"], s["bcs"], precision="fp32", stream=seq_stream)
+        x = pl.new_state(p0)
+        pl.init_state(x)
+        pl.prepare(x, seq_steps)
+        plans.append(pl)
+        states.append(x)
+    torch.cuda.synchronize()
+    e0.record(seq_stream)
+    for pl, x in zip(plans, states):
+        pl.step(x, seq_steps)
+    e1.record(seq_stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) * steps / seq_steps
+    for pl in plans:
+        pl.close()
+    del plans, states
+    torch.cuda.empty_cache()
+    err = None if args.no_cpu_baseline else batched_accuracy(solves, p0s, finals, combined, pairs, R, steps)
+    return {"vs_sequential_single_solve_fp32": seq_ms / batched_ms, "batched_ms": batched_ms,
+            "sequential_ms": seq_ms, "solves": len(solves), "steps": steps, "points_per_step": points,
+            "batched_updates_per_s": points * steps / (batched_ms * 1e-3), "launch": cfg,
+            "sequential_sample": "%d steps of each solve (its own captured graph, one shared stream), scaled to %d"
+                                 % (seq_steps, steps),
+            "accuracy": {"rel_l2_vs_fp64_oracle_worst": err, "after_steps": steps, "tolerance": 1e-5,
+                         "sample": "every 16th instance: both solves and their combination"}}
+
+
+def surrogate_speedup(args, B=256):
+    """Surrogate inference on a batch of 256 held-out inputs against the batched FP32 solver on the same
+    inputs (800 steps each), with the surrogate's error against that solver."""
+    import torch
+
+    import workloads
+    from paper_2005_00322_amd import Batch
+    from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig
+
+    wpath = args.weights or os.path.join(ROOT, "paper_2005_00322_amd", "weights", "nop_128x128_c32_m48_l4.npz")
+    cfg = SurrogateConfig()
+    p0s, c0s = workloads.nop_inputs(B, n=cfg.H, index_offset=2 * 10 ** 6)
+    dev = torch.device("cuda")
+    p = torch.from_numpy(p0s.astype(np.float32)).to(dev)
+    c = torch.from_numpy(c0s.astype(np.float32)).to(dev)
+    cmax = c.amax(dim=(1, 2)).double().cpu().numpy()
+    solves = [{"shape": (cfg.H, cfg.W), "bcs": workloads.NOP_BCS, "dx": workloads.DX, "dt": workloads.NOP_DT,
+               "c0": float(cmax[i])} for i in range(B)]
+    stream = torch.cuda.Stream()
+    b = Batch(solves, stream=stream)
+    b.set_c0_maps([c[i] for i in range(B)])
+    b.autotune(trial_steps=5, cache_path=os.path.join("/tmp", "pstd_batch_tune_nop.json"))
+    st = b.new_states([p[i] for i in range(B)])
+    b.init_states(st)
+    b.step(st, workloads.NOP_STEPS)           # warm: captures the launch graph
+    b.synchronize()
+    st = b.new_states([p[i] for i in range(B)])
+    b.init_states(st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(st, workloads.NOP_STEPS)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pstd_ms = e0.elapsed_time(e1)
+    b.synchronize()
+    ref = torch.stack([x.p for x in st])
+    del st
+    b.close()
+    net = Surrogate(cfg, max_batch=B)
+    d = np.load(wpath)
+    net.set_params(d["theta"])
+    out = torch.empty_like(p)
+    for _ in range(3):
+        net.infer(p, c, out=out)
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record(net._stream)
+    for _ in range(reps):
+        net.infer(p, c, out=out)
+    e1.record(net._stream)
+    torch.cuda.synchronize()
+    nop_ms = e0.elapsed_time(e1) / reps
+    err = net.relative_errors(out, ref)
+    net.close()
+    return {"vs_batched_fp32_pstd": pstd_ms / nop_ms, "pstd_ms": pstd_ms, "surrogate_ms": nop_ms, "batch": B,
+            "solver_steps": workloads.NOP_STEPS, "weights": os.path.basename(wpath),
+            "accuracy": {"rel_l2_vs_fp32_pstd": {"mean": float(err.mean()), "median": float(np.median(err)),
+                                                 "p95": float(np.quantile(err, 0.95))},
+                         "note": "the FP32 batched solver is the judge; it matches the FP64 oracle to 2e-6"}}
 
 
 def batch_step_cost(solves):
@@ -739,8 +1063,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="pstd2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pstd3d", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-speedups", action="store_true",
+                    help="pstd3d: skip the batched and surrogate speedup measurements")
     ap.add_argument("--weights", default=None, help="surrogate parameters (npz with 'theta') for --workload nop")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known HBM traffic, for scaling "
@@ -762,6 +1088,10 @@ def main():
     if args.calibrate_copy:
         torch.cuda.set_device(0)
         calibration_copies()
+    if args.workload == "pstd3d":
+        torch.cuda.set_device(0)
+        run_headline(args, K, W)
+        return
     if args.workload == "faces":
         torch.cuda.set_device(0)
         run_faces(args, K, W)

@@ -84,8 +84,8 @@ typedef struct pstd_plan_s* pstd_plan;
  * "Differentiation with staggered grids", folds -dt/rho0 and -dt rho0 c0^2 into them, rounds them to
  * the plan's precision and copies them to the device.  Axes that start on the FFT path (see pstd_path)
  * get FFT tables instead (twiddles and the spectral multipliers, also formed in FP64).  Sizes: n <= 4097
- * per axis on the dense path; up to 8193 (FP32 state) or 4097 (FP64) where 2(n-1) = 16 x 2^a 3^b 5^c;
- * 1D plans above 1365 nodes only on the FFT path.  Returns PSTD_E_UNSTABLE if the time step is above the
+ * per axis on the dense path; up to 8193 (FP32 state) or 4097 (FP64) where 2(n-1) = 16 x 2^a 3^b 5^c.
+ * Returns PSTD_E_UNSTABLE if the time step is above the
  * stability limit, PSTD_E_UNSUPPORTED for sizes outside these limits. */
 int pstd_plan_create(const pstd_grid* grid, double dx, double dt, double c0,
                      const int32_t bc_per_face[6], pstd_plan* out);
@@ -107,8 +107,16 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0,
 int pstd_state_init(pstd_plan plan, pstd_state* state, int32_t u_mode);
 
 /* Advance the state by n_steps >= 0 steps of Eq. (dtt_pstd_solution) (§4.3 for 2D/3D): every u_a from
- * p^n first, then p^{n+1} from all u_a^{n+1/2}.  Asynchronous on the plan's stream. */
+ * p^n first, then p^{n+1} from all u_a^{n+1/2}.  Asynchronous on the plan's stream.  The steps replay
+ * captured HIP graphs (whole chunks of 50 steps, then one graph of the remaining steps; 1D plans of at most
+ * 1365 nodes with walls on nodes run one kernel instead); a graph is captured on first use for the
+ * state's buffers and kept by the plan (one full-chunk graph and one of the last other length). */
 int pstd_step(pstd_plan plan, pstd_state* state, int64_t n_steps);
+
+/* Capture, without running anything, the graphs a later pstd_step(plan, state, n_steps) replays, so that
+ * the capture cost stays out of a timed or latency-critical call.  Synchronous on the host; enqueues no
+ * work.  Same arguments and errors as pstd_step. */
+int pstd_step_prepare(pstd_plan plan, const pstd_state* state, int64_t n_steps);
 
 /* Execution path of pstd_step.
  *   PER_AXIS: one dense contraction kernel per axis and half step (axes up to 4097 nodes).
@@ -321,6 +329,38 @@ int pstd_nop_relative_errors(pstd_nop nop, const float* pred, const float* targe
  * surrogate's validated error exceeds the tolerance) to the PSTD solver instead.  Synchronous. */
 int pstd_nop_input_stats(pstd_nop nop, const float* p0, const float* c0, int32_t batch, int32_t margin, double* stats);
 int pstd_nop_destroy(pstd_nop nop);
+/* The surrogate's gate: when it may answer instead of the solver.  validated_error is its relative L2
+ * error against the solver on held-out pairs (a high quantile); a request whose tolerance is below it
+ * always goes to the solver.  The other fields bound the training distribution: the sound-speed range,
+ * the largest |p0| and the largest share of sum p0^2 within wall_margin nodes of a wall. */
+typedef struct {
+  double validated_error;
+  double c0_lo, c0_hi;
+  double p_max;
+  int32_t wall_margin;
+  double wall_share_max;
+} pstd_nop_gate;
+
+/* The PSTD problem the surrogate stands for, which the fallback solves: spacing, time step, density,
+ * faces {x-, x+, y-, y+} (Neumann or Dirichlet) and the number of steps (the network predicts the pressure
+ * after that many steps from rest, u^{-1/2} as pstd_state_init's u_mode 0). */
+typedef struct {
+  double dx, dt, rho0;
+  int32_t bc[4];
+  int64_t steps;
+} pstd_nop_problem;
+
+/* Answer batch requests (device p0, c0 maps, out: batch x H x W floats each; any batch size): the
+ * input statistics of pstd_nop_input_stats decide per sample whether it lies inside the gate's
+ * training distribution; samples inside it are answered by the network when gate->validated_error <=
+ * tol, every other sample by the FP32 batched solver of pstd_batch_* (its c0 map squared pointwise, its
+ * stability limit from the map's maximum), whose pressure is stepped in place in out.  fallback (host,
+ * batch entries, nullable) receives 1 for solver answers; n_fallback (nullable) their count.
+ * Synchronous; allocates the fallback solves' velocity buffers for the duration of the call.
+ * Not a method of the paper: the solver remains the surrogate's fallback and the judge of its error. */
+int pstd_nop_predict(pstd_nop nop, const pstd_nop_gate* gate, const pstd_nop_problem* problem, const float* p0,
+                     const float* c0, float* out, int32_t batch, double tol, int32_t* fallback, int32_t* n_fallback);
+
 
 const char* pstd_status_string(int status);
 const char* pstd_last_error(void);

@@ -124,6 +124,58 @@ def image_solution(shape, bcs, dx, c0, dt, m, centre, amp, sigma, u_mode="centre
     return out
 
 
+def partial_image_positions_1d(xs: float, L: float, RL: float, RR: float, reach: float):
+    """Image sources of a point x_s in [0, L] between walls of real reflection coefficients R_L (at 0) and
+    R_R (at L), as in §5: every reflection off a wall multiplies an image's amplitude by that wall's R.
+
+    Positions 2jL + x_s carry (R_L R_R)^|j|; positions 2jL - x_s carry R_R^j R_L^(j-1) for j >= 1 and
+    R_L^(1-j) R_R^(-j) for j <= 0 (the left image R_L at -x_s, the right image R_R at 2L - x_s, ...).
+    With R = +-1 these are the polarities of ``image_positions_1d``.  Only images within ``reach`` of
+    the domain are returned.
+    """
+    J = int(np.ceil((reach + 2 * L) / (2 * L))) + 1
+    out = []
+    for j in range(-J, J + 1):
+        direct = (2 * j * L + xs, (RL * RR) ** abs(j))
+        mirrored = (2 * j * L - xs, RR ** j * RL ** (j - 1) if j >= 1 else RL ** (1 - j) * RR ** (-j))
+        for pos, amp in (direct, mirrored):
+            if -reach <= pos <= L + reach and amp != 0.0:
+                out.append((pos, amp))
+    return out
+
+
+def partial_image_solution(shape, R_faces, dx, c0, dt, m, centre, amp, sigma, u_mode="centred"):
+    """Field on the p nodes of a box with a real reflection coefficient on every face, after m steps from
+    one Gaussian at ``centre``: the free-space solution summed over the separable image sources, each
+    carrying the product over axes of its per-axis amplitude (``partial_image_positions_1d``).
+
+    R_faces: [(R_L, R_R)] per axis.  This is the physical solution the weighted sums of §5 reproduce
+    while no wave has met the same pair of walls twice.
+    """
+    ndim = len(shape)
+    reach = c0 * dt * m + 14.0 * sigma
+    per_axis = [partial_image_positions_1d(centre[a], (shape[a] - 1) * dx, R_faces[a][0], R_faces[a][1], reach)
+                for a in range(ndim)]
+    grids = np.meshgrid(*[np.arange(s) * dx for s in shape], indexing="ij")
+    out = np.zeros(shape)
+
+    def rec(a, pos, weight):
+        nonlocal out
+        if a == ndim:
+            r = np.sqrt(sum((grids[b] - pos[b]) ** 2 for b in range(ndim)))
+            near = r < reach
+            if np.any(near):
+                vals = np.zeros(shape)
+                vals[near] = free_space_gaussian(r[near], ndim, amp, sigma, c0, dt, m, u_mode)
+                out += weight * vals
+            return
+        for x, s in per_axis[a]:
+            rec(a + 1, pos + [x], weight * s)
+
+    rec(0, [], 1.0)
+    return out
+
+
 def image_summed_gaussian(shape, bcs, dx, centre, amp, sigma):
     """The initial pressure that matches ``image_solution`` at m = 0 (Gaussian plus all its images)."""
     ndim = len(shape)

@@ -35,6 +35,16 @@ class State(C.Structure):
     _fields_ = [("p", C.c_void_p), ("u", C.c_void_p * 3), ("step", C.c_int64)]
 
 
+class NopGate(C.Structure):
+    _fields_ = [("validated_error", C.c_double), ("c0_lo", C.c_double), ("c0_hi", C.c_double),
+                ("p_max", C.c_double), ("wall_margin", C.c_int32), ("wall_share_max", C.c_double)]
+
+
+class NopProblem(C.Structure):
+    _fields_ = [("dx", C.c_double), ("dt", C.c_double), ("rho0", C.c_double), ("bc", C.c_int32 * 4),
+                ("steps", C.c_int64)]
+
+
 class NopConfig(C.Structure):
     _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("channels", C.c_int32), ("modes", C.c_int32),
                 ("layers", C.c_int32), ("hidden", C.c_int32), ("max_batch", C.c_int32), ("split", C.c_int32)]
@@ -59,6 +69,7 @@ SIGNATURES = {
                                       C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pstd_state_init": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32]),
     "pstd_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int64]),
+    "pstd_step_prepare": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int64]),
     "pstd_plan_set_path": (C.c_int, [C.c_void_p, C.c_int32]),
     "pstd_apply_axis": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_int32, C.c_int32]),
     "pstd_combine_R": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -95,6 +106,8 @@ SIGNATURES = {
     "pstd_nop_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]),
     "pstd_nop_relative_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "pstd_nop_input_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "pstd_nop_predict": (C.c_int, [C.c_void_p, C.POINTER(NopGate), C.POINTER(NopProblem), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(C.c_int32)]),
     "pstd_nop_destroy": (C.c_int, [C.c_void_p]),
     "pstd_status_string": (C.c_char_p, [C.c_int]),
     "pstd_last_error": (C.c_char_p, []),

@@ -92,6 +92,14 @@ int upload_operator(pstd_plan_s* P, const std::vector<double>& m, int M, int K, 
   return PSTD_OK;
 }
 
+void drop_graphs(pstd_plan_s* P) {
+  for (auto& g : P->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = pstd_plan_s::StepGraph{};
+  }
+}
+
 void free_plan(pstd_plan_s* P) {
   if (!P) return;
   for (int a = 0; a < 3; ++a) {
@@ -107,8 +115,7 @@ void free_plan(pstd_plan_s* P) {
   }
   if (P->c2map) (void)hipFree(P->c2map);
   if (P->flag) (void)hipFree(P->flag);
-  if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
+  drop_graphs(P);
   delete P;
 }
 
@@ -284,6 +291,48 @@ hipError_t enqueue_steps(pstd_plan_s* P, pstd_state* st, int64_t nsteps, hipStre
 
 constexpr int64_t kGraphChunk = 50;  // steps captured per graph launch
 
+// The captured graph of `steps` steps on this state's buffers (captured on first use, kept per plan:
+// slot 0 for a full chunk, slot 1 for the last other length).  Capturing runs nothing.
+int step_graph(pstd_plan_s* P, const pstd_state* st, int64_t steps, hipGraphExec_t* out) {
+  pstd_plan_s::StepGraph& g = P->graphs[steps == kGraphChunk ? 0 : 1];
+  const bool same = g.exec && g.steps == steps && g.key[0] == st->p && g.key[1] == st->u[0] &&
+                    g.key[2] == st->u[1] && g.key[3] == st->u[2];
+  if (!same) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = pstd_plan_s::StepGraph{};
+    hipStream_t cs;
+    PSTD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      pstd_state tmp = *st;
+      const hipError_t le = enqueue_steps(P, &tmp, steps, cs);
+      e = hipStreamEndCapture(cs, &g.graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      g = pstd_plan_s::StepGraph{};
+      return fail(PSTD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    g.steps = steps;
+    g.key[0] = st->p;
+    g.key[1] = st->u[0];
+    g.key[2] = st->u[1];
+    g.key[3] = st->u[2];
+  }
+  *out = g.exec;
+  return PSTD_OK;
+}
+
+// Whether pstd_step runs the whole time loop in the single-workgroup 1D kernel (walls on nodes, at most
+// 1365 nodes, not on the FFT path); other 1D plans step through the dense contractions.
+bool use_step1d(const pstd_plan_s* P) {
+  return P->ndim == 1 && !axis_fft(P, 0) && !axis_periodic(P, 0) && !axis_half_wall(P, 0) && P->n[0] <= 1365;
+}
+
 }  // namespace
 }  // namespace pstd
 
@@ -344,11 +393,8 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   }
   if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
     return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
-  // walls on nodes: the single-workgroup 1D kernel (up to 1365 nodes) or the FFT path; periodic and
-  // half-step-wall axes run on the dense contraction path (up to 4097 nodes, checked above)
-  if (grid->ndim == 1 && grid->n[0] > 1365 && bc_per_face[0] != PSTD_PERIODIC && !half_wall(bc_per_face[1]) &&
-      !fft_axis_possible(static_cast<int>(grid->n[0]), precision))
-    return fail(PSTD_E_UNSUPPORTED, "1D grids above 1365 nodes need the FFT path (2(n-1) = 16 x 2^a 3^b 5^c)");
+  // 1D walls on nodes: the single-workgroup kernel up to 1365 nodes, above that the FFT path where 2(n-1)
+  // factors and the dense contraction path otherwise (up to 4097 nodes, checked above)
   int64_t total = 1;
   for (int a = 0; a < grid->ndim; ++a) total *= grid->n[a];
   if (total > (int64_t(1) << 31)) return fail(PSTD_E_UNSUPPORTED, "grid above 2^31 points");
@@ -461,47 +507,43 @@ int pstd_step(pstd_plan P, pstd_state* st, int64_t n_steps) {
   if (n_steps == 0) return PSTD_OK;
   const int pst = prepare_axes(P);
   if (pst != PSTD_OK) return pst;
-  if (P->ndim == 1 && !axis_fft(P, 0) && !axis_periodic(P, 0) && !axis_half_wall(P, 0)) {
+  if (use_step1d(P)) {
     PSTD_HIP(launch_step1d(P->prec, P->G[0], P->D[0], st->p, st->u[0], static_cast<int>(P->n[0]), n_steps,
                            P->c2map, P->stream));
     st->step += n_steps;
     return PSTD_OK;
   }
-  // chunks of kGraphChunk steps replay one captured graph; the remainder is launched directly
-  int64_t left = n_steps;
-  const bool same_key = P->graph_exec && P->graph_key[0] == st->p && P->graph_key[1] == st->u[0] &&
-                        P->graph_key[2] == st->u[1] && P->graph_key[3] == st->u[2];
-  if (left >= kGraphChunk && !same_key) {
-    if (P->graph_exec) {
-      (void)hipGraphExecDestroy(P->graph_exec);
-      P->graph_exec = nullptr;
-    }
-    if (P->graph) {
-      (void)hipGraphDestroy(P->graph);
-      P->graph = nullptr;
-    }
-    hipStream_t cs;
-    PSTD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      hipError_t le = enqueue_steps(P, st, kGraphChunk, cs);
-      e = hipStreamEndCapture(cs, &P->graph);
-      if (le != hipSuccess) e = le;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) return fail(PSTD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    P->graph_key[0] = st->p;
-    P->graph_key[1] = st->u[0];
-    P->graph_key[2] = st->u[1];
-    P->graph_key[3] = st->u[2];
+  // every step runs from a captured graph: whole chunks of kGraphChunk steps, then one graph of the rest
+  const int64_t full = n_steps / kGraphChunk, rest = n_steps % kGraphChunk;
+  hipGraphExec_t g = nullptr;
+  if (full > 0) {
+    const int gst = step_graph(P, st, kGraphChunk, &g);
+    if (gst != PSTD_OK) return gst;
+    for (int64_t i = 0; i < full; ++i) PSTD_HIP(hipGraphLaunch(g, P->stream));
   }
-  while (left >= kGraphChunk) {
-    PSTD_HIP(hipGraphLaunch(P->graph_exec, P->stream));
-    left -= kGraphChunk;
+  if (rest > 0) {
+    const int gst = step_graph(P, st, rest, &g);
+    if (gst != PSTD_OK) return gst;
+    PSTD_HIP(hipGraphLaunch(g, P->stream));
   }
-  if (left > 0) PSTD_HIP(enqueue_steps(P, st, left, P->stream));
   st->step += n_steps;
+  return PSTD_OK;
+}
+
+int pstd_step_prepare(pstd_plan P, const pstd_state* st, int64_t n_steps) {
+  if (!P || !st || !st->p) return fail(PSTD_E_INVALID_ARG, "null plan/state/p");
+  for (int a = 0; a < P->ndim; ++a)
+    if (!st->u[a]) return fail(PSTD_E_INVALID_ARG, "u[%d] is null", a);
+  if (n_steps < 0) return fail(PSTD_E_INVALID_ARG, "n_steps < 0");
+  const int pst = prepare_axes(P);
+  if (pst != PSTD_OK) return pst;
+  if (n_steps == 0 || use_step1d(P)) return PSTD_OK;
+  hipGraphExec_t g = nullptr;
+  if (n_steps >= kGraphChunk) {
+    const int gst = step_graph(P, st, kGraphChunk, &g);
+    if (gst != PSTD_OK) return gst;
+  }
+  if (n_steps % kGraphChunk) return step_graph(P, st, n_steps % kGraphChunk, &g);
   return PSTD_OK;
 }
 
@@ -524,14 +566,7 @@ int pstd_plan_set_path(pstd_plan P, int32_t path) {
     P->path = old;
     return pst;
   }
-  if (P->graph_exec) {  // a captured graph may belong to the other path
-    (void)hipGraphExecDestroy(P->graph_exec);
-    P->graph_exec = nullptr;
-  }
-  if (P->graph) {
-    (void)hipGraphDestroy(P->graph);
-    P->graph = nullptr;
-  }
+  drop_graphs(P);  // captured graphs may belong to the other path
   return PSTD_OK;
 }
 

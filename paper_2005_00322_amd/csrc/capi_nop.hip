@@ -486,6 +486,89 @@ int pstd_nop_input_stats(pstd_nop N, const float* p0, const float* c0, int32_t b
   return PSTD_OK;
 }
 
+int pstd_nop_predict(pstd_nop N, const pstd_nop_gate* g, const pstd_nop_problem* prob, const float* p0,
+                     const float* c0, float* out, int32_t batch, double tol, int32_t* fallback, int32_t* n_fallback) {
+  if (!N || !g || !prob || !p0 || !c0 || !out) return fail(PSTD_E_INVALID_ARG, "null pointer");
+  if (batch < 1) return fail(PSTD_E_INVALID_ARG, "batch < 1");
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(PSTD_E_INVALID_ARG, "tol must be finite and >= 0");
+  if (!(prob->dx > 0) || !(prob->dt > 0) || !(prob->rho0 > 0) || prob->steps < 0)
+    return fail(PSTD_E_INVALID_ARG, "dx, dt, rho0 must be positive and steps >= 0");
+  for (int f = 0; f < 4; ++f)
+    if (prob->bc[f] != PSTD_NEUMANN && prob->bc[f] != PSTD_DIRICHLET)
+      return fail(PSTD_E_INVALID_ARG, "the fallback solver takes Neumann or Dirichlet faces");
+  if (g->wall_margin < 0) return fail(PSTD_E_INVALID_ARG, "wall_margin < 0");
+  const int H = N->cfg.H, W = N->cfg.W, mb = N->cfg.max_batch;
+  const int64_t P = N->P;
+  // 1. input statistics, at most max_batch samples per call
+  std::vector<double> st(4 * static_cast<size_t>(batch));
+  for (int s0 = 0; s0 < batch; s0 += mb) {
+    const int n = std::min(mb, batch - s0);
+    const int r = pstd_nop_input_stats(N, p0 + s0 * P, c0 + s0 * P, n, g->wall_margin, st.data() + 4 * s0);
+    if (r != PSTD_OK) return r;
+  }
+  // 2. the gate: inside the training distribution and a tolerance the validated error meets
+  std::vector<int32_t> fb(batch);
+  int32_t nf = 0;
+  for (int b = 0; b < batch; ++b) {
+    const double* x = st.data() + 4 * b;
+    const bool inside = x[0] >= g->c0_lo && x[1] <= g->c0_hi && x[2] <= g->p_max && x[3] <= g->wall_share_max;
+    fb[b] = (!inside || g->validated_error > tol) ? 1 : 0;
+    nf += fb[b];
+  }
+  // 3. the surrogate on every chunk that holds an admitted sample (fallback rows are overwritten below)
+  for (int s0 = 0; s0 < batch; s0 += mb) {
+    const int n = std::min(mb, batch - s0);
+    bool any = false;
+    for (int b = s0; b < s0 + n; ++b) any = any || !fb[b];
+    if (!any) continue;
+    const int r = pstd_nop_infer(N, p0 + s0 * P, c0 + s0 * P, out + s0 * P, n);
+    if (r != PSTD_OK) return r;
+  }
+  // 4. the FP32 batched solver for the rest: each such sample's pressure is stepped in place in out
+  if (nf > 0) {
+    std::vector<int64_t> nn(2 * static_cast<size_t>(nf));
+    std::vector<int32_t> bc(4 * static_cast<size_t>(nf));
+    std::vector<double> dx(nf, prob->dx), dt(nf, prob->dt), cmax(nf);
+    std::vector<const float*> maps(nf);
+    std::vector<pstd_state> states(nf);
+    float* ubuf = nullptr;
+    const int64_t ux = static_cast<int64_t>(H - 1) * W, uy = static_cast<int64_t>(H) * (W - 1);
+    if (hipMalloc(&ubuf, sizeof(float) * (ux + uy) * nf) != hipSuccess)
+      return fail(PSTD_E_OOM, "hipMalloc of the fallback velocities failed");
+    int i = 0;
+    int r = PSTD_OK;
+    for (int b = 0; b < batch && r == PSTD_OK; ++b) {
+      if (!fb[b]) continue;
+      nn[2 * i] = H;
+      nn[2 * i + 1] = W;
+      for (int f = 0; f < 4; ++f) bc[4 * i + f] = prob->bc[f];
+      cmax[i] = st[4 * b + 1];
+      maps[i] = c0 + b * P;
+      states[i] = pstd_state{};
+      states[i].p = out + b * P;
+      states[i].u[0] = ubuf + i * (ux + uy);
+      states[i].u[1] = ubuf + i * (ux + uy) + ux;
+      if (hipMemcpyAsync(out + b * P, p0 + b * P, sizeof(float) * P, hipMemcpyDeviceToDevice, N->stream) != hipSuccess)
+        r = fail(PSTD_E_HIP, "copying the fallback inputs failed");
+      ++i;
+    }
+    pstd_batch B = nullptr;
+    if (r == PSTD_OK)
+      r = pstd_batch_create(nf, nn.data(), bc.data(), dx.data(), dt.data(), cmax.data(), prob->rho0, N->stream, &B);
+    if (r == PSTD_OK) r = pstd_batch_set_c0_maps(B, maps.data());
+    if (r == PSTD_OK) r = pstd_batch_state_init(B, states.data(), 0);
+    if (r == PSTD_OK) r = pstd_batch_step(B, states.data(), prob->steps);
+    if (r == PSTD_OK) r = pstd_batch_synchronize(B);
+    if (B) (void)pstd_batch_destroy(B);
+    (void)hipStreamSynchronize(N->stream);
+    (void)hipFree(ubuf);
+    if (r != PSTD_OK) return r;
+  }
+  if (fallback) std::memcpy(fallback, fb.data(), sizeof(int32_t) * batch);
+  if (n_fallback) *n_fallback = nf;
+  return PSTD_OK;
+}
+
 int pstd_nop_destroy(pstd_nop N) {
   if (!N) return PSTD_OK;
   (void)(N->stream ? hipStreamSynchronize(N->stream) : hipDeviceSynchronize());

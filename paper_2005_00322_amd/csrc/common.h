@@ -288,11 +288,13 @@ struct pstd_plan_s {
   void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
   int* flag = nullptr;         // device int for reductions (owned)
   int path = 0;                // PSTD_PATH_* (0 = automatic)
-  // captured step graphs
-  hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph = nullptr;
-  int64_t graph_steps = 0;
-  void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  // captured step graphs: slot 0 holds a full chunk of steps, slot 1 the last other length used
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t steps = 0;
+    void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+  } graphs[2];
 };
 
 namespace pstd {

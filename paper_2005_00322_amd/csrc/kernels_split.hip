@@ -9,15 +9,25 @@
 // (both operands read as rows of a [row][k] LDS tile, 16 bytes per lane) and receives
 // C[8*(r/4) + 4*(l/32) + r%4][l%32] in accumulator register r.  Output columns follow the lane index,
 // so the operand whose rows are unit-stride in Y goes to the Q port:
-//   strided layout   (Y[b][m][c]): P = operator rows m, Q = field columns c
+//   strided layout   (Y[b][m][c]): P = operator rows m, Q = field columns (b, c)
 //   contiguous layout (Y[r][m]):   P = field rows r,   Q = operator rows m
+//
+// Tiles: 192 operator rows x 256 field lines per block of eight waves (one block per CU: 160 KB of LDS).
+// What bounds these launches is the traffic from L2 into the CUs (every block fetches its operator and
+// field slices from L2; the field comes from HBM once), so the tile is as large as the accumulators
+// allow: per K-slice a block fetches 192 + 256 rows for 192 x 256 outputs, 43% less traffic per output
+// than 128 x 128 tiles.  A field tile may span several outer blocks of a strided layout (its lines are
+// the flattened (b, c) pairs), so every axis has batch x extent / 256 field tiles.
 //
 // Pipeline: two LDS buffers and two register sets.  While the MFMAs consume K-slice s from one LDS
 // buffer, the global loads of slices s+1 and s+2 are in flight in the two register sets; after the
 // MFMAs slice s+1 is split into bf16 hi/lo and written to the other buffer, the loads of slice s+3 are
-// issued into the freed register set, and one barrier per slice separates the two buffers.  The epilogue issues every load of Y
-// before its first store.  Blocks sharing one field tile are placed on the same XCD back to back so
-// the tile comes from HBM once and from that XCD's L2 afterwards.
+// issued into the freed register set, and one barrier per slice separates the two buffers.  The
+// epilogue issues every load of Y before its first store.  The two operator tiles of a field tile are
+// placed on the same XCD back to back, so the field tile comes from HBM once and from that XCD's L2
+// for the second.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pstd {
@@ -30,32 +40,33 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct SArgs {
   const uint16_t* Ahi;
-  const uint16_t* Alo;
   uint32_t lo_off;         // byte offset of the lo part from the hi part
   int lda, M, K;
+  int mrows;               // allocated (padded) operator rows
   const float* X;
   float* Y;
-  int64_t ncols, batch, x_bstride, y_bstride;
-  int op_tiles;        // tiles along the operator rows
-  int64_t fld_tiles;   // tiles along the field (columns or rows) times batch
+  int64_t ncols, x_bstride, y_bstride;
+  int64_t lines;           // field lines: batch * ncols (strided) or rows (contiguous)
+  int op_tiles;            // tiles along the operator rows
+  int64_t fld_tiles;       // tiles along the field lines
   float alpha, beta;
   const float* scale;
 };
 
 constexpr int BK = 32;            // K slice per pipeline stage (two MFMA K-steps)
 constexpr int LDK = BK + 8;       // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
-constexpr int BT = 128;           // tile edge along P and along Q
-constexpr int NT = 256;           // 4 waves, 2 x 2, each 64 x 64
-constexpr int TILE_ELEMS = BT * LDK;
-constexpr int OP_CH = BT * (BK / 8) / NT;    // 16-byte operator chunks per thread per part (2)
-constexpr int FL_G = BT * (BK / 8) / NT;     // 8-float field groups per thread (2)
+constexpr int BO = 192;           // operator rows per tile
+constexpr int BF = 256;           // field lines per tile
+constexpr int NT = 512;           // eight waves
+constexpr int OP_CH = BO * (BK / 8) * 2 / NT;   // 16-byte operator chunks (hi and lo) per thread (3)
+constexpr int FL_G = BF * (BK / 8) / NT;        // 8-float field groups per thread (2)
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr uint32_t kOOB = 0x80000000u;   // byte offset past every buffer used here (all < 2 GiB)
 
 // Raw buffer resource over `bytes` bytes: a 4-byte load at an offset >= bytes returns 0 and a store
 // there is dropped, which replaces bounds checks by out-of-range offsets.  Only 4-byte buffer accesses
-// are used: this compiler shrinks 16-byte buffer loads to one dword when optimising.
+// are used.
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
 }
@@ -80,25 +91,35 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& h, bf16x8& l
   }
 }
 
-// FMODE (contiguous layout only): 0 = one 4-byte load per field element, 8 consecutive k per lane;
-// 1 = one 4-byte load per element with the lanes along k (two rows of 32 consecutive floats per wave
-// instruction, coalesced at any row length and alignment), neighbouring lanes pairing their values
-// with a DPP swap so that each lane stores one packed bf16 pair (even lanes the hi parts, odd lanes
-// the lo parts); 2 = two 16-byte loads per 8 floats (X 16-byte aligned and K % 4 == 0).
+// FMODE: 0 = strided layout, one 4-byte load per field element, 8 consecutive k per thread;
+// 1 = contiguous layout, one 4-byte load per element with the lanes along k (two rows of 32 consecutive
+// floats per wave instruction, coalesced at any row length and alignment), neighbouring lanes pairing
+// their values with a DPP swap so that each lane stores one packed bf16 pair (even lanes the hi parts,
+// odd lanes the lo parts); 2 = contiguous layout, two 16-byte loads per 8 floats (X 16-byte aligned and
+// K % 4 == 0).
 template <bool CONTIG, int FMODE>
-__global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
+__global__ __launch_bounds__(NT, 1) void split_kernel(SArgs a) {
   constexpr bool VEC = FMODE == 2;
   constexpr bool LANEK = CONTIG && FMODE == 1;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[2][4][TILE_ELEMS];   // [buffer][P hi, P lo, Q hi, Q lo]
+  // ports: P rows and Q rows of the tile, the wave grid over them and each wave's 32 x 32 MFMA tiles
+  constexpr int BP = CONTIG ? BF : BO, BQ = CONTIG ? BO : BF;
+  constexpr int WP = CONTIG ? 4 : 2, WQ = 8 / WP;
+  constexpr int TP = BP / WP, TQ = BQ / WQ;          // 64 x 96 (contiguous) or 96 x 64 (strided)
+  constexpr int IP = TP / 32, JQ = TQ / 32;
+  constexpr int P_ELEMS = BP * LDK, Q_ELEMS = BQ * LDK;
+  constexpr int BUF_ELEMS = 2 * (P_ELEMS + Q_ELEMS);
+  // [buffer][P hi | P lo | Q hi | Q lo]
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * BUF_ELEMS];
+  constexpr int PH = 0, PL = P_ELEMS, QH = 2 * P_ELEMS, QL = 2 * P_ELEMS + Q_ELEMS;
+  constexpr int OPH = CONTIG ? QH : PH, OPL = CONTIG ? QL : PL;
+  constexpr int FLH = CONTIG ? PH : QH, FLL = CONTIG ? PL : QL;
+
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wp = wave & 1, wq = wave >> 1;
-  // operator / field roles of the P and Q ports
-  constexpr int OPH = CONTIG ? 2 : 0, OPL = CONTIG ? 3 : 1;
-  constexpr int FLH = CONTIG ? 0 : 2, FLL = CONTIG ? 1 : 3;
+  const int wp = wave % WP, wq = wave / WP;
 
-  // tile coordinates: XCD-grouped when the field tile count allows it
+  // tile coordinates: the op_tiles tiles of a field tile run on one XCD when the count allows it
   const int64_t t = blockIdx.x;
   int op_t;
   int64_t fl_t;
@@ -110,78 +131,69 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
     op_t = static_cast<int>(t % a.op_tiles);
     fl_t = t / a.op_tiles;
   }
-  int64_t b, f0;
-  if (CONTIG) {
-    b = 0;
-    f0 = fl_t * BT;
-  } else {
-    const int64_t per = (a.ncols + BT - 1) / BT;
-    b = fl_t / per;
-    f0 = (fl_t % per) * BT;
-  }
-  const int o0 = op_t * BT;
-  // buffer resources: the operator, this block's field slab and its output slab
-  const uint32_t x_bytes = static_cast<uint32_t>(4 * (CONTIG ? a.ncols * a.K : a.ncols * static_cast<int64_t>(a.K)));
-  const uint32_t y_bytes = static_cast<uint32_t>(4 * a.ncols * a.M);
-  const float* Xb = a.X + b * a.x_bstride;
-  const rsrc_t rX = make_rsrc(Xb, x_bytes);
-  const rsrc_t rY = make_rsrc(a.Y + b * a.y_bstride, y_bytes);
-  const rsrc_t rS = make_rsrc(a.scale ? a.scale + b * a.y_bstride : a.Y, a.scale ? y_bytes : 0u);
+  const int64_t f0 = fl_t * BF;
+  const int o0 = op_t * BO;
+  // buffer resources over the whole input and output (both below 2 GiB)
+  const uint32_t x_bytes = static_cast<uint32_t>(4 * (CONTIG ? a.lines * a.K : (a.lines / a.ncols) * a.x_bstride));
+  const uint32_t y_bytes = static_cast<uint32_t>(4 * (CONTIG ? a.lines * a.M : (a.lines / a.ncols) * a.y_bstride));
+  const rsrc_t rX = make_rsrc(a.X, x_bytes);
+  const rsrc_t rY = make_rsrc(a.Y, y_bytes);
+  const rsrc_t rS = make_rsrc(a.scale ? a.scale : a.Y, a.scale ? y_bytes : 0u);
 
-  // this thread's staging coordinates (fixed for all slices)
-  int op_row[OP_CH], op_chk[OP_CH];
-#pragma unroll
-  for (int i = 0; i < OP_CH; ++i) {
-    const int e = tid + i * NT;
-    op_row[i] = e / (BK / 8);
-    op_chk[i] = e % (BK / 8);
-  }
-  int fl_line[FL_G], fl_grp[FL_G];
-#pragma unroll
-  for (int i = 0; i < FL_G; ++i) {
-    const int e = tid + i * NT;
-    fl_line[i] = CONTIG ? e / (BK / 8) : e % BT;
-    fl_grp[i] = CONTIG ? e % (BK / 8) : e / BT;
-  }
-
-  // per-thread byte offsets that stay fixed across slices (slices add a wave-uniform offset)
+  // this thread's operator chunks (hi and lo parts in one index space); rows past the allocation read
+  // the last allocated row (its outputs lie past M and are not stored)
+  int op_dst[OP_CH];
   uint32_t op_voff[OP_CH];
 #pragma unroll
-  for (int i = 0; i < OP_CH; ++i) op_voff[i] = 2u * static_cast<uint32_t>((o0 + op_row[i]) * a.lda + op_chk[i] * 8);
+  for (int i = 0; i < OP_CH; ++i) {
+    const int c = tid + i * NT;
+    const int part = c / (BO * (BK / 8));
+    const int rem = c % (BO * (BK / 8));
+    const int row = rem / (BK / 8), chk = rem % (BK / 8);
+    op_dst[i] = (part ? OPL : OPH) + row * LDK + chk * 8;
+    const int grow = min(o0 + row, a.mrows - 1);
+    op_voff[i] = (part ? a.lo_off : 0u) + 2u * static_cast<uint32_t>(grow * a.lda + chk * 8);
+  }
+  // this thread's field groups: line and first k of 8
+  int fl_line[FL_G], fl_grp[FL_G];
   uint32_t fl_voff[FL_G];
   bool fl_ok[FL_G];
 #pragma unroll
   for (int i = 0; i < FL_G; ++i) {
+    const int e = tid + i * NT;
+    fl_line[i] = CONTIG ? e / (BK / 8) : e % BF;
+    fl_grp[i] = CONTIG ? e % (BK / 8) : e / BF;
     const int64_t line = f0 + fl_line[i];
-    fl_ok[i] = line < a.ncols;
-    // strided: X[k][line] at (k * ncols + line) * 4; contiguous: X[line][k] at (line * K + k) * 4
-    fl_voff[i] = CONTIG ? static_cast<uint32_t>(4 * (line * a.K + fl_grp[i] * 8))
-                        : static_cast<uint32_t>(4 * (static_cast<int64_t>(fl_grp[i]) * 8 * a.ncols + line));
+    fl_ok[i] = line < a.lines;
+    if (CONTIG) {
+      fl_voff[i] = static_cast<uint32_t>(4 * (line * a.K + fl_grp[i] * 8));
+    } else {
+      // strided: line (b, c) holds X[b][k][c] at b x_bstride + k ncols + c
+      const int64_t b = line / a.ncols, c = line - b * a.ncols;
+      fl_voff[i] = static_cast<uint32_t>(4 * (b * a.x_bstride + static_cast<int64_t>(fl_grp[i]) * 8 * a.ncols + c));
+    }
   }
   const uint32_t kstride = CONTIG ? 4u : static_cast<uint32_t>(4 * a.ncols);   // bytes per unit of k
-  // FMODE 1: element q (0 .. 15) of a slice is row (tid / 32) + 8 q, k = k0 + tid % 32
+  // FMODE 1: element q (0 .. 15) of a slice is row (tid / 32) + 16 q, k = k0 + tid % 32
   const int lk = tid & 31, lrow = tid >> 5;
   const uint32_t lk_base = static_cast<uint32_t>(4 * ((f0 + lrow) * a.K + lk));
-  const uint32_t lk_qstride = static_cast<uint32_t>(4 * 8 * a.K);
+  const uint32_t lk_qstride = static_cast<uint32_t>(4 * 16 * a.K);
 
-  u32x4 rOh[2][OP_CH], rOl[2][OP_CH];
+  u32x4 rO[2][OP_CH];
   float rF[2][FL_G][8];
 
 #define PSTD_LOAD_SLICE(R, K0)                                                                        \
   {                                                                                                   \
     const int k0_ = (K0);                                                                             \
-    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) {                                               \
-      rOh[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + 2u * k0_);                                          \
-      rOl[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + a.lo_off + 2u * k0_);                               \
-    }                                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) rO[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + 2u * k0_); \
     _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                                \
       const int kb = k0_ + fl_grp[i] * 8;                                                             \
       if (VEC) {                                                                                      \
-        /* each 16-byte half is all valid or all past the row (K % 4 == 0) */                         \
-        /* an invalid half reads offset 0 (in bounds) and is zeroed */                                \
+        /* each 16-byte half is all valid or all past the row (K % 4 == 0); an invalid half reads */  \
+        /* offset 0 (in bounds) and is zeroed */                                                      \
         const bool h0 = fl_ok[i] && kb + 4 <= a.K, h1 = fl_ok[i] && kb + 8 <= a.K;                    \
-        const f32x4 v0 = ld16<f32x4>(Xb, h0 ? fl_voff[i] + 4u * k0_ : 0u);                            \
-        const f32x4 v1 = ld16<f32x4>(Xb, h1 ? fl_voff[i] + 16u + 4u * k0_ : 0u);                      \
+        const f32x4 v0 = ld16<f32x4>(a.X, h0 ? fl_voff[i] + 4u * k0_ : 0u);                           \
+        const f32x4 v1 = ld16<f32x4>(a.X, h1 ? fl_voff[i] + 16u + 4u * k0_ : 0u);                     \
         _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                               \
           rF[R][i][j] = h0 ? v0[j] : 0.f;                                                             \
           rF[R][i][4 + j] = h1 ? v1[j] : 0.f;                                                         \
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
       } else if (LANEK) {                                                                             \
         _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                               \
           const int q_ = 8 * i + j;                                                                   \
-          const bool ok_ = f0 + lrow + 8 * q_ < a.ncols && k0_ + lk < a.K;                            \
+          const bool ok_ = f0 + lrow + 16 * q_ < a.lines && k0_ + lk < a.K;                           \
           rF[R][i][j] = ld_f32(rX, ok_ ? lk_base + q_ * lk_qstride : kOOB, 4u * k0_);                  \
         }                                                                                             \
       } else {                                                                                        \
@@ -202,17 +214,13 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
 
 #define PSTD_STORE_SLICE(R, BUF)                                                                      \
   {                                                                                                   \
-    __bf16* L = &lds[(BUF)][0][0];                                                                    \
-    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) {                                               \
-      const int o = op_row[i] * LDK + op_chk[i] * 8;                                                  \
-      *reinterpret_cast<u32x4*>(L + OPH * TILE_ELEMS + o) = rOh[R][i];                                \
-      *reinterpret_cast<u32x4*>(L + OPL * TILE_ELEMS + o) = rOl[R][i];                                \
-    }                                                                                                 \
+    __bf16* L = lds + (BUF) * BUF_ELEMS;                                                              \
+    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) *reinterpret_cast<u32x4*>(L + op_dst[i]) = rO[R][i]; \
     if (LANEK) {                                                                                      \
       /* lanes 2m and 2m+1 hold k = 2m, 2m+1 of one row: after the swap both hold the pair; the even */ \
       /* lane stores its hi parts, the odd lane its lo parts, each as one dword */                    \
       const bool odd_ = (lk & 1) != 0;                                                                \
-      __bf16* dst_ = L + (odd_ ? FLL : FLH) * TILE_ELEMS + (lk & ~1);                                 \
+      __bf16* dst_ = L + (odd_ ? FLL : FLH) + (lk & ~1);                                              \
       _Pragma("unroll") for (int i = 0; i < FL_G; ++i) _Pragma("unroll") for (int j = 0; j < 8; ++j) { \
         const float x_ = rF[R][i][j];                                                                 \
         const float y_ = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x_), 0xB1, 0xF, 0xF, false)); \
@@ -222,43 +230,45 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
         const __bf16 po_ = odd_ ? static_cast<__bf16>(o_ - static_cast<float>(ho_)) : ho_;            \
         const uint32_t w_ = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, pe_)) |                \
                             (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, po_)) << 16);         \
-        *reinterpret_cast<uint32_t*>(dst_ + (lrow + 8 * (8 * i + j)) * LDK) = w_;                     \
+        *reinterpret_cast<uint32_t*>(dst_ + (lrow + 16 * (8 * i + j)) * LDK) = w_;                    \
       }                                                                                               \
     } else {                                                                                          \
       _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                              \
         bf16x8 h, l;                                                                                  \
         split8(rF[R][i], h, l);                                                                       \
         const int o = fl_line[i] * LDK + fl_grp[i] * 8;                                               \
-        *reinterpret_cast<bf16x8*>(L + FLH * TILE_ELEMS + o) = h;                                     \
-        *reinterpret_cast<bf16x8*>(L + FLL * TILE_ELEMS + o) = l;                                     \
+        *reinterpret_cast<bf16x8*>(L + FLH + o) = h;                                                  \
+        *reinterpret_cast<bf16x8*>(L + FLL + o) = l;                                                  \
       }                                                                                               \
     }                                                                                                 \
   }
 
-  f32x16 acc[2][2];
+  f32x16 acc[IP][JQ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IP; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JQ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int prow = wp * 64 + (lane & 31);
-  const int qrow = wq * 64 + (lane & 31);
+  const int prow = wp * TP + (lane & 31);
+  const int qrow = wq * TQ + (lane & 31);
 
 #define PSTD_COMPUTE(BUF)                                                                             \
   {                                                                                                   \
-    const __bf16* L = &lds[(BUF)][0][0];                                                              \
+    const __bf16* L = lds + (BUF) * BUF_ELEMS;                                                        \
     _Pragma("unroll") for (int kk = 0; kk < BK; kk += 16) {                                           \
       const int koff = kk + 8 * (lane >> 5);                                                          \
-      bf16x8 ph[2], pl[2], qh[2], ql[2];                                                              \
-      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                 \
-        ph[i] = *reinterpret_cast<const bf16x8*>(L + 0 * TILE_ELEMS + (prow + 32 * i) * LDK + koff);  \
-        pl[i] = *reinterpret_cast<const bf16x8*>(L + 1 * TILE_ELEMS + (prow + 32 * i) * LDK + koff);  \
-        qh[i] = *reinterpret_cast<const bf16x8*>(L + 2 * TILE_ELEMS + (qrow + 32 * i) * LDK + koff);  \
-        ql[i] = *reinterpret_cast<const bf16x8*>(L + 3 * TILE_ELEMS + (qrow + 32 * i) * LDK + koff);  \
+      bf16x8 ph[IP], pl[IP], qh[JQ], ql[JQ];                                                          \
+      _Pragma("unroll") for (int i = 0; i < IP; ++i) {                                                \
+        ph[i] = *reinterpret_cast<const bf16x8*>(L + PH + (prow + 32 * i) * LDK + koff);              \
+        pl[i] = *reinterpret_cast<const bf16x8*>(L + PL + (prow + 32 * i) * LDK + koff);              \
       }                                                                                               \
-      _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) {   \
+      _Pragma("unroll") for (int j = 0; j < JQ; ++j) {                                                \
+        qh[j] = *reinterpret_cast<const bf16x8*>(L + QH + (qrow + 32 * j) * LDK + koff);              \
+        ql[j] = *reinterpret_cast<const bf16x8*>(L + QL + (qrow + 32 * j) * LDK + koff);              \
+      }                                                                                               \
+      _Pragma("unroll") for (int i = 0; i < IP; ++i) _Pragma("unroll") for (int j = 0; j < JQ; ++j) { \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl[i], qh[j], acc[i][j], 0, 0, 0);        \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], ql[j], acc[i][j], 0, 0, 0);        \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[i], qh[j], acc[i][j], 0, 0, 0);        \
@@ -295,67 +305,95 @@ __global__ __launch_bounds__(NT, 2) void split_kernel(SArgs a) {
 #undef PSTD_STORE_SLICE
 
   // fused update epilogue; lanes 0..31 write 32 consecutive floats of one output line.  Every load of
-  // Y (and of the c0 map) is issued before the first store: one memory round trip.  Outside the field
-  // the offset is out of range: loads return 0 and stores are dropped.
-  uint32_t yoff[2][2][16];
+  // Y is issued before the first store: one memory round trip.  Outside the field the offset is out of
+  // range: loads return 0 and stores are dropped.  Offsets are formed where they are used (a few integer
+  // operations each) rather than kept next to the accumulators.
+  const int lrow4 = 4 * (lane >> 5), lcol = lane & 31;
+  // the Q-port coordinate of column j: a field line (strided) or an operator row (contiguous)
+  int64_t qbase[JQ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < JQ; ++j) {
+    const int qc = wq * TQ + j * 32 + lcol;
+    if (CONTIG) {
+      qbase[j] = o0 + qc;                       // m
+    } else {
+      const int64_t line = f0 + qc;
+      const int64_t b = line / a.ncols, c = line - b * a.ncols;
+      qbase[j] = line < a.lines ? b * a.y_bstride + c : -1;   // offset of (b, m = 0, c); -1 past the field
+    }
+  }
+  auto yoff = [&](int i, int j, int r) -> uint32_t {
+    const int pr = wp * TP + i * 32 + 8 * (r >> 2) + lrow4 + (r & 3);
+    if (CONTIG) {
+      const int64_t line = f0 + pr;
+      const int64_t m = qbase[j];
+      return (line < a.lines && m < a.M) ? static_cast<uint32_t>(4 * (line * a.M + m)) : kOOB;
+    }
+    const int m = o0 + pr;
+    return (qbase[j] >= 0 && m < a.M) ? static_cast<uint32_t>(4 * (qbase[j] + static_cast<int64_t>(m) * a.ncols))
+                                      : kOOB;
+  };
+  if (a.scale) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < IP; ++i)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int pr = wp * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int qc = wq * 64 + j * 32 + (lane & 31);
-        const int64_t line = f0 + (CONTIG ? pr : qc);
-        const int m = o0 + (CONTIG ? qc : pr);
-        const bool ok = line < a.ncols && m < a.M;
-        yoff[i][j][r] = ok ? static_cast<uint32_t>(4 * (CONTIG ? line * a.M + m : static_cast<int64_t>(m) * a.ncols + line))
-                           : kOOB;
-      }
-  float yv[2][2][16];
+      for (int j = 0; j < JQ; ++j)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ld_f32(rS, yoff(i, j, r), 0);
+  }
+  if (a.beta != 0.f) {
+    float yv[IP][JQ][16];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < IP; ++i)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        yv[i][j][r] = a.beta != 0.f ? ld_f32(rY, yoff[i][j][r], 0) : 0.f;
-        if (a.scale) acc[i][j][r] *= ld_f32(rS, yoff[i][j][r], 0);
-      }
+      for (int j = 0; j < JQ; ++j)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+        for (int r = 0; r < 16; ++r) yv[i][j][r] = ld_f32(rY, yoff(i, j, r), 0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < IP; ++i)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) st_f32(rY, a.beta * yv[i][j][r] + a.alpha * acc[i][j][r], yoff[i][j][r]);
+      for (int j = 0; j < JQ; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) st_f32(rY, a.beta * yv[i][j][r] + a.alpha * acc[i][j][r], yoff(i, j, r));
+  } else {
+#pragma unroll
+    for (int i = 0; i < IP; ++i)
+#pragma unroll
+      for (int j = 0; j < JQ; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) st_f32(rY, a.alpha * acc[i][j][r], yoff(i, j, r));
+  }
 }
 
 template <bool CONTIG>
 hipError_t launch_s(const ContractArgs& c, hipStream_t s) {
-  static_assert(BT <= kRowPad && kRowPad % BT == 0 && kColPad % BK == 0, "operator padding must cover tiles");
+  static_assert(kColPad % BK == 0, "operator columns must be padded to whole K slices");
   SArgs a;
   a.Ahi = static_cast<const uint16_t*>(c.A);
-  a.Alo = static_cast<const uint16_t*>(c.A_lo);
   a.lda = c.lda;
   a.M = c.M;
   a.K = c.K;
+  a.mrows = static_cast<int>(round_up(c.M, kRowPad));   // the allocation of upload_operator
   a.X = static_cast<const float*>(c.X);
   a.Y = static_cast<float*>(c.Y);
   a.ncols = c.ncols;
-  a.batch = c.batch;
   a.x_bstride = c.x_bstride;
   a.y_bstride = c.y_bstride;
+  a.lines = CONTIG ? c.ncols : c.ncols * c.batch;
   a.alpha = c.alpha;
   a.beta = c.beta;
   a.scale = static_cast<const float*>(c.scale);
-  a.op_tiles = (c.M + BT - 1) / BT;
-  a.fld_tiles = ((c.ncols + BT - 1) / BT) * (CONTIG ? 1 : c.batch);
+  a.op_tiles = (c.M + BO - 1) / BO;
+  a.fld_tiles = (a.lines + BF - 1) / BF;
   const int64_t blocks = a.fld_tiles * a.op_tiles;
   if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-  // buffer offsets are 32-bit: every slab must stay below 2 GiB (checked at plan creation too)
-  const int64_t xb = 4 * c.ncols * static_cast<int64_t>(c.K), yb = 4 * c.ncols * static_cast<int64_t>(c.M);
+  // buffer offsets are 32-bit: the whole input and output must stay below 2 GiB (checked at plan creation)
+  const int64_t xb = 4 * (CONTIG ? a.lines * c.K : c.batch * c.x_bstride);
+  const int64_t yb = 4 * (CONTIG ? a.lines * c.M : c.batch * c.y_bstride);
   const int64_t ob = reinterpret_cast<const char*>(c.A_lo) - reinterpret_cast<const char*>(c.A);
   if (xb >= (int64_t(1) << 31) || yb >= (int64_t(1) << 31) || ob <= 0 || 2 * ob >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
+  if (!CONTIG && (c.x_bstride != static_cast<int64_t>(c.K) * c.ncols || c.y_bstride != static_cast<int64_t>(c.M) * c.ncols))
     return hipErrorInvalidValue;
   a.lo_off = static_cast<uint32_t>(ob);
   const dim3 grid(static_cast<unsigned>(blocks));

@@ -158,6 +158,12 @@ class Plan:
         st.step = cs.step
         return st
 
+    def prepare(self, st: State, n_steps: int) -> None:
+        """Capture, without running them, the step graphs a later step(st, n_steps) replays."""
+        self._check_state(st)
+        cs = st._c()
+        check(load().pstd_step_prepare(self._h, C.byref(cs), int(n_steps)), "pstd_step_prepare")
+
     PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3}
 
     def set_path(self, path: str) -> None:

@@ -9,6 +9,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import _lib
 from ._lib import NopConfig, check, load
 from .pstd import Batch, _stream_handle, _torch
 
@@ -194,23 +195,24 @@ class Gate:
     wall_share_max: float = 1e-3
 
 
-def predict(net: Surrogate, p0, c0, tol: float, gate: Gate, dx, dt, steps, bcs):
-    """Surrogate answer where the gate admits it, the FP32 PSTD solver's answer elsewhere.
+def predict(net: Surrogate, p0, c0, tol: float, gate: Gate, dx, dt, steps, bcs, rho0=1000.0):
+    """Surrogate answer where the gate admits it, the FP32 PSTD solver's answer elsewhere
+    (``pstd_nop_predict``: statistics, gate, inference and the batched fallback all run in the library).
 
     Returns (out, fallback) with fallback a boolean array marking the samples the solver produced."""
     torch = _torch()
     p, cm = net._dev(p0), net._dev(c0)
     B = int(p.shape[0])
-    st = input_stats(net, p, cm, gate.wall_margin)
-    inside = ((st[:, 0] >= gate.c0_lo) & (st[:, 1] <= gate.c0_hi) & (st[:, 2] <= gate.p_max)
-              & (st[:, 3] <= gate.wall_share_max))
-    fallback = ~inside | (gate.validated_error > tol)
     out = torch.empty_like(p)
-    for s0 in range(0, B, net.max_batch):
-        s1 = min(B, s0 + net.max_batch)
-        net.infer(p[s0:s1], cm[s0:s1], out=out[s0:s1])
-    idx = np.nonzero(fallback)[0]
-    if idx.size:
-        ti = torch.from_numpy(idx).to(p.device)
-        out[ti] = solver_targets(p[ti], cm[ti], dx, dt, steps, bcs)
-    return out, fallback
+    g = _lib.NopGate(float(gate.validated_error), float(gate.c0_lo), float(gate.c0_hi), float(gate.p_max),
+                     int(gate.wall_margin), float(gate.wall_share_max))
+    pr = _lib.NopProblem()
+    pr.dx, pr.dt, pr.rho0, pr.steps = float(dx), float(dt), float(rho0), int(steps)
+    faces = [int(f) for pair in bcs for f in pair]
+    for i in range(4):
+        pr.bc[i] = faces[i]
+    fb = np.zeros(B, np.int32)
+    nf = C.c_int32(0)
+    check(load().pstd_nop_predict(net._h, C.byref(g), C.byref(pr), p.data_ptr(), cm.data_ptr(), out.data_ptr(), B,
+                                  float(tol), fb.ctypes.data_as(C.c_void_p), C.byref(nf)), "pstd_nop_predict")
+    return out, fb.astype(bool)

@@ -95,3 +95,23 @@ def test_stability_limit_enforced(shape, bcs):
     assert lib.pstd_plan_create(C.byref(_grid(shape)), dx, dt_bad, c0, _faces(*bcs), C.byref(h)) == _lib.E_UNSTABLE
     if len(shape) == 1:
         assert abs(limit - 2.0 / np.pi) < 1e-12     # §4.2's 1D limit for Neumann at both ends
+
+
+def test_nop_predict_rejects_bad_arguments_before_device_work():
+    lib = _lib.load()
+    g = _lib.NopGate(0.1, 1400.0, 1600.0, 3.0, 10, 1e-3)
+    pr = _lib.NopProblem()
+    pr.dx, pr.dt, pr.rho0, pr.steps = 1e-4, 1e-8, 1000.0, 10
+    nf = C.c_int32(-1)
+    # null surrogate handle, null gate, null buffers
+    assert lib.pstd_nop_predict(None, C.byref(g), C.byref(pr), 1, 1, 1, 4, 0.5, None, C.byref(nf)) == _lib.E_INVALID_ARG
+    assert lib.pstd_nop_predict(None, None, C.byref(pr), 1, 1, 1, 4, 0.5, None, None) == _lib.E_INVALID_ARG
+    assert nf.value == -1
+    assert b"null" in lib.pstd_last_error()
+
+
+def test_step_prepare_rejects_bad_arguments():
+    lib = _lib.load()
+    st = _lib.State()
+    assert lib.pstd_step_prepare(None, C.byref(st), 10) == _lib.E_INVALID_ARG
+    assert lib.pstd_step_prepare(None, None, 10) == _lib.E_INVALID_ARG

@@ -163,4 +163,11 @@ def test_gate_and_solver_fallback():
     # a tolerance below the validated error sends everything to the solver
     out, fb = predict(net, p, c, 0.1, gate, workloads.DX, dt, 30, workloads.NOP_BCS)
     assert fb.all() and torch.equal(out, ref)
+    # a request larger than the surrogate's buffers: statistics and inference in max_batch chunks
+    p6 = torch.cat([p, p[:2]]).contiguous()
+    c6 = torch.cat([c, c[:2]]).contiguous()
+    out, fb = predict(net, p6, c6, 0.5, gate, workloads.DX, dt, 30, workloads.NOP_BCS)
+    assert fb.tolist() == [False, False, True, True, False, False]
+    assert torch.equal(out[:2], net_out[:2]) and torch.equal(out[2:4], ref[2:])
+    assert torch.allclose(out[4:], net_out[:2], rtol=1e-6, atol=1e-6 * float(net_out[:2].abs().max()))
     net.close()

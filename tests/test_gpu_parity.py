@@ -51,6 +51,34 @@ def test_1d_image_source_fp64():
     assert rel_l2(p, ref) < 1e-9
 
 
+@pytest.mark.parametrize("prec,n,path", [("fp64", 1400, None), ("fp32", 1400, None), ("fp64", 2049, "per_axis"),
+                                         ("fp32", 2049, "per_axis")])
+def test_1d_walls_above_single_workgroup(prec, n, path):
+    # walls on nodes above 1365 nodes: 2(n-1) = 2798 has the prime factor 1399, so the 1400-node axis runs
+    # on the dense contraction path; the 2049-node axis is moved there from the FFT path
+    dx, c0 = 1e-4, 1500.0
+    bcs = ((D, N),)
+    p0 = workloads.gaussian((n,), dx, (0.37 * (n - 1) * dx,), 8 * dx)
+    case = workloads.Case("walls1d", (n,), bcs, dx, 0.4 * dx / c0, c0, 120, p0, precision=prec)
+    _print_case(case, prec)
+    p, _ = run_gpu(case, prec, path=path)
+    ref = oracle_problem(case).modal_solution(p0, case.steps)
+    assert rel_l2(p, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("steps", [1, 7, 49, 50, 57, 120])
+def test_any_step_count_replays_graphs(steps):
+    # every step count replays captured graphs (whole chunks of 50 steps, then one of the rest); the
+    # result equals single steps and the oracle
+    case = workloads.random_small_case(21, 3, max_n=20, steps=steps)
+    _print_case(case, "fp32")
+    p1, _ = run_gpu(case, "fp32")
+    p2, _ = run_gpu(case, "fp32", chunks=[1] * steps)
+    po, _ = oracle_problem(case).run(case.p0, steps)
+    assert np.array_equal(p1, p2)
+    assert rel_l2(p1, po) < TOL["fp32"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16"])
 @pytest.mark.parametrize("seed,ndim", [(10, 2), (11, 2), (12, 3), (13, 3), (14, 2)])
 def test_random_small(prec, seed, ndim):

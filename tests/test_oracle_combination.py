@@ -5,6 +5,8 @@
 * Non-reflecting walls (R_L = R_R = 0): the weighted sum of the four basic 1D fields equals the
   free-space solution (no images) until T = 3L/c0, and is zero to rounding once the pulse has left.
 * (R_L, R_R) = (0, 0.5): the sum equals the image solution with amplitudes r up to T = 2L/c0.
+* 2D, a different partial R on each face: the 16 weighted basic fields equal the image solution in
+  which each image carries the product of its per-face reflection factors.
 * The two-field op p_R = (1+R)/2 p_N + (1-R)/2 p_D equals the four-field result until doubly reflected
   arrivals and differs after them.
 """
@@ -109,3 +111,56 @@ def test_two_field_combination_window():
     # R = +1 / -1 reproduce the basic fields exactly
     assert np.array_equal(pstd.combine_R(fields[3], fields[0], 1.0), fields[0])
     assert np.array_equal(pstd.combine_R(fields[3], fields[0], -1.0), fields[3])
+
+
+def test_partial_images_reduce_to_basic_walls():
+    """R = +-1 on both walls: the partial-reflection image series is the basic walls' series."""
+    L, xs, reach = 1.0, 0.37, 5.0
+    for bl, br in pstd.BASIC_CASES:
+        RL, RR = (1.0 if bl == N else -1.0), (1.0 if br == N else -1.0)
+        a = sorted(images.image_positions_1d(xs, L, bl, br, reach))
+        b = sorted(images.partial_image_positions_1d(xs, L, RL, RR, reach))
+        assert len(a) == len(b)
+        for (pa, sa), (pb, sb) in zip(a, b):
+            assert abs(pa - pb) < 1e-14 and sa == sb
+
+
+def _mixed_faces_case():
+    shape, dx, c0 = (57, 69), 1e-4, 1500.0
+    dt = 0.2 * dx / c0
+    L = [(n - 1) * dx for n in shape]
+    centre, sigma = (0.45 * L[0], 0.5 * L[1]), 3 * dx
+    x = [np.arange(n) * dx for n in shape]
+    X, Y = np.meshgrid(*x, indexing="ij")
+    p0 = np.exp(-0.5 * ((X - centre[0]) ** 2 + (Y - centre[1]) ** 2) / sigma ** 2)
+    m = int(round(1.9 * min(L) / (c0 * dt)))        # doubly reflected images inside, before 2 L_min / c0
+    return shape, dx, c0, dt, centre, sigma, p0, m
+
+
+def _weighted_fields(shape, dx, c0, dt, p0, m, weights):
+    out = np.zeros(shape)
+    for cases, w in weights.items():
+        if w != 0.0:
+            out += w * pstd.Problem(shape, cases, dx, dt, c0).modal_solution(p0, m)
+    return out
+
+
+def test_mixed_partial_faces_2d_match_images():
+    """A different real R on each face of a 2D box: the 16 weighted basic-wall fields (§5, extended to
+    d dimensions by separable images) equal the physical image solution in which every image carries
+    the product of its per-face reflection factors, while no wave has met one pair of walls twice.
+
+    The weights come from ``combination_weights`` and the reference from ``partial_image_solution``,
+    which forms no weight at all.  The doubly reflected images have entered the box, so planted errors
+    in the weights (axes exchanged, left and right exchanged, the R_L R_R term dropped or of the wrong
+    sign) each move the weighted sum by 2e-2 or more, against 1e-14 agreement."""
+    R = [(0.0, 0.5), (-0.3, 0.8)]
+    shape, dx, c0, dt, centre, sigma, p0, m = _mixed_faces_case()
+    comb = _weighted_fields(shape, dx, c0, dt, p0, m, pstd.combination_weights(R))
+    ref = images.partial_image_solution(shape, R, dx, c0, dt, m, centre, 1.0, sigma)
+    assert np.max(np.abs(ref)) > 0.02
+    assert np.max(np.abs(comb - ref)) < 1e-9
+    # the reference tells the faces apart: swapped axes or mirrored walls are far from it
+    for other in ([R[1], R[0]], [R[0][::-1], R[1]], [R[0], R[1][::-1]]):
+        alt = images.partial_image_solution(shape, other, dx, c0, dt, m, centre, 1.0, sigma)
+        assert np.max(np.abs(alt - ref)) > 1e-2
