@@ -64,9 +64,8 @@ constexpr int FL_G = BF * (BK / 8) / NT;        // 8-float field groups per thre
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr uint32_t kOOB = 0x80000000u;   // byte offset past every buffer used here (all < 2 GiB)
 
-// Raw buffer resource over `bytes` bytes: a 4-byte load at an offset >= bytes returns 0 and a store
-// there is dropped, which replaces bounds checks by out-of-range offsets.  Only 4-byte buffer accesses
-// are used.
+// Raw buffer resource over `bytes` bytes: a load at an offset >= bytes returns 0 without a memory access
+// and a store there is dropped, which replaces bounds checks by out-of-range offsets.
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
 }
@@ -76,10 +75,8 @@ __device__ __forceinline__ float ld_f32(rsrc_t r, uint32_t voff, uint32_t soff) 
 __device__ __forceinline__ void st_f32(rsrc_t r, float v, uint32_t voff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
 }
-// 16-byte global load at a wave-uniform base plus a 32-bit byte offset
-template <typename V>
-__device__ __forceinline__ V ld16(const void* base, uint32_t off) {
-  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+__device__ __forceinline__ u32x4 ld_b128(rsrc_t r, uint32_t voff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
 }
 
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& h, bf16x8& l) {
@@ -139,6 +136,7 @@ __global__ __launch_bounds__(NT, 1) void split_kernel(SArgs a) {
   const rsrc_t rX = make_rsrc(a.X, x_bytes);
   const rsrc_t rY = make_rsrc(a.Y, y_bytes);
   const rsrc_t rS = make_rsrc(a.scale ? a.scale : a.Y, a.scale ? y_bytes : 0u);
+  const rsrc_t rA = make_rsrc(a.Ahi, 2u * a.lo_off);          // hi part then lo part
 
   // this thread's operator chunks (hi and lo parts in one index space); rows past the allocation read
   // the last allocated row (its outputs lie past M and are not stored)
@@ -181,22 +179,25 @@ __global__ __launch_bounds__(NT, 1) void split_kernel(SArgs a) {
 
   u32x4 rO[2][OP_CH];
   float rF[2][FL_G][8];
+  const int nslices = (a.K + BK - 1) / BK;
+  const int kend = nslices * BK;        // loads of slices past the last one read nothing
 
 #define PSTD_LOAD_SLICE(R, K0)                                                                        \
   {                                                                                                   \
     const int k0_ = (K0);                                                                             \
-    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i) rO[R][i] = ld16<u32x4>(a.Ahi, op_voff[i] + 2u * k0_); \
+    const bool kin_ = k0_ < kend;                                                                     \
+    _Pragma("unroll") for (int i = 0; i < OP_CH; ++i)                                                 \
+      rO[R][i] = ld_b128(rA, kin_ ? op_voff[i] + 2u * k0_ : kOOB);                                    \
     _Pragma("unroll") for (int i = 0; i < FL_G; ++i) {                                                \
       const int kb = k0_ + fl_grp[i] * 8;                                                             \
       if (VEC) {                                                                                      \
-        /* each 16-byte half is all valid or all past the row (K % 4 == 0); an invalid half reads */  \
-        /* offset 0 (in bounds) and is zeroed */                                                      \
+        /* each 16-byte half is all valid or all past the row (K % 4 == 0) */                         \
         const bool h0 = fl_ok[i] && kb + 4 <= a.K, h1 = fl_ok[i] && kb + 8 <= a.K;                    \
-        const f32x4 v0 = ld16<f32x4>(a.X, h0 ? fl_voff[i] + 4u * k0_ : 0u);                           \
-        const f32x4 v1 = ld16<f32x4>(a.X, h1 ? fl_voff[i] + 16u + 4u * k0_ : 0u);                     \
+        const f32x4 v0 = __builtin_bit_cast(f32x4, ld_b128(rX, h0 ? fl_voff[i] + 4u * k0_ : kOOB));   \
+        const f32x4 v1 = __builtin_bit_cast(f32x4, ld_b128(rX, h1 ? fl_voff[i] + 16u + 4u * k0_ : kOOB)); \
         _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                               \
-          rF[R][i][j] = h0 ? v0[j] : 0.f;                                                             \
-          rF[R][i][4 + j] = h1 ? v1[j] : 0.f;                                                         \
+          rF[R][i][j] = v0[j];                                                                        \
+          rF[R][i][4 + j] = v1[j];                                                                    \
         }                                                                                             \
       } else if (LANEK) {                                                                             \
         _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                               \
@@ -277,14 +278,12 @@ __global__ __launch_bounds__(NT, 1) void split_kernel(SArgs a) {
   }
 
   // slice s lives in LDS buffer s&1 and (before that) in register set s&1.  Prefetches past the last
-  // slice re-load the last slice (in bounds, never stored where it is read), which keeps the loop body
-  // straight-line so that each wait covers only the loads it needs.
-  const int nslices = (a.K + BK - 1) / BK;
-  const int last = nslices - 1;
+  // slice use out-of-range offsets (no memory access), which keeps the loop body straight-line so that
+  // each wait covers only the loads it needs.
   PSTD_LOAD_SLICE(0, 0);
-  PSTD_LOAD_SLICE(1, min(1, last) * BK);
+  PSTD_LOAD_SLICE(1, BK);
   PSTD_STORE_SLICE(0, 0);
-  PSTD_LOAD_SLICE(0, min(2, last) * BK);
+  PSTD_LOAD_SLICE(0, 2 * BK);
   lds_barrier();
   // Only the MFMA work is conditional: the stores and (clamped) loads run in every step, so each load
   // stays where it is issued instead of being moved next to its store behind a branch.
@@ -292,12 +291,12 @@ __global__ __launch_bounds__(NT, 1) void split_kernel(SArgs a) {
     // even slice s: LDS buffer 0; slice s+1 waits in register set 1, slice s+2 in set 0
     PSTD_COMPUTE(0);
     PSTD_STORE_SLICE(1, 1);
-    PSTD_LOAD_SLICE(1, min(s + 3, last) * BK);
+    PSTD_LOAD_SLICE(1, (s + 3) * BK);
     lds_barrier();
     // odd slice s+1 (none past the last): LDS buffer 1; slice s+2 waits in set 0, slice s+3 in set 1
     if (s + 1 < nslices) PSTD_COMPUTE(1);
     PSTD_STORE_SLICE(0, 0);
-    PSTD_LOAD_SLICE(0, min(s + 4, last) * BK);
+    PSTD_LOAD_SLICE(0, (s + 4) * BK);
     lds_barrier();
   }
 #undef PSTD_COMPUTE
