@@ -362,6 +362,18 @@ int pstd_nop_predict(pstd_nop nop, const pstd_nop_gate* gate, const pstd_nop_pro
                      const float* c0, float* out, int32_t batch, double tol, int32_t* fallback, int32_t* n_fallback);
 
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): err[b] = |pred[b] - target[b]|_2 / |target[b]|_2 (0 where the
+ * target is zero) for b < batch, the measure of pstd_nop_relative_errors without a surrogate handle.
+ * pred, target: device arrays of batch x count floats; err: device array of batch doubles (caller-owned).
+ * Sums in FP64.  Enqueues two kernels on hip_stream (NULL = null stream) and nothing else: no allocation,
+ * copy or synchronisation.  The per-block partial sums live in a 1 MiB array that the library keeps on
+ * each GPU it runs on until the process ends; every call on a GPU shares it, so calls that overlap on one
+ * GPU (several streams or host threads) race.  PSTD_E_INVALID_ARG for null pointers or batch, count < 1;
+ * PSTD_E_UNSUPPORTED for batch above 65536. */
+int pstd_relative_errors_static(const float* pred, const float* target, int32_t batch, int64_t count, double* err,
+                                void* hip_stream);
+
 const char* pstd_status_string(int status);
 const char* pstd_last_error(void);
 

@@ -109,6 +109,7 @@ SIGNATURES = {
     "pstd_nop_predict": (C.c_int, [C.c_void_p, C.POINTER(NopGate), C.POINTER(NopProblem), C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(C.c_int32)]),
     "pstd_nop_destroy": (C.c_int, [C.c_void_p]),
+    "pstd_relative_errors_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]),
     "pstd_status_string": (C.c_char_p, [C.c_int]),
     "pstd_last_error": (C.c_char_p, []),
 }
