@@ -7,8 +7,8 @@ and the current stream.  There is no CPU fallback: every call raises if the libr
 from .pstd import (DIRICHLET, DIRICHLET_HALF, GRAD_NODES, GRAD_STAG, NEUMANN, NEUMANN_HALF, NODES_TO_STAG,
                    PERIODIC, STAG_TO_NODES, Batch,
                    Plan, PstdError, State, axis_operator, combine_R,
-                   combine_fields, face_weights, lib_path, load_library, solve_faces_2d)
+                   combine_fields, face_weights, lib_path, load_library, solve_faces, solve_faces_2d)
 
-__all__ = ["Plan", "Batch", "State", "PstdError", "combine_R", "combine_fields", "face_weights", "solve_faces_2d",
+__all__ = ["Plan", "Batch", "State", "PstdError", "combine_R", "combine_fields", "face_weights", "solve_faces", "solve_faces_2d",
            "axis_operator", "NEUMANN", "DIRICHLET", "PERIODIC", "NEUMANN_HALF", "DIRICHLET_HALF", "GRAD_NODES", "GRAD_STAG", "NODES_TO_STAG",
            "STAG_TO_NODES", "load_library", "lib_path"]

@@ -5,7 +5,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpstd.so")
+# the in-tree build; PSTD_LIBRARY names another build of the same sources (e.g. the host-sanitizer one)
+LIB_PATH = os.environ.get("PSTD_LIBRARY") or os.path.join(_PKG, "libpstd.so")
 
 OK = 0
 E_INVALID_ARG = -1

@@ -303,6 +303,29 @@ def solve_faces_2d(shape, dx, dt, c0, R_faces, p0, n_steps, rho0=1000.0, batch=N
     return p, batch, states
 
 
+def solve_faces(shape, dx, dt, c0, R_faces, p0, n_steps, rho0=1000.0, precision="fp32", stream=None, out=None):
+    """The field for per-face reflection coefficients in 1D, 2D or 3D (§5): the 4^d basic-wall solves of the
+    same problem, one plan each on one stream, then their weighted sum (pstd_combine_fields) with the
+    weights of pstd_face_weights.  For many 2D solves of one shape ``solve_faces_2d`` runs them as one batch.
+
+    Returns p (float32, the plans' precision must be fp32 or split_bf16).
+    """
+    torch = _torch()
+    if precision not in ("fp32", "split_bf16"):
+        raise ValueError("the weighted sum runs on float32 fields")
+    cases, w = face_weights(R_faces)
+    s = torch.cuda.Stream() if stream is None else stream
+    fields = []
+    for cs in cases:
+        with Plan(shape, dx, dt, c0, cs, rho0=rho0, precision=precision, stream=s) as pl:
+            st = pl.new_state(p0)
+            pl.init_state(st)
+            pl.step(st, n_steps)
+            fields.append(st.p)
+            s.synchronize()
+    return combine_fields(fields, w, out=out, stream=s)
+
+
 class Batch:
     """Many independent 2D FP32 solves stepped by one persistent launch (include/pstd.h, pstd_batch_*).
 

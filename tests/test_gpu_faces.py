@@ -49,3 +49,26 @@ def test_rigid_faces_give_the_neumann_solve():
     nn = states[0].p.cpu().numpy()          # field 0: Neumann on every face, weight 1
     batch.close()
     assert np.array_equal(got, nn)
+
+
+@pytest.mark.parametrize("ndim,shape,steps,prec", [(1, (97,), 200, "fp32"), (3, (24, 26, 22), 30, "fp32"),
+                                                  (3, (24, 26, 22), 30, "split_bf16")])
+def test_faces_1d_3d_match_oracle(ndim, shape, steps, prec):
+    # 4 basic fields in 1D, 64 in 3D (§5: 2^(2d) solves), weighted by pstd_face_weights on the device
+    import torch
+    from paper_2005_00322_amd import solve_faces
+    rng = np.random.default_rng(40 + ndim)
+    c0, dx = float(rng.uniform(1400, 1600)), 1e-4
+    dt = 0.3 * dx / c0
+    R = [tuple(float(v) for v in rng.uniform(-1.0, 1.0, 2)) for _ in range(ndim)]
+    grids = np.meshgrid(*[np.arange(n) * dx for n in shape], indexing="ij")
+    centre = [rng.uniform(0.35, 0.65) * (n - 1) * dx for n in shape]
+    p0 = np.exp(-0.5 * sum((g - c) ** 2 for g, c in zip(grids, centre)) / (3 * dx) ** 2)
+    print("faces", ndim, shape, prec, R, flush=True)
+    p = solve_faces(shape, dx, dt, c0, R, p0, steps, precision=prec)
+    torch.cuda.synchronize()
+    got = p.double().cpu().numpy()
+    ref = np.zeros(shape)
+    for cs, w in opstd.combination_weights(R).items():
+        ref += w * opstd.Problem(shape, cs, dx, dt, c0).modal_solution(p0, steps)
+    assert rel_l2(got, ref) < TOL[prec]
