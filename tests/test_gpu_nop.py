@@ -1,10 +1,18 @@
 """GPU parity of the neural-operator surrogate against its FP64 reference (oracle.nop).
 
-Forward output and every parameter gradient are compared on a small configuration.  With split bf16
-products (hi*hi + hi*lo + lo*hi) the kernels are close to FP32 and must match to 1e-4 relative; with
-plain bf16 products (the training setting) to 3e-2.  The Adam kernel is compared with the reference
-update applied to the GPU's own gradient.  The batched solver's sound-speed maps (used to generate the
-training targets) are compared with the oracle's heterogeneous stepping.
+Forward output and every parameter gradient are compared on small configurations and on the full
+128 x 128 configuration (32 channels, 48 modes, 4 layers, 128 hidden units).  With split bf16 products
+(hi*hi + hi*lo + lo*hi) the kernels are close to FP32 and must match to 1e-4 relative.  With plain bf16
+products (the training setting) every product rounds both operands to bf16 (unit roundoff u = 2^-9), a
+relative perturbation of about sqrt(2) u per product; the longest chain of the forward pass is the lift,
+five spectral products per layer and the two projection products (1 + 5 x 4 + 2 = 23 at full size), so
+the output carries about sqrt(2 x 23) u = 1.3e-2 and a gradient, whose chain runs through those
+products and back through their transposes, about sqrt(4 x 23) u = 1.9e-2.  The bounds below are 2.5x
+those estimates: 3e-2 for the output and 5e-2 for each gradient group.  The output bias's gradient is a
+plain sum of the output gradient over every position, which can cancel; its error is measured against
+the sum of the summands' magnitudes instead of the sum itself.  The Adam kernel is compared with the
+reference update applied to the GPU's own gradient.  The batched solver's sound-speed maps (used to
+generate the training targets) are compared with the oracle's heterogeneous stepping.
 """
 import numpy as np
 import pytest
@@ -44,27 +52,66 @@ def _setup(split, B=3, seed=0, shape=SMALL):
     return torch, net, ocfg, theta, p0, c0, tgt
 
 
-@pytest.mark.parametrize("shape", ["small", "medium", "large", "wide"])
-@pytest.mark.parametrize("split,tol", [(True, 1e-4), (False, 3e-2)])
-def test_forward_and_gradients_match_reference(split, tol, shape):
-    torch, net, ocfg, theta, p0, c0, tgt = _setup(split, shape=SHAPES[shape])
-    print("surrogate parity split", split, shape, flush=True)
+TOL_OUT = {True: 1e-4, False: 3e-2}
+TOL_GRAD = {True: 1e-4, False: 5e-2}
+
+
+def _check_parity(net, ocfg, theta, p0, c0, tgt, split):
+    import torch
     out = net.forward(p0, c0)
     loss = net.backward(tgt)
     torch.cuda.synchronize()
     assert torch.equal(net.infer(p0, c0), out)   # the inference form computes the same map
     g = net.get_grads().astype(np.float64)
     th = theta.astype(np.float64)
-    ref_out = onop.forward(ocfg, th, p0.astype(np.float64), c0.astype(np.float64))
-    ref_loss, ref_g = onop.backward(ocfg, th, p0.astype(np.float64), c0.astype(np.float64), tgt.astype(np.float64))
-    assert rel_l2(out.double().cpu().numpy(), ref_out) < tol
-    assert abs(loss - ref_loss) < tol * ref_loss
+    p64, c64, t64 = p0.astype(np.float64), c0.astype(np.float64), tgt.astype(np.float64)
+    ref_out = onop.forward(ocfg, th, p64, c64)
+    ref_loss, ref_g = onop.backward(ocfg, th, p64, c64, t64)
+    e_out = rel_l2(out.double().cpu().numpy(), ref_out)
+    print("output rel L2 %.3e (bound %.0e)" % (e_out, TOL_OUT[split]), flush=True)
+    assert e_out < TOL_OUT[split]
+    assert abs(loss - ref_loss) < TOL_OUT[split] * ref_loss
+    # scale of the output bias's gradient: the magnitudes of its summands, the loss's output gradient
+    B = ref_out.shape[0]
+    dout = 2.0 * (ref_out - t64) / (B * np.sum(t64 ** 2, axis=(1, 2), keepdims=True))
     o = 0
     for name, shp in onop.param_shapes(ocfg):
         n = int(np.prod(shp))
-        e = rel_l2(g[o:o + n], ref_g[o:o + n])
-        assert e < (tol if split else 5 * tol), (name, e)
+        if name == "q2b":
+            e = abs(g[o] - ref_g[o]) / float(np.sum(np.abs(dout)))
+        else:
+            e = rel_l2(g[o:o + n], ref_g[o:o + n])
+        assert e < TOL_GRAD[split], (name, e)
         o += n
+
+
+@pytest.mark.parametrize("shape", ["small", "medium", "large", "wide"])
+@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_forward_and_gradients_match_reference(split, shape, seed):
+    torch, net, ocfg, theta, p0, c0, tgt = _setup(split, seed=seed, shape=SHAPES[shape])
+    print("surrogate parity split", split, shape, "seed", seed, flush=True)
+    _check_parity(net, ocfg, theta, p0, c0, tgt, split)
+    net.close()
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_full_configuration_matches_reference(split):
+    # the surrogate's own configuration on one held-out-style input (p0 blobs, smooth c0 map)
+    import torch
+    from paper_2005_00322_amd.surrogate import Surrogate, SurrogateConfig, param_shapes
+
+    scfg = SurrogateConfig()
+    ocfg = onop.Config()
+    assert (scfg.H, scfg.W, scfg.channels, scfg.modes, scfg.layers, scfg.hidden) == \
+        (ocfg.H, ocfg.W, ocfg.C, ocfg.Mm, ocfg.layers, ocfg.Hp)
+    net = Surrogate(scfg, max_batch=1, split=split)
+    theta = workloads.nop_init(param_shapes(scfg), seed=0, gain=1.5).astype(np.float32)
+    net.set_params(theta)
+    p0s, c0s = workloads.nop_inputs(1, n=scfg.H, index_offset=3 * 10 ** 6)
+    tgt = np.random.default_rng(10).standard_normal((1, scfg.H, scfg.W)).astype(np.float32)
+    print("surrogate full configuration split", split, flush=True)
+    _check_parity(net, ocfg, theta, p0s.astype(np.float32), c0s.astype(np.float32), tgt, split)
     net.close()
 
 
