@@ -57,10 +57,10 @@ WORKLOADS = {
 SOURCES = {
     "pstd1d": ("common.h", "capi.hip", "kernels_misc.hip"),
     "pstd2d": ("common.h", "capi.hip", "kernels_phase2d.hip"),
-    "pstd3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
+    "pstd3d": ("common.h", "capi.hip", "tables.cpp", "structure.cpp", "kernels_split.hip"),
     "pstd2d_large": ("common.h", "capi.hip", "fft_plan.cpp", "kernels_fft.hip"),
     "periodic2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
-    "resample3d": ("common.h", "capi.hip", "tables.cpp", "kernels_split.hip"),
+    "resample3d": ("common.h", "capi.hip", "tables.cpp", "structure.cpp", "kernels_split.hip"),
     "halfwall2d": ("common.h", "capi.hip", "tables.cpp", "kernels_phase2d.hip"),
     "batched": ("common.h", "capi_batch.hip", "kernels_batch2d.hip"),
     "faces": ("common.h", "capi.hip", "capi_batch.hip", "kernels_batch2d.hip", "kernels_misc.hip"),

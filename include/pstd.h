@@ -128,8 +128,15 @@ int pstd_step_prepare(pstd_plan plan, const pstd_state* state, int64_t n_steps);
  *             axis and half step; other axes stay dense.
  *   AUTO:     FUSED where it applies; otherwise FFT on axes above 512 nodes (1D plans: above 1365) and
  *             dense contractions elsewhere.
+ *   STORED:   PER_AXIS, with every split-bf16 contraction reading its operator's entries from memory.
+ *             Under the other paths a SPLIT_BF16 contraction whose operator has between 193 and 384
+ *             rows and at most 512 columns forms its operator slices on the chip from the operator's
+ *             Toeplitz and Hankel parts (pstd_axis_operator_structure), which reads two vectors
+ *             instead of the matrix.
  * All compute the same step and replay captured HIP graphs; the choice changes speed and rounding only. */
-typedef enum { PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2, PSTD_PATH_FFT = 3 } pstd_path;
+typedef enum {
+  PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2, PSTD_PATH_FFT = 3, PSTD_PATH_STORED = 4
+} pstd_path;
 
 /* Select the execution path of later pstd_step calls (builds dense operators on first use when an axis
  * moves off the FFT path).  PSTD_E_UNSUPPORTED if the plan cannot use it. */
@@ -187,6 +194,22 @@ int pstd_plan_get_operator(pstd_plan plan, int32_t axis, int32_t which, double* 
  * pair (both PSTD_PERIODIC) gives the n x n operators of Eq. (fourier_pstd_solution), a half-step right
  * wall the n x n operators of its DTT types V-VIII.  out must hold the matrix.  Synchronous. */
 int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* out);
+
+/* Toeplitz-plus-Hankel form of the same operator (host only, no GPU needed).  Each operator is a forward
+ * trig transform, a diagonal and an inverse one (§3.2, Eq. (dtt_pstd_solution_a)/(dtt_pstd_solution_b));
+ * products of the two transforms' cosines and sines are trig functions of the difference and of the sum
+ * of the output and input indices, so with R x C the operator's shape
+ *     A[r][c] = wr[r] * wc[c] * (f[r - c + C - 1] + g[r + c]),
+ * where f and g hold R + C - 1 values each (caller-owned) and the weights are one except
+ * w[0] = wr[0], w[1] = wr[R-1], w[2] = wc[0], w[3] = wc[C-1] (a wall node counted once in the
+ * symmetric extension, or held at zero).  f and g are determined up to one constant per parity of
+ * r + c, chosen to minimise the sum of their squares.  *resid (nullable) receives the largest entry
+ * error relative to max|A|.  PSTD_E_UNSUPPORTED if the operator has no such form (then only
+ * *resid is written), PSTD_E_INVALID_ARG as pstd_axis_operator.  (Tolerance 1e-9, far below FP32
+ * rounding; a boundary line below 1e-12 max|A| counts as zero.)  The split-bf16 contractions use the form
+ * to build their operator slices on the chip (see pstd_plan_set_path). */
+int pstd_axis_operator_structure(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which,
+                                 double* f, double* g, double* w, double* resid);
 
 /* Collocated differentiation (§3.3) and half-step interpolation (§3.4) of a wall-bounded axis: which
  *   2 = PSTD_OP_GRAD_NODES   d/dx on the n nodes (n x n): forward T1, times a1 k, inverse of the

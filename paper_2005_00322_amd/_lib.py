@@ -81,6 +81,9 @@ SIGNATURES = {
     "pstd_plan_get_operator": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "pstd_axis_operator": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                      C.POINTER(C.c_double)]),
+    "pstd_axis_operator_structure": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                               C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pstd_apply_axis_operator": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "pstd_plan_numel": (C.c_int64, [C.c_void_p, C.c_int32]),
     "pstd_plan_destroy": (C.c_int, [C.c_void_p]),

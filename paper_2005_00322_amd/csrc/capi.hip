@@ -89,6 +89,25 @@ int upload_operator(pstd_plan_s* P, const std::vector<double>& m, int M, int K, 
     }
   if (hipMalloc(&op->data, 2 * cnt * 2) != hipSuccess) return fail(PSTD_E_OOM, "hipMalloc of an operator failed");
   PSTD_HIP(hipMemcpy(op->data, host.data(), 2 * cnt * 2, hipMemcpyHostToDevice));
+  // operators the contraction forms on the chip from f and g: windows Fr[i] = f(kThRowsMax - 1 - i) and
+  // G[i] = g(i), i < th_len, zero past the operator
+  std::vector<double> f, g;
+  double w[4], resid = 0.0;
+  if (M > kThRowsMin && M <= kThRowsMax && op->Kp <= kThColsMax &&
+      toeplitz_hankel(m.data(), M, K, kThTol, &f, &g, w, &resid)) {
+    const int len = kThRowsMax + op->Kp + 8;
+    std::vector<float> win(2 * static_cast<size_t>(len), 0.f);
+    for (int i = 0; i < len; ++i) {
+      const int d = kThRowsMax - 1 - i;
+      if (d >= 1 - K && d <= M - 1) win[i] = static_cast<float>(scale * f[d + K - 1]);
+      if (i <= M + K - 2) win[len + i] = static_cast<float>(scale * g[i]);
+    }
+    if (hipMalloc(&op->th, win.size() * sizeof(float)) != hipSuccess)
+      return fail(PSTD_E_OOM, "hipMalloc of an operator failed");
+    PSTD_HIP(hipMemcpy(op->th, win.data(), win.size() * sizeof(float), hipMemcpyHostToDevice));
+    op->th_len = len;
+    for (int i = 0; i < 4; ++i) op->thw[i] = static_cast<float>(w[i]);
+  }
   return PSTD_OK;
 }
 
@@ -105,12 +124,15 @@ void free_plan(pstd_plan_s* P) {
   for (int a = 0; a < 3; ++a) {
     if (P->G[a].data) (void)hipFree(P->G[a].data);
     if (P->G[a].dataT) (void)hipFree(P->G[a].dataT);
+    if (P->G[a].th) (void)hipFree(P->G[a].th);
     if (P->D[a].data) (void)hipFree(P->D[a].data);
     if (P->D[a].dataT) (void)hipFree(P->D[a].dataT);
+    if (P->D[a].th) (void)hipFree(P->D[a].th);
     fft_axis_free(&P->fft[a]);
     for (int k = 0; k < 4; ++k) {
       if (P->R[a][k].data) (void)hipFree(P->R[a][k].data);
       if (P->R[a][k].dataT) (void)hipFree(P->R[a][k].dataT);
+      if (P->R[a][k].th) (void)hipFree(P->R[a][k].th);
     }
   }
   if (P->c2map) (void)hipFree(P->c2map);
@@ -203,9 +225,16 @@ hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const vo
     c.x_bstride = static_cast<int64_t>(op.K) * inner;
     c.y_bstride = static_cast<int64_t>(op.M) * inner;
   }
+  c.th = nullptr;
+  c.th_len = 0;
   if (P->prec == PSTD_FP64) return launch_contract_fp64(c, contiguous, s);
   if (P->prec == PSTD_FP32) return launch_contract_fp32(c, contiguous, s);
   c.A_lo = static_cast<const uint16_t*>(op.data) + static_cast<size_t>(op.Mp) * op.Kp;
+  if (op.th && P->use_th) {
+    c.th = op.th;
+    c.th_len = op.th_len;
+    for (int i = 0; i < 4; ++i) c.thw[i] = op.thw[i];
+  }
   return launch_contract_split(c, contiguous, s);
 }
 
@@ -549,7 +578,7 @@ int pstd_step_prepare(pstd_plan P, const pstd_state* st, int64_t n_steps) {
 
 int pstd_plan_set_path(pstd_plan P, int32_t path) {
   if (!P) return fail(PSTD_E_INVALID_ARG, "null plan");
-  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_FFT) return fail(PSTD_E_INVALID_ARG, "bad path");
+  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_STORED) return fail(PSTD_E_INVALID_ARG, "bad path");
   if (path == PSTD_PATH_FFT) {
     bool any = false;
     for (int a = 0; a < P->ndim; ++a) any = any || P->fft[a].ok;
@@ -566,6 +595,7 @@ int pstd_plan_set_path(pstd_plan P, int32_t path) {
     P->path = old;
     return pst;
   }
+  P->use_th = path != PSTD_PATH_STORED;
   drop_graphs(P);  // captured graphs may belong to the other path
   return PSTD_OK;
 }
@@ -690,6 +720,38 @@ int pstd_axis_operator(int64_t n, int32_t bc_left, int32_t bc_right, double dx, 
   const AxisTables& t = axis_tables(static_cast<int>(n), axis_case(bc_left, bc_right));
   const std::vector<double>& m = which == 0 ? t.G : t.D;
   for (size_t i = 0; i < m.size(); ++i) out[i] = m[i] / dx;
+  return PSTD_OK;
+}
+
+int pstd_axis_operator_structure(int64_t n, int32_t bc_left, int32_t bc_right, double dx, int32_t which, double* f,
+                                 double* g, double* w, double* resid) {
+  if (!f || !g || !w) return fail(PSTD_E_INVALID_ARG, "null output");
+  if (n < 3 || n > 4097) return fail(PSTD_E_INVALID_ARG, "n must be in [3, 4097]");
+  const bool per = bc_left == PSTD_PERIODIC && bc_right == PSTD_PERIODIC;
+  const int m = (per || half_wall(bc_right)) ? static_cast<int>(n) : static_cast<int>(n) - 1;
+  int rows = 0, cols = 0;
+  switch (which) {
+    case 0: rows = m; cols = static_cast<int>(n); break;
+    case 1: rows = static_cast<int>(n); cols = m; break;
+    case 2: rows = cols = static_cast<int>(n); break;
+    case 3: rows = cols = m; break;
+    case 4: rows = m; cols = static_cast<int>(n); break;
+    case 5: rows = static_cast<int>(n); cols = m; break;
+    default: return fail(PSTD_E_INVALID_ARG, "bad which");
+  }
+  std::vector<double> A(static_cast<size_t>(rows) * cols);
+  const int st = pstd_axis_operator(n, bc_left, bc_right, dx, which, A.data());
+  if (st != PSTD_OK) return st;
+  std::vector<double> fv, gv;
+  double wv[4], r = 0.0;
+  const bool ok = toeplitz_hankel(A.data(), rows, cols, kThTol, &fv, &gv, wv, &r);
+  if (resid) *resid = r;
+  if (!ok) return fail(PSTD_E_UNSUPPORTED, "operator has no Toeplitz-plus-Hankel form (residual %g)", r);
+  for (size_t i = 0; i < fv.size(); ++i) {
+    f[i] = fv[i];
+    g[i] = gv[i];
+  }
+  for (int i = 0; i < 4; ++i) w[i] = wv[i];
   return PSTD_OK;
 }
 

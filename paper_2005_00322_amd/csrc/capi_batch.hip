@@ -297,7 +297,7 @@ bool read_cache(const char* path, const std::string& sig, int* blocks, int* orde
   const char* po = strstr(buf, "\"order\"");
   const char* pt = strstr(buf, "\"tile\"");
   if (!pb || !po || !pt || sscanf(pb, "\"blocks\": %d", &b) != 1 || sscanf(po, "\"order\": %d", &o) != 1 ||
-      sscanf(pt, "\"tile\": %d", &t) != 1 || (t != 32 && t != 64))
+      sscanf(pt, "\"tile\": %d", &t) != 1 || b < 0 || o < 0 || o > 1 || (t != 16 && t != 32 && t != 64))
     return false;
   if (sig != s) return false;
   *blocks = b;
@@ -532,7 +532,8 @@ int pstd_batch_autotune(pstd_batch B, int32_t trial_steps, const char* cache_pat
   if (!B || trial_steps < 1) return fail(PSTD_E_INVALID_ARG, "bad batch or trial_steps");
   const std::string sig = signature(B);
   int cb = 0, co = 0, ct = 32;
-  if (cache_path && read_cache(cache_path, sig, &cb, &co, &ct)) {
+  // a cached tile-16 entry is reused only where the fused phase launches apply (one shape of at most 512^2)
+  if (cache_path && read_cache(cache_path, sig, &cb, &co, &ct) && (ct != 16 || phase_eligible(B))) {
     B->blocks = cb;
     B->order = co;
     B->tile = ct;

@@ -89,7 +89,26 @@ struct DevOperator {
   int Mp = 0, Kp = 0;      // padded size (row stride = Kp)
   void* data = nullptr;    // FP64: double[Mp*Kp]; FP32: float[Mp*Kp]; SPLIT: bf16 hi[Mp*Kp] then lo[Mp*Kp]
   void* dataT = nullptr;   // 1D plans: transposed copy, Kp x Mp (row stride Mp)
+  // SPLIT only, operators with a Toeplitz-plus-Hankel form and kThRowsMin < M <= kThRowsMax, Kp <= kThColsMax:
+  // FP32 f and g windows of th_len values each (see kernels_split.hip) and the end weights
+  // {first row, last row, first column, last column}
+  float* th = nullptr;
+  int th_len = 0;
+  float thw[4] = {1.f, 1.f, 1.f, 1.f};
 };
+
+// Operators whose slices the split-bf16 contraction forms from their Toeplitz and Hankel parts.
+constexpr int kThRowsMin = 192, kThRowsMax = 384, kThColsMax = 512;
+constexpr int kThLen = kThRowsMax + kThColsMax + 8;   // upper bound of th_len
+// Largest entry error of the form, relative to max|A|: far below FP32 rounding, so the slices formed on
+// the chip equal the stored operator to the rounding of their FP32 sum.
+constexpr double kThTol = 1e-9;
+
+// A (R x C, row-major, FP64) = diag(wr) (F + H) diag(wc) with F[r][c] = f[r - c + C - 1],
+// H[r][c] = g[r + c] (f and g of R + C - 1 values), wr and wc one except w = {wr[0], wr[R-1], wc[0],
+// wc[C-1]}, to tol * max|A|; false (outputs untouched except resid) when A has no such form.
+bool toeplitz_hankel(const double* A, int R, int C, double tol, std::vector<double>* f, std::vector<double>* g,
+                     double w[4], double* resid);
 
 struct ContractArgs {
   const void* A;        // operator, row-major, row stride lda, zero padded
@@ -105,6 +124,9 @@ struct ContractArgs {
   float alpha, beta;    // Y = beta*Y + alpha * scale * (A X)
   double alpha_d, beta_d;
   const void* scale;    // optional per-point factor with Y's layout (c0(x)^2 map, state dtype), may be null
+  const float* th;      // SPLIT_BF16: Toeplitz/Hankel windows of the operator (null: read A and A_lo)
+  int th_len;
+  float thw[4];
 };
 
 // Launchers (kernels_*.hip).  contiguous = the contracted axis is the last (unit-stride) one.
@@ -288,6 +310,7 @@ struct pstd_plan_s {
   void* c2map = nullptr;       // c0(x)^2 in the state dtype (owned), null for a homogeneous medium
   int* flag = nullptr;         // device int for reductions (owned)
   int path = 0;                // PSTD_PATH_* (0 = automatic)
+  bool use_th = true;          // split-bf16 contractions form Toeplitz-plus-Hankel operators on the chip
   // captured step graphs: slot 0 holds a full chunk of steps, slot 1 the last other length used
   struct StepGraph {
     hipGraphExec_t exec = nullptr;

@@ -60,6 +60,24 @@ def axis_operator(n: int, bc_left: int, bc_right: int, dx: float, which: int) ->
     return out
 
 
+def axis_operator_structure(n: int, bc_left: int, bc_right: int, dx: float, which: int):
+    """Toeplitz-plus-Hankel form of axis_operator(...) as the library finds it (host only):
+    (f, g, w, residual) with A[r][c] = wr[r] wc[c] (f[r - c + C - 1] + g[r + c]), w = (wr[0], wr[-1],
+    wc[0], wc[-1]) and every other weight one.  Raises if the operator has no such form."""
+    lib = load()
+    m = n if (int(bc_left) == PERIODIC or int(bc_right) in (NEUMANN_HALF, DIRICHLET_HALF)) else n - 1
+    rows, cols = operator_shape(n, m, which) if which in range(6) else (1, 1)
+    f = np.zeros(rows + cols - 1)
+    g = np.zeros(rows + cols - 1)
+    w = np.zeros(4)
+    r = C.c_double(0.0)
+    P = C.POINTER(C.c_double)
+    check(lib.pstd_axis_operator_structure(int(n), int(bc_left), int(bc_right), float(dx), int(which),
+                                           f.ctypes.data_as(P), g.ctypes.data_as(P), w.ctypes.data_as(P),
+                                           C.byref(r)), "pstd_axis_operator_structure")
+    return f, g, w, r.value
+
+
 @dataclass
 class State:
     """Device state (torch tensors): p and one velocity field per axis."""
@@ -164,11 +182,13 @@ class Plan:
         cs = st._c()
         check(load().pstd_step_prepare(self._h, C.byref(cs), int(n_steps)), "pstd_step_prepare")
 
-    PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3}
+    PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3, "stored": 4}
 
     def set_path(self, path: str) -> None:
         """Execution path of later steps: "auto", "per_axis" (dense contractions), "fused" (2D FP32: two
-        kernels per step) or "fft" (LDS-resident FFTs on every axis whose 2(n-1) is 16 x 2^a 3^b 5^c)."""
+        kernels per step), "fft" (LDS-resident FFTs on every axis whose 2(n-1) is 16 x 2^a 3^b 5^c) or
+        "stored" (per_axis with split-bf16 operators read from memory rather than formed from their
+        Toeplitz and Hankel parts)."""
         check(load().pstd_plan_set_path(self._h, self.PATHS[path]), "pstd_plan_set_path")
 
     def apply_axis(self, st: State, axis: int, which: int) -> None:

@@ -118,6 +118,32 @@ def test_batch_autotune_cache(tmp_path):
         assert np.array_equal(x, y)
 
 
+def test_batch_autotune_cache_keeps_tile(tmp_path):
+    """A cached tile-16 (fused phase launch) choice is reused for a one-shape batch; an entry edited to tile
+    16 for a batch of mixed shapes is ignored and the trials run again."""
+    import json
+    from paper_2005_00322_amd import Batch
+    rng = np.random.default_rng(8)
+    same = [{"shape": (64, 48), "bcs": ((int(a), int(b)), (int(c), int(d))), "dx": 1e-4, "dt": 0.3e-4 / 1500,
+             "c0": 1500.0} for a, b, c, d in rng.integers(0, 2, size=(8, 4))]
+    cache = os.path.join(str(tmp_path), "same.json")
+    with Batch(same) as b:
+        cfg = b.autotune(trial_steps=3, cache_path=cache)
+        cfg2 = b.autotune(trial_steps=3, cache_path=cache)
+    assert not cfg["from_cache"] and cfg2["from_cache"]
+    assert (cfg2["blocks"], cfg2["order"], cfg2["tile"]) == (cfg["blocks"], cfg["order"], cfg["tile"])
+    mixed, _ = _random_solves(9, 4, 30, 90)
+    cache = os.path.join(str(tmp_path), "mixed.json")
+    with Batch(mixed) as b:
+        first = b.autotune(trial_steps=3, cache_path=cache)
+        assert first["tile"] in (32, 64)
+        entry = json.load(open(cache))
+        entry["tile"] = 16
+        json.dump(entry, open(cache, "w"))
+        again = b.autotune(trial_steps=3, cache_path=cache)
+    assert not again["from_cache"] and again["tile"] in (32, 64)
+
+
 def test_batched_workload_full():
     """The 128-instance workload (paired all-Neumann / all-Dirichlet solves, sides 96..512, 1000 steps)
     against the oracle's closed form for every solve, and the combination for every instance."""
