@@ -109,29 +109,39 @@ struct Stager {
   }
 };
 
-// FP32 MFMA per slice, summed into FP64: TILE 32 = four waves of 16 x 16 (v_mfma_f32_16x16x4f32, four
-// chains); TILE 64 = four waves of 32 x 32 (v_mfma_f32_32x32x2f32, two chains).
+// FP32 MFMA per slice into FP32 partial sums, which flush() adds into the FP64 accumulators every
+// kFlush slices (64 terms of k): TILE 32 = four waves of 16 x 16 (v_mfma_f32_16x16x4f32, four chains);
+// TILE 64 = four waves of 32 x 32 (v_mfma_f32_32x32x2f32, two chains).
+constexpr int kFlush = 2;
 template <int TILE>
 struct Acc;
 template <>
 struct Acc<32> {
   static constexpr int R = 4;
-  __device__ static void slice(const float* Pl, const float* Ql, double (&accd)[R]) {
+  struct Part {
+    f32x4 c0, c1, c2, c3;
+  };
+  __device__ static void zero(Part& p) {
+    p.c0 = p.c1 = p.c2 = p.c3 = f32x4{0, 0, 0, 0};
+  }
+  __device__ static void slice(const float* Pl, const float* Ql, Part& p) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
     const float* Pp = Pl + ((wave & 1) * 16 + (lane & 15)) * LDB + kl;
     const float* Qp = Ql + ((wave >> 1) * 16 + (lane & 15)) * LDB + kl;
-    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, c2 = {0, 0, 0, 0}, c3 = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < BK; k += 16) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k], Qp[k], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 4], Qp[k + 4], c1, 0, 0, 0);
-      c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 8], Qp[k + 8], c2, 0, 0, 0);
-      c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 12], Qp[k + 12], c3, 0, 0, 0);
+      p.c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k], Qp[k], p.c0, 0, 0, 0);
+      p.c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 4], Qp[k + 4], p.c1, 0, 0, 0);
+      p.c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 8], Qp[k + 8], p.c2, 0, 0, 0);
+      p.c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Pp[k + 12], Qp[k + 12], p.c3, 0, 0, 0);
     }
+  }
+  __device__ static void flush(Part& p, double (&accd)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      accd[r] += (static_cast<double>(c0[r]) + static_cast<double>(c1[r])) +
-                 (static_cast<double>(c2[r]) + static_cast<double>(c3[r]));
+      accd[r] += (static_cast<double>(p.c0[r]) + static_cast<double>(p.c1[r])) +
+                 (static_cast<double>(p.c2[r]) + static_cast<double>(p.c3[r]));
+    zero(p);
   }
   // tile-local output coordinates of register r (lane l receives C[4 (l/16) + r][l%16])
   __device__ static int row(int r) { return ((threadIdx.x >> 6) & 1) * 16 + 4 * ((threadIdx.x & 63) >> 4) + r; }
@@ -140,21 +150,28 @@ struct Acc<32> {
 template <>
 struct Acc<64> {
   static constexpr int R = 16;
-  __device__ static void slice(const float* Pl, const float* Ql, double (&accd)[R]) {
+  struct Part {
+    f32x16 c0, c1;
+  };
+  __device__ static void zero(Part& p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) p.c0[r] = p.c1[r] = 0.f;
+  }
+  __device__ static void slice(const float* Pl, const float* Ql, Part& p) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 5;
     // lane l supplies P[l%32][k + l/32] and Q[l%32][k + l/32]
     const float* Pp = Pl + ((wave & 1) * 32 + (lane & 31)) * LDB + kl;
     const float* Qp = Ql + ((wave >> 1) * 32 + (lane & 31)) * LDB + kl;
-    f32x16 c0, c1;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) c0[r] = c1[r] = 0.f;
 #pragma unroll
     for (int k = 0; k < BK; k += 4) {
-      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k], Qp[k], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k + 2], Qp[k + 2], c1, 0, 0, 0);
+      p.c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k], Qp[k], p.c0, 0, 0, 0);
+      p.c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Pp[k + 2], Qp[k + 2], p.c1, 0, 0, 0);
     }
+  }
+  __device__ static void flush(Part& p, double (&accd)[R]) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) accd[r] += static_cast<double>(c0[r]) + static_cast<double>(c1[r]);
+    for (int r = 0; r < R; ++r) accd[r] += static_cast<double>(p.c0[r]) + static_cast<double>(p.c1[r]);
+    zero(p);
   }
   // lane l receives C[8 (r/4) + 4 (l/32) + r%4][l%32]
   __device__ static int row(int r) {
@@ -173,6 +190,9 @@ template <int TILE, int PK, int QK>
 __device__ __forceinline__ void tile_contract(const Stager<TILE, PK>& P, const Stager<TILE, QK>& Q, int K, float* lds,
                                               double (&accd)[Acc<TILE>::R]) {
   constexpr int V = TILE / 8, D = 4;
+  static_assert(D % kFlush == 0, "the partial sums are flushed within each unrolled group");
+  typename Acc<TILE>::Part part;
+  Acc<TILE>::zero(part);
   float* Pl[2] = {lds, lds + 2 * TILE * LDB};
   float* Ql[2] = {lds + TILE * LDB, lds + 3 * TILE * LDB};
   const int nsl = (K + BK - 1) / BK;
@@ -193,7 +213,8 @@ __device__ __forceinline__ void tile_contract(const Stager<TILE, PK>& P, const S
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const int t = s0 + i;   // wave-uniform
-      if (t < nsl) Acc<TILE>::slice(Pl[i & 1], Ql[i & 1], accd);
+      if (t < nsl) Acc<TILE>::slice(Pl[i & 1], Ql[i & 1], part);
+      if (i % kFlush == kFlush - 1) Acc<TILE>::flush(part, accd);
       P.store(Pl[(i + 1) & 1], rp[(i + 1) % D]);
       Q.store(Ql[(i + 1) & 1], rq[(i + 1) % D]);
       P.load((t + D) * BK, rp[i]);
@@ -276,7 +297,7 @@ __device__ void grid_barrier(unsigned* arrivals, unsigned* timeout) {
 }
 
 template <int TILE>
-__global__ __launch_bounds__(NT) void batch2d_kernel(BatchArgs a) {
+__global__ __launch_bounds__(NT, 2) void batch2d_kernel(BatchArgs a) {
   __shared__ float lds[4 * TILE * LDB];
   const int home = blockIdx.x % kBatchQueues;
   for (int64_t s = 0; s < a.steps; ++s) {
