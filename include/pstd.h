@@ -128,6 +128,9 @@ int pstd_step_prepare(pstd_plan plan, const pstd_state* state, int64_t n_steps);
  *             axis and half step; other axes stay dense.
  *   AUTO:     FUSED where it applies; otherwise FFT on axes above 512 nodes (1D plans: above 1365) and
  *             dense contractions elsewhere.
+ *   FFT_GENERIC: FFT, with every axis on the mixed-radix kernel.  Under the other paths an FP32 axis
+ *             whose 2(n-1) is a power of two from 256 to 8192 runs a kernel specialised to that length
+ *             (radix-16 passes, twiddles and spectral multipliers from tables formed in FP64).
  *   STORED:   PER_AXIS, with every split-bf16 contraction reading its operator's entries from memory.
  *             Under the other paths a SPLIT_BF16 contraction whose operator has between 193 and 384
  *             rows and at most 512 columns forms its operator slices on the chip from the operator's
@@ -135,7 +138,8 @@ int pstd_step_prepare(pstd_plan plan, const pstd_state* state, int64_t n_steps);
  *             instead of the matrix.
  * All compute the same step and replay captured HIP graphs; the choice changes speed and rounding only. */
 typedef enum {
-  PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2, PSTD_PATH_FFT = 3, PSTD_PATH_STORED = 4
+  PSTD_PATH_AUTO = 0, PSTD_PATH_PER_AXIS = 1, PSTD_PATH_FUSED = 2, PSTD_PATH_FFT = 3, PSTD_PATH_STORED = 4,
+  PSTD_PATH_FFT_GENERIC = 5
 } pstd_path;
 
 /* Select the execution path of later pstd_step calls (builds dense operators on first use when an axis

@@ -180,7 +180,7 @@ int ensure_dense(pstd_plan_s* P, int a) {
 // nodes (1D plans keep the single-workgroup kernel up to 1365 nodes).
 bool axis_fft(const pstd_plan_s* P, int a) {
   if (!P->fft[a].ok) return false;
-  if (P->path == PSTD_PATH_FFT) return true;
+  if (P->path == PSTD_PATH_FFT || P->path == PSTD_PATH_FFT_GENERIC) return true;
   if (P->path != PSTD_PATH_AUTO) return false;
   if (P->ndim == 1) return P->n[0] > 1365;
   return P->n[a] > 512;
@@ -269,11 +269,20 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
   const int64_t lines = x.contig ? outer : outer * inner;
   // transforms per block: enough blocks to fill the chip first (about 1024), then as many lines per
   // block as 64 KB of LDS holds; at least 64 threads (F L / 16) where that allows
-  const int fmax = fft_max_per_block(P->prec == PSTD_FP64, f.L);
-  int F = static_cast<int>(std::min<int64_t>(fmax, std::max<int64_t>(1, lines / 2048)));
-  F = std::max(F, std::min(fmax, std::max(1, 1024 / f.L)));
-  F = static_cast<int>(std::min<int64_t>(F, (lines + 1) / 2));
-  F = std::max(F, 1);
+  const bool pow2 = f.tw != nullptr && P->fft_pow2;
+  int F;
+  if (pow2) {
+    F = fft_pow2_lines(f.L) / 2;   // fixed by the kernel
+    x.tw = f.tw;
+    x.h = f.hb;
+    x.pre = f.pre;
+  } else {
+    const int fmax = fft_max_per_block(P->prec == PSTD_FP64, f.L);
+    F = static_cast<int>(std::min<int64_t>(fmax, std::max<int64_t>(1, lines / 2048)));
+    F = std::max(F, std::min(fmax, std::max(1, 1024 / f.L)));
+    F = static_cast<int>(std::min<int64_t>(F, (lines + 1) / 2));
+    F = std::max(F, 1);
+  }
   x.F = F;
   const int W = 2 * F;
   if (x.contig) {
@@ -289,7 +298,7 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
     x.y_bstride = static_cast<int64_t>(x.nout) * inner;
   }
   x.xcd_spread = x.groups >= 64;
-  return launch_fft_axis(P->prec == PSTD_FP64, x, s);
+  return pow2 ? launch_fft_pow2(x, s) : launch_fft_axis(P->prec == PSTD_FP64, x, s);
 }
 
 bool use_fused2d(const pstd_plan_s* P) {
@@ -578,8 +587,8 @@ int pstd_step_prepare(pstd_plan P, const pstd_state* st, int64_t n_steps) {
 
 int pstd_plan_set_path(pstd_plan P, int32_t path) {
   if (!P) return fail(PSTD_E_INVALID_ARG, "null plan");
-  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_STORED) return fail(PSTD_E_INVALID_ARG, "bad path");
-  if (path == PSTD_PATH_FFT) {
+  if (path < PSTD_PATH_AUTO || path > PSTD_PATH_FFT_GENERIC) return fail(PSTD_E_INVALID_ARG, "bad path");
+  if (path == PSTD_PATH_FFT || path == PSTD_PATH_FFT_GENERIC) {
     bool any = false;
     for (int a = 0; a < P->ndim; ++a) any = any || P->fft[a].ok;
     if (!any) return fail(PSTD_E_UNSUPPORTED, "no axis has 2(n-1) = 16 x 2^a 3^b 5^c within the FFT capacity");
@@ -596,6 +605,7 @@ int pstd_plan_set_path(pstd_plan P, int32_t path) {
     return pst;
   }
   P->use_th = path != PSTD_PATH_STORED;
+  P->fft_pow2 = path != PSTD_PATH_FFT_GENERIC;
   drop_graphs(P);  // captured graphs may belong to the other path
   return PSTD_OK;
 }

@@ -200,6 +200,10 @@ struct FftAxis {
   int sL = 1, sR = 1;           // +1 Neumann wall, -1 Dirichlet wall
   void* tab = nullptr;          // 64 + L/16 entries: w^l (l < 64) then w^{64 h}, w = e^{-2 pi i / 4L}
   double kfac[2] = {0, 0};      // pi c / (N L) with c the velocity (0) or pressure (1) constant
+  // FP32 plans with L = 2^m, 256 <= L <= 8192 (fft_pow2_kernel): complex FP32 tables
+  void* tw = nullptr;           // w, w^2, w^4, w^8 of each Stockham pass after the first, per j mod Ns
+  void* hb = nullptr;           // e^{i pi (2t + a) / (2L)}, t < L/16 (a = 1 for mixed walls)
+  void* pre = nullptr;          // e^{-i pi t / L}, t < L/16 (mixed walls)
 };
 
 struct FftArgs {
@@ -207,6 +211,9 @@ struct FftArgs {
   void* Y;                      // output field (read-modify-write)
   const void* scale;            // optional per-point factor with Y's layout, may be null
   const void* tab;              // root table (FftAxis::tab)
+  const void* tw;               // fft_pow2_kernel: FftAxis::tw, FftAxis::hb, FftAxis::pre
+  const void* h;
+  const void* pre;
   double kfac;                  // FftAxis::kfac of this direction
   double alpha, beta;           // Y = beta Y + alpha scale (op X)
   int N, L;
@@ -232,6 +239,10 @@ int fft_max_per_block(bool dbl, int L);   // transforms per block that keep a bl
 bool fft_axis_possible(int n, int prec);
 void fft_axis_free(FftAxis* f);
 hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s);
+// FP32 power-of-two lengths 256 <= L <= 8192: lines per block of fft_pow2_kernel (0: not supported), and
+// its launch (F = lines / 2 transforms per block, tables tw, h, pre set)
+int fft_pow2_lines(int L);
+hipError_t launch_fft_pow2(const FftArgs& a, hipStream_t s);
 
 // ---- neural-operator surrogate (kernels_nop.hip, capi_nop.hip) ----------------------------------------
 // C[z] = alpha A[z] B[z] (+ beta C[z]) (+ bias_m[m]) (+ D[z]) (* GELU'(dgelu[z])), then with act set
@@ -311,6 +322,7 @@ struct pstd_plan_s {
   int* flag = nullptr;         // device int for reductions (owned)
   int path = 0;                // PSTD_PATH_* (0 = automatic)
   bool use_th = true;          // split-bf16 contractions form Toeplitz-plus-Hankel operators on the chip
+  bool fft_pow2 = true;        // FP32 power-of-two FFT axes use fft_pow2_kernel
   // captured step graphs: slot 0 holds a full chunk of steps, slot 1 the last other length used
   struct StepGraph {
     hipGraphExec_t exec = nullptr;

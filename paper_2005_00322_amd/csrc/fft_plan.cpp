@@ -75,14 +75,42 @@ int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   f.kfac[0] = pi * sG / (static_cast<double>(N) * L);
   f.kfac[1] = pi * sD / (static_cast<double>(N) * L);
   const bool dbl = P->prec == PSTD_FP64;
-  const int st = dbl ? upload_complex<double>(tab, &f.tab) : upload_complex<float>(tab, &f.tab);
+  int st = dbl ? upload_complex<double>(tab, &f.tab) : upload_complex<float>(tab, &f.tab);
   if (st != PSTD_OK) return st;
+  if (P->prec == PSTD_FP32 && fft_pow2_lines(L) > 0) {
+    // fft_pow2_kernel: radix-16 passes, then one pass of the remaining factor 2, 4 or 8.  Per pass after
+    // the first, w, w^2, w^4, w^8 for w = e^{-2 pi i (j mod Ns) / (Ns R)}; per thread t < L/16 of a
+    // transform, e^{i pi (2t + a) / (2L)} (a = 1 for mixed walls: the multiplier's phase, whose other
+    // factors the kernel forms) and e^{-i pi t / L} (the mixed-wall pre-twiddle's)
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    const int np = (lg + 3) / 4, rl = 1 << (lg - 4 * (np - 1)), q = L / 16;
+    std::vector<std::complex<double>> tw;
+    for (int p = 1, ns = 16; p < np; ++p, ns *= 16) {
+      const int R = p < np - 1 ? 16 : rl;
+      for (int jm = 0; jm < ns; ++jm)
+        for (int e = 1; e <= 8; e *= 2) tw.push_back(std::polar(1.0, -2.0 * pi * jm * e / (static_cast<double>(ns) * R)));
+    }
+    st = upload_complex<float>(tw, &f.tw);
+    const int anti = f.sL * f.sR < 0 ? 1 : 0;
+    std::vector<std::complex<double>> hb(q), pre(q);
+    for (int t = 0; t < q; ++t) {
+      hb[t] = std::polar(1.0, pi * (2.0 * t + anti) / (2.0 * L));
+      pre[t] = std::polar(1.0, -pi * t / L);
+    }
+    if (st == PSTD_OK) st = upload_complex<float>(hb, &f.hb);
+    if (st == PSTD_OK && anti) st = upload_complex<float>(pre, &f.pre);
+    if (st != PSTD_OK) return st;
+  }
   f.ok = true;
   return PSTD_OK;
 }
 
 void fft_axis_free(FftAxis* f) {
   if (f->tab) (void)hipFree(f->tab);
+  if (f->tw) (void)hipFree(f->tw);
+  if (f->hb) (void)hipFree(f->hb);
+  if (f->pre) (void)hipFree(f->pre);
   *f = FftAxis();
 }
 }  // namespace pstd

@@ -524,6 +524,379 @@ hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- FP32 transforms of a power-of-two length L = 2^LG, 256 <= L <= 8192 ----------------------------
+// The same operator as fft_axis_kernel with the length, the pass plan and the LDS layout fixed at compile
+// time, so that index arithmetic is shifts and most LDS accesses of a pass are one of a few base
+// registers plus an immediate offset:
+//   layout   entry e of a transform at sw(e) (the bank swizzle above), F = 4096 / L transforms per block:
+//            32 KB of LDS per block up to L = 4096, so five blocks fit a CU;
+//   passes   radix 16, then one radix 2, 4 or 8 pass for the remaining factor; thread t of a transform
+//            holds entries t + s L/16 (s < 16) at the start of the first pass and at the end of the last;
+//   tables   formed in FP64 on the host and rounded once: per pass after the first, w, w^2, w^4, w^8 for
+//            w = W_{Ns R}^{j mod Ns} (the other powers as products of at most three of them); per thread
+//            t < L/16, e^{i pi (2t + a)/(2L)} (a = 1 for mixed walls) for the spectral multiplier and
+//            e^{-i pi t/L} for the mixed-wall pre-twiddle.  The entries t + s L/16 add a factor
+//            e^{+-i pi s/16} (constants) to these;
+//   fusion   the extension (and pre-twiddle) is applied as the first pass reads the raw samples; the last
+//            forward pass leaves each thread exactly the entries its first inverse pass needs, so
+//            conj(H X) and that inverse pass follow in registers; the conjugation (and post-twiddle) is
+//            applied as the last inverse pass writes;
+//   memory   every thread issues all its loads of the input lines at once, and of the old output values
+//            at once, without branches.
+template <int LG>
+struct Pow2 {
+  static constexpr int L = 1 << LG, N = L / 2, Q = L / 16;
+  static constexpr int F = L <= 4096 ? 4096 / L : 1;   // transforms per block
+  static constexpr int NT = F * Q;                      // threads per block
+  static constexpr int NP = (LG + 3) / 4;               // passes
+  static constexpr int RL = 1 << (LG - 4 * (NP - 1));   // radix of the last pass
+  static constexpr int EPT = 17;                        // input / output elements per thread (2F lines)
+  static constexpr int radix(int p) { return p < NP - 1 ? 16 : RL; }
+  static constexpr int ns(int p) { return 1 << (4 * p); }
+  // offset of pass p's twiddles in the table (passes 1 .. NP-1, four entries per j mod Ns)
+  static constexpr int toff(int p) { return p <= 1 ? 0 : toff(p - 1) + 4 * ns(p - 1); }
+};
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// cos and sin of pi r / 16, r = 0..15
+constexpr float kC32[16] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f, 0.83146961230254523708f,
+                            0.70710678118654752440f, 0.55557023301960222474f, 0.38268343236508977173f,
+                            0.19509032201612826785f, 0.0f, -0.19509032201612826785f, -0.38268343236508977173f,
+                            -0.55557023301960222474f, -0.70710678118654752440f, -0.83146961230254523708f,
+                            -0.92387953251128675613f, -0.98078528040323044913f};
+constexpr float kS32[16] = {0.0f, 0.19509032201612826785f, 0.38268343236508977173f, 0.55557023301960222474f,
+                            0.70710678118654752440f, 0.83146961230254523708f, 0.92387953251128675613f,
+                            0.98078528040323044913f, 1.0f, 0.98078528040323044913f, 0.92387953251128675613f,
+                            0.83146961230254523708f, 0.70710678118654752440f, 0.55557023301960222474f,
+                            0.38268343236508977173f, 0.19509032201612826785f};
+
+// slot + sw(e + OFF) from A = slot + sw(e) (slot a multiple of 256) when e < OFF's lowest set bit and OFF
+// is a multiple of 32: OFF's bits 4..8 enter the XOR, its low five bits are zero (otherwise computed in
+// full; called with OFF a constant after unrolling)
+__device__ __forceinline__ int sw_add(int A, int e, int OFF) {
+  return OFF % 32 == 0 ? (A ^ ((OFF >> 4) & 31)) + OFF : A - sw(e) + sw(e + OFF);
+}
+
+// An opaque copy of a per-thread index: addresses derived from it are recomputed where they are used
+// instead of being kept live (or spilled) from one pass to another that uses the same ones.
+__device__ __forceinline__ int fresh(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// w, w^2, w^4, w^8 of pass P for butterfly j
+template <int LG, int P>
+__device__ __forceinline__ void tw_load(const f2v* __restrict__ tw, int j, f4v (&t)[2]) {
+  typedef Pow2<LG> C;
+  const f4v* p = reinterpret_cast<const f4v*>(tw + C::toff(P) + 4 * (j & (C::ns(P) - 1)));
+  t[0] = p[0];
+  t[1] = p[1];
+}
+
+// v[r] *= w^r, r = 1 .. R-1, from t = (w, w^2, w^4, w^8)
+template <int R>
+__device__ __forceinline__ void tw_apply(f2v* v, const f4v (&t)[2]) {
+  f2v w[16];
+  w[1] = f2v{t[0].x, t[0].y};
+  w[2] = f2v{t[0].z, t[0].w};
+  w[4] = f2v{t[1].x, t[1].y};
+  w[8] = f2v{t[1].z, t[1].w};
+#pragma unroll
+  for (int p = 3; p < R; ++p) {
+    if ((p & (p - 1)) == 0) continue;
+    const int hb = 1 << (31 - __builtin_clz(p));
+    w[p] = cmul(w[hb], w[p - hb]);
+  }
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+}
+
+// Stockham pass P (P >= 1) of the plan: read, twiddle, DFT; the outputs stay in v for the caller.
+template <int LG, int P>
+__device__ __forceinline__ void pow2_pass_in(const f2v* __restrict__ z, const f2v* __restrict__ tw, int jt, int A,
+                                             f2v (&v)[16]) {
+  typedef Pow2<LG> C;
+  constexpr int R = C::radix(P), NB = 16 / R, PER = C::L / R;
+  jt = fresh(jt);
+  A = fresh(A);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = z[sw_add(A, jt, (i / R) * C::Q + (i % R) * PER)];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    f4v t[2];
+    tw_load<LG, P>(tw, jt + b * C::Q, t);
+    tw_apply<R>(v + b * R, t);
+    dft<f2v, R>(v + b * R);
+  }
+}
+
+// write of 16 outputs of an Ns = 1 radix-16 pass: entry 16 jt + r
+__device__ __forceinline__ void pow2_write_ns1(f2v* z, int slot, int jt, const f2v (&v)[16]) {
+  jt = fresh(jt);
+  slot = fresh(slot);
+  // sw(16 jt + r) = (16 jt with bit 4 cleared) + 16 ((jt ^ jt >> 4) & 1) + (r ^ (jt & 15))
+  const int base = slot + (16 * jt & ~31) + 16 * ((jt ^ (jt >> 4)) & 1);
+  const int x = jt & 15;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) z[base + (x ^ r)] = v[r];
+}
+
+// Stockham write of pass P's outputs (an inner pass: radix 16, Ns >= 16)
+template <int LG, int P>
+__device__ __forceinline__ void pow2_pass_out(f2v* __restrict__ z, int slot, int jt, const f2v (&v)[16]) {
+  typedef Pow2<LG> C;
+  constexpr int R = C::radix(P), NS = C::ns(P);
+  static_assert(R == 16 && NS >= 16, "inner passes are radix 16");
+  jt = fresh(jt);
+  slot = fresh(slot);
+  if constexpr (NS == 16) {
+    // entry k0 + 16 r, k0 = 256 (jt >> 4) + (jt & 15): bits 0..3 are (jt & 15) ^ r, bit 4 is
+    // (r ^ jt >> 4) & 1, bits 5.. are 256 (jt >> 4) + 32 (r >> 1)
+    const int hi = slot + 256 * (jt >> 4);
+    const int b0 = hi + 16 * ((jt >> 4) & 1), b1 = hi + 16 * (((jt >> 4) & 1) ^ 1);
+    const int x = jt & 15;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[((r & 1) ? b1 : b0) + (x ^ r) + 32 * (r >> 1)] = v[r];
+  } else {
+    const int k0 = ((jt / NS) * NS * R) + (jt & (NS - 1));
+    const int K = slot + sw(k0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[(K ^ (((i * NS) >> 4) & 31)) + i * NS] = v[i];
+  }
+}
+
+template <int LG, int P>
+__device__ __forceinline__ void pow2_inner(f2v* z, const f2v* tw, int slot, int jt, int A) {
+  if constexpr (P < Pow2<LG>::NP - 1) {
+    f2v v[16];
+    pow2_pass_in<LG, P>(z, tw, jt, A, v);
+    lds_barrier();
+    pow2_pass_out<LG, P>(z, slot, jt, v);
+    lds_barrier();
+    pow2_inner<LG, P + 1>(z, tw, slot, jt, A);
+  }
+}
+
+// outputs of the last pass (radix RL, NB = 16 / RL butterflies per thread) in the order of the entries
+// jt + s L/16: s = b + r NB
+template <int LG>
+__device__ __forceinline__ void pow2_gather(const f2v (&v)[16], f2v (&u)[16]) {
+  constexpr int R = Pow2<LG>::RL, NB = 16 / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[b + r * NB] = v[b * R + r];
+}
+
+template <int LG, bool CONTIG>
+__global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kernel(FftArgs a) {
+  typedef Pow2<LG> C;
+  constexpr int L = C::L, N = C::N, Q = C::Q, W = 2 * C::F, EPT = C::EPT;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  f2v* z = reinterpret_cast<f2v*>(smem);
+  const f2v* tw = static_cast<const f2v*>(a.tw);
+  int64_t grp = blockIdx.x;
+  if (a.xcd_spread) grp = static_cast<int64_t>(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  if (grp >= a.groups) return;
+  const int tid = threadIdx.x;
+  int64_t b = 0, l0;
+  if (CONTIG) {
+    l0 = grp * W;
+  } else {
+    b = grp / a.gpb;
+    l0 = (grp - b * a.gpb) * W;
+  }
+  const int nl = static_cast<int>(min<int64_t>(W, a.ncols - l0));
+  const int nin = a.nin, nout = a.nout;
+  // the group's first line; offsets from there stay below 2^31 elements (plans hold at most 2^31 points)
+  const int64_t xo = b * a.x_bstride + (CONTIG ? l0 * nin : l0);
+  const int64_t yo = b * a.y_bstride + (CONTIG ? l0 * nout : l0);
+  const float* X = static_cast<const float*>(a.X) + xo;
+  float* Y = static_cast<float*>(a.Y) + yo;
+  const int ld = static_cast<int>(a.ncols);   // strided: elements between consecutive positions of a line
+  const float inv_nin = __builtin_amdgcn_rcpf(static_cast<float>(nin));
+  const float inv_nout = __builtin_amdgcn_rcpf(static_cast<float>(nout));
+  // element e of the group's input (output) lines: line c, position k along the line
+  auto in_pos = [&](int e, int& c, int& k) {
+    if (CONTIG) {
+      c = fdiv(e, nin, inv_nin);
+      k = e - c * nin;
+    } else {
+      c = e & (W - 1);
+      k = e / W;
+    }
+  };
+  auto out_pos = [&](int e, int& c, int& m) {
+    if (CONTIG) {
+      c = fdiv(e, nout, inv_nout);
+      m = e - c * nout;
+    } else {
+      c = e & (W - 1);
+      m = e / W;
+    }
+  };
+  auto in_off = [&](int c, int k) { return CONTIG ? c * nin + k : k * ld + c; };
+  auto out_off = [&](int c, int m) { return CONTIG ? c * nout + m : m * ld + c; };
+
+  // ---- loads: the input lines and the old output values (W lines of at most N + 1 values: 17 per thread)
+  const bool read_y = a.beta != 0.0;
+  const int cnt_in = W * nin, cnt_out = W * nout;
+  // every thread issues all its loads (an element past the lines reads the group's first element and
+  // is dropped), so no load waits behind a branch
+  float xv[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + u * C::NT;
+    int c, k;
+    in_pos(e, c, k);
+    const bool ok = e < cnt_in && c < nl;
+    const float t = X[ok ? in_off(c, k) : 0];
+    xv[u] = ok ? t : 0.0f;
+  }
+  {
+    int tid2 = threadIdx.x;   // positions recomputed, not kept live across the loads
+    asm volatile("" : "+v"(tid2));
+    float* zs = reinterpret_cast<float*>(z);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid2 + u * C::NT;
+      int c, k;
+      in_pos(e, c, k);
+      if (e < cnt_in) zs[2 * ((c >> 1) * L + sw(k)) + (c & 1)] = xv[u];
+    }
+  }
+  lds_barrier();
+
+  const int f = tid / Q, jt = tid & (Q - 1);
+  const int slot = f * L;
+  const int A = slot + sw(jt);   // slot + sw(jt): the layout of transform f
+  // the multiplier's and the pre-twiddle's per-thread factors
+  const f2v hb = static_cast<const f2v*>(a.h)[jt];
+  const f2v pb = a.anti ? static_cast<const f2v*>(a.pre)[jt] : f2v{1.f, 0.f};
+  f2v v[16];
+  // ---- first forward pass: extension (mirror about the right wall, sign sR for G, -sR for D; Dirichlet
+  // wall nodes enter as 0), pre-twiddle for mixed walls, radix 16 without twiddles
+  {
+    const float sg = a.dir == 0 ? static_cast<float>(a.sR) : static_cast<float>(-a.sR);
+    const int mo = a.dir == 0 ? -jt : -1 - jt;   // mirrored entry: (16 - r) Q + mo
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = i < 8 ? z[sw_add(A, jt, i * Q)] : z[slot + sw((16 - i) * Q + mo)];
+#pragma unroll
+    for (int r = 8; r < 16; ++r) v[r] = f2v{v[r].x * sg, v[r].y * sg};
+    if (a.dir == 0 && jt == 0) {
+      if (a.sL < 0) v[0] = f2v{0.f, 0.f};
+      if (a.sR < 0) v[8] = f2v{0.f, 0.f};
+    }
+    if (a.anti) {
+      // e^{-i pi (jt + r Q) / L} = e^{-i pi jt / L} e^{-i pi r / 16}
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], cmul(pb, f2v{kC32[r], -kS32[r]}));
+    }
+    dft<f2v, 16>(v);
+    lds_barrier();
+    pow2_write_ns1(z, slot, jt, v);
+    lds_barrier();
+  }
+  pow2_inner<LG, 1>(z, tw, slot, jt, A);
+  // ---- last forward pass, conj(H X), first inverse pass (radix 16 without twiddles)
+  {
+    pow2_pass_in<LG, C::NP - 1>(z, tw, jt, A, v);
+    f2v u[16];
+    pow2_gather<LG>(v, u);
+    // H_k = i g_k e^{i sigma pi (t + s L/8) / (2L)} at k = jt + s L/16, t = 2 jt + a (a = 1 for mixed
+    // walls), sigma = +1 (G) or -1 (D): the signed frequency 2 m_k = t + s L/8 folded by -2L (which flips
+    // the phase's sign) from s = 8 on, g_k = |2 m_k| kfac / 2
+    const float sgm = a.dir == 0 ? 1.0f : -1.0f;
+    const f2v B = f2v{hb.x, sgm * hb.y};
+    const float kh = static_cast<float>(0.5 * a.kfac);
+    const float t = static_cast<float>(2 * jt + a.anti);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const f2v d = cmul(B, f2v{kC32[s], sgm * kS32[s]});
+      const float g = s < 8 ? kh * (static_cast<float>(s * (L / 8)) + t) : kh * (static_cast<float>((16 - s) * (L / 8)) - t);
+      const f2v p = cmul(d, u[s]);
+      u[s] = f2v{-g * p.y, -g * p.x};   // conj(i g p)
+    }
+    dft<f2v, 16>(u);
+    lds_barrier();
+    pow2_write_ns1(z, slot, jt, u);
+    lds_barrier();
+  }
+  pow2_inner<LG, 1>(z, tw, slot, jt, A);
+  // ---- last inverse pass, conjugation and post-twiddle
+  {
+    pow2_pass_in<LG, C::NP - 1>(z, tw, jt, A, v);
+    f2v u[16];
+    pow2_gather<LG>(v, u);
+    if (a.anti) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const f2v t = cmul(pb, f2v{kC32[s], -kS32[s]});   // e^{-i pi j / L}; the post-twiddle is its conjugate
+        u[s] = f2v{u[s].x * t.x - u[s].y * t.y, -(u[s].x * t.y + u[s].y * t.x)};   // conj(u) conj(t)
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) u[s].y = -u[s].y;
+    }
+    lds_barrier();
+    const int A2 = fresh(A), jt2 = fresh(jt);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[sw_add(A2, jt2, i * Q)] = u[i];
+    lds_barrier();
+  }
+
+  // ---- epilogue: Y = beta Y + alpha scale out, formed in FP64
+  const float* S = a.scale ? static_cast<const float*>(a.scale) + yo : nullptr;
+  // positions recomputed from an opaque thread index: the compiler would otherwise keep the load phase's
+  // offsets live through the transforms
+  int tid3 = threadIdx.x;
+  asm volatile("" : "+v"(tid3));
+  float yv[EPT];
+  if (read_y) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid3 + u * C::NT;
+      int c, m;
+      out_pos(e, c, m);
+      const bool ok = e < cnt_out && c < nl;
+      yv[u] = Y[ok ? out_off(c, m) : 0];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) yv[u] = 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid3 + u * C::NT;
+    int c, m;
+    out_pos(e, c, m);
+    if (e < cnt_out && c < nl) {
+      const float sv = S ? S[out_off(c, m)] : 1.0f;
+      const f2v w = z[(c >> 1) * L + sw(m)];
+      float ov = (c & 1) ? w.y : w.x;
+      // pressure at a Dirichlet wall node stays 0
+      if (a.dir == 1 && ((m == 0 && a.sL < 0) || (m == N && a.sR < 0))) ov = 0.0f;
+      Y[out_off(c, m)] = static_cast<float>(a.beta * static_cast<double>(yv[u]) +
+                                            a.alpha * static_cast<double>(sv) * static_cast<double>(ov));
+    }
+  }
+}
+
+template <int LG>
+hipError_t launch_pow2(const FftArgs& a, hipStream_t s) {
+  typedef Pow2<LG> C;
+  const size_t shm = static_cast<size_t>(C::F) * C::L * sizeof(f2v);
+  int64_t blocks = a.groups;
+  if (a.xcd_spread) blocks = round_up(blocks, 8);
+  if (a.contig)
+    hipLaunchKernelGGL((fft_pow2_kernel<LG, true>), dim3(static_cast<unsigned>(blocks)), dim3(C::NT), shm, s, a);
+  else
+    hipLaunchKernelGGL((fft_pow2_kernel<LG, false>), dim3(static_cast<unsigned>(blocks)), dim3(C::NT), shm, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int fft_capacity(bool dbl) { return dbl ? 8192 : 16384; }
@@ -537,6 +910,23 @@ int fft_max_per_block(bool dbl, int L) {
 
 hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s) {
   return dbl ? launch_typed<double>(a, s) : launch_typed<float>(a, s);
+}
+
+int fft_pow2_lines(int L) {
+  if (L < 256 || L > 8192 || (L & (L - 1)) != 0) return 0;
+  return L <= 4096 ? 2 * (4096 / L) : 2;
+}
+
+hipError_t launch_fft_pow2(const FftArgs& a, hipStream_t s) {
+  switch (a.L) {
+    case 256: return launch_pow2<8>(a, s);
+    case 512: return launch_pow2<9>(a, s);
+    case 1024: return launch_pow2<10>(a, s);
+    case 2048: return launch_pow2<11>(a, s);
+    case 4096: return launch_pow2<12>(a, s);
+    case 8192: return launch_pow2<13>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace pstd

@@ -182,13 +182,14 @@ class Plan:
         cs = st._c()
         check(load().pstd_step_prepare(self._h, C.byref(cs), int(n_steps)), "pstd_step_prepare")
 
-    PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3, "stored": 4}
+    PATHS = {"auto": 0, "per_axis": 1, "fused": 2, "fft": 3, "stored": 4, "fft_generic": 5}
 
     def set_path(self, path: str) -> None:
         """Execution path of later steps: "auto", "per_axis" (dense contractions), "fused" (2D FP32: two
-        kernels per step), "fft" (LDS-resident FFTs on every axis whose 2(n-1) is 16 x 2^a 3^b 5^c) or
-        "stored" (per_axis with split-bf16 operators read from memory rather than formed from their
-        Toeplitz and Hankel parts)."""
+        kernels per step), "fft" (LDS-resident FFTs on every axis whose 2(n-1) is 16 x 2^a 3^b 5^c),
+        "fft_generic" (fft with every axis on the mixed-radix kernel, also where an FP32 power-of-two
+        length has its own) or "stored" (per_axis with split-bf16 operators read from memory rather than
+        formed from their Toeplitz and Hankel parts)."""
         check(load().pstd_plan_set_path(self._h, self.PATHS[path]), "pstd_plan_set_path")
 
     def apply_axis(self, st: State, axis: int, which: int) -> None:
