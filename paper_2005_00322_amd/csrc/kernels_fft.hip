@@ -542,7 +542,8 @@ hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
 //            conj(H X) and that inverse pass follow in registers; the conjugation (and post-twiddle) is
 //            applied as the last inverse pass writes;
 //   memory   every thread issues all its loads of the input lines at once, and of the old output values
-//            at once, without branches.
+//            at once, without branches; on unit-stride axes the old output values are loaded with the
+//            input (their loads overlap), on strided ones in the epilogue (registers).
 template <int LG>
 struct Pow2 {
   static constexpr int L = 1 << LG, N = L / 2, Q = L / 16;
@@ -718,23 +719,18 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   const int ld = static_cast<int>(a.ncols);   // strided: elements between consecutive positions of a line
   const float inv_nin = __builtin_amdgcn_rcpf(static_cast<float>(nin));
   const float inv_nout = __builtin_amdgcn_rcpf(static_cast<float>(nout));
-  // element e of the group's input (output) lines: line c, position k along the line
-  auto in_pos = [&](int e, int& c, int& k) {
-    if (CONTIG) {
-      c = fdiv(e, nin, inv_nin);
-      k = e - c * nin;
-    } else {
-      c = e & (W - 1);
-      k = e / W;
-    }
-  };
-  auto out_pos = [&](int e, int& c, int& m) {
-    if (CONTIG) {
-      c = fdiv(e, nout, inv_nout);
-      m = e - c * nout;
-    } else {
-      c = e & (W - 1);
-      m = e / W;
+  // element e of the group's lines of n values: line c, position k along it.  On a unit-stride axis the
+  // lines are consecutive rows, so e is also the element's offset from the group's first one.
+  struct Pos {
+    int c, k;
+    __device__ Pos(int e, int n, float inv) {
+      if (CONTIG) {
+        c = fdiv(e, n, inv);
+        k = e - c * n;
+      } else {
+        c = e & (W - 1);
+        k = e / W;
+      }
     }
   };
   auto in_off = [&](int c, int k) { return CONTIG ? c * nin + k : k * ld + c; };
@@ -742,29 +738,44 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
 
   // ---- loads: the input lines and the old output values (W lines of at most N + 1 values: 17 per thread)
   const bool read_y = a.beta != 0.0;
-  const int cnt_in = W * nin, cnt_out = W * nout;
   // every thread issues all its loads (an element past the lines reads the group's first element and
   // is dropped), so no load waits behind a branch
   float xv[EPT];
+  const int cin = nl * nin, cout = nl * nout;
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     const int e = tid + u * C::NT;
-    int c, k;
-    in_pos(e, c, k);
-    const bool ok = e < cnt_in && c < nl;
-    const float t = X[ok ? in_off(c, k) : 0];
+    int off;
+    bool ok;
+    if (CONTIG) {
+      off = e;
+      ok = e < cin;
+    } else {
+      const Pos p(e, nin, inv_nin);
+      off = in_off(p.c, p.k);
+      ok = p.c < nl && p.k < nin;
+    }
+    const float t = X[ok ? off : 0];
     xv[u] = ok ? t : 0.0f;
   }
-  {
-    int tid2 = threadIdx.x;   // positions recomputed, not kept live across the loads
-    asm volatile("" : "+v"(tid2));
-    float* zs = reinterpret_cast<float*>(z);
+  float yv[EPT];
+  if (CONTIG) {
+    const int t0 = fresh(tid);
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = tid2 + u * C::NT;
-      int c, k;
-      in_pos(e, c, k);
-      if (e < cnt_in) zs[2 * ((c >> 1) * L + sw(k)) + (c & 1)] = xv[u];
+      const int e = t0 + u * C::NT;
+      yv[u] = read_y ? Y[e < cout ? e : 0] : 0.0f;
+    }
+  }
+  {
+    // positions recomputed, not kept live across the loads
+    float* zs = reinterpret_cast<float*>(z);
+    const int t0 = fresh(tid);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = t0 + u * C::NT;
+      const Pos p(e, nin, inv_nin);
+      if (e < W * nin) zs[2 * ((p.c >> 1) * L + sw(p.k)) + (p.c & 1)] = xv[u];
     }
   }
   lds_barrier();
@@ -851,35 +862,32 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   const float* S = a.scale ? static_cast<const float*>(a.scale) + yo : nullptr;
   // positions recomputed from an opaque thread index: the compiler would otherwise keep the load phase's
   // offsets live through the transforms
-  int tid3 = threadIdx.x;
-  asm volatile("" : "+v"(tid3));
-  float yv[EPT];
-  if (read_y) {
+  const int tid3 = fresh(tid);
+  if (!CONTIG) {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = tid3 + u * C::NT;
-      int c, m;
-      out_pos(e, c, m);
-      const bool ok = e < cnt_out && c < nl;
-      yv[u] = Y[ok ? out_off(c, m) : 0];
+      const Pos p(tid3 + u * C::NT, nout, inv_nout);
+      const bool ok = p.c < nl && p.k < nout;
+      yv[u] = read_y ? Y[ok ? out_off(p.c, p.k) : 0] : 0.0f;
     }
-  } else {
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) yv[u] = 0.0f;
   }
 #pragma unroll
+  for (int u = 0; u < EPT; ++u) asm volatile("" : "+v"(yv[u]));   // widened to FP64 here, not at the load
+  const int tid4 = fresh(tid3);
+#pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    const int e = tid3 + u * C::NT;
-    int c, m;
-    out_pos(e, c, m);
-    if (e < cnt_out && c < nl) {
-      const float sv = S ? S[out_off(c, m)] : 1.0f;
-      const f2v w = z[(c >> 1) * L + sw(m)];
-      float ov = (c & 1) ? w.y : w.x;
+    const int e = tid4 + u * C::NT;
+    const Pos p(e, nout, inv_nout);
+    const int c = p.c, m = p.k;
+    if (c < nl && m < nout) {
+      const int off = CONTIG ? e : out_off(c, m);
+      const float sv = S ? S[off] : 1.0f;
+      const f2v v2 = z[(c >> 1) * L + sw(m)];
+      float ov = (c & 1) ? v2.y : v2.x;
       // pressure at a Dirichlet wall node stays 0
       if (a.dir == 1 && ((m == 0 && a.sL < 0) || (m == N && a.sR < 0))) ov = 0.0f;
-      Y[out_off(c, m)] = static_cast<float>(a.beta * static_cast<double>(yv[u]) +
-                                            a.alpha * static_cast<double>(sv) * static_cast<double>(ov));
+      Y[off] = static_cast<float>(a.beta * static_cast<double>(yv[u]) +
+                                  a.alpha * static_cast<double>(sv) * static_cast<double>(ov));
     }
   }
 }
