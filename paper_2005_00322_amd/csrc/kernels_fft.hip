@@ -821,12 +821,15 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
     // the phase's sign) from s = 8 on, g_k = |2 m_k| kfac / 2
     const float sgm = a.dir == 0 ? 1.0f : -1.0f;
     const f2v B = f2v{hb.x, sgm * hb.y};
-    const float kh = static_cast<float>(0.5 * a.kfac);
+    // kfac / 2 as a pair of floats: each g_k is rounded once, not every mode scaled by one rounded factor
+    const double khd = 0.5 * a.kfac;
+    const float kh = static_cast<float>(khd), kl = static_cast<float>(khd - static_cast<double>(kh));
     const float t = static_cast<float>(2 * jt + a.anti);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const f2v d = cmul(B, f2v{kC32[s], sgm * kS32[s]});
-      const float g = s < 8 ? kh * (static_cast<float>(s * (L / 8)) + t) : kh * (static_cast<float>((16 - s) * (L / 8)) - t);
+      const float n2 = s < 8 ? static_cast<float>(s * (L / 8)) + t : static_cast<float>((16 - s) * (L / 8)) - t;
+      const float g = __builtin_fmaf(kh, n2, kl * n2);
       const f2v p = cmul(d, u[s]);
       u[s] = f2v{-g * p.y, -g * p.x};   // conj(i g p)
     }
