@@ -84,7 +84,8 @@ typedef struct pstd_plan_s* pstd_plan;
  * "Differentiation with staggered grids", folds -dt/rho0 and -dt rho0 c0^2 into them, rounds them to
  * the plan's precision and copies them to the device.  Axes that start on the FFT path (see pstd_path)
  * get FFT tables instead (twiddles and the spectral multipliers, also formed in FP64).  Sizes: n <= 4097
- * per axis on the dense path; up to 8193 (FP32 state) or 4097 (FP64) where 2(n-1) = 16 x 2^a 3^b 5^c.
+ * per axis on the dense path; up to 8193 (FP32 state) or 4097 (FP64) where 2(n-1) = 16 x 2^a 3^b 5^c; a
+ * periodic axis of a float state up to 8192 points where n is a power of two (the FFT path).
  * Returns PSTD_E_UNSTABLE if the time step is above the
  * stability limit, PSTD_E_UNSUPPORTED for sizes outside these limits. */
 int pstd_plan_create(const pstd_grid* grid, double dx, double dt, double c0,
@@ -125,7 +126,9 @@ int pstd_step_prepare(pstd_plan plan, const pstd_state* state, int64_t n_steps);
  *   FFT:      every axis whose extended period 2(n-1) is 16 x 2^a 3^b 5^c (up to 16384 for a float state,
  *             8192 for FP64) applies its operators as LDS-resident FFTs of the field's symmetric
  *             extension (§3.2: each DTT is a DFT of an evenly or oddly extended sequence), one kernel per
- *             axis and half step; other axes stay dense.
+ *             axis and half step, and so does a periodic axis of a float state whose n is a power of two
+ *             from 256 to 8192 (the DFT of the line itself, Eq. (fourier_pstd_solution)); other axes stay
+ *             dense.
  *   AUTO:     FUSED where it applies; otherwise FFT on axes above 512 nodes (1D plans: above 1365) and
  *             dense contractions elsewhere.
  *   FFT_GENERIC: FFT, with every axis on the mixed-radix kernel.  Under the other paths an FP32 axis

@@ -180,6 +180,7 @@ int ensure_dense(pstd_plan_s* P, int a) {
 // nodes (1D plans keep the single-workgroup kernel up to 1365 nodes).
 bool axis_fft(const pstd_plan_s* P, int a) {
   if (!P->fft[a].ok) return false;
+  if (P->fft[a].periodic && !P->fft_pow2) return false;   // the mixed-radix kernel extends symmetrically
   if (P->path == PSTD_PATH_FFT || P->path == PSTD_PATH_FFT_GENERIC) return true;
   if (P->path != PSTD_PATH_AUTO) return false;
   if (P->ndim == 1) return P->n[0] > 1365;
@@ -255,8 +256,9 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
   x.N = f.N;
   x.L = f.L;
   const int n = static_cast<int>(P->n[a]);
-  x.nin = which == 0 ? n : n - 1;
-  x.nout = which == 0 ? n - 1 : n;
+  x.periodic = f.periodic;
+  x.nin = which == 0 || f.periodic ? n : n - 1;
+  x.nout = which == 1 || f.periodic ? n : n - 1;
   x.dir = which;
   x.sL = f.sL;
   x.sR = f.sR;
@@ -410,7 +412,10 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
   if (precision < PSTD_FP64 || precision > PSTD_SPLIT_BF16) return fail(PSTD_E_INVALID_ARG, "bad precision");
   for (int a = 0; a < grid->ndim; ++a) {
     if (grid->n[a] < 3) return fail(PSTD_E_INVALID_ARG, "axis %d has %lld nodes (need >= 3)", a, (long long)grid->n[a]);
-    if (grid->n[a] > 4097 && !(grid->n[a] <= 16385 && fft_axis_possible(static_cast<int>(grid->n[a]), precision)))
+    const bool per_fft = bc_per_face[2 * a] == PSTD_PERIODIC && precision != PSTD_FP64 && grid->n[a] <= 8192 &&
+                         fft_pow2_lines(static_cast<int>(grid->n[a])) > 0;
+    if (grid->n[a] > 4097 && bc_per_face[2 * a] != PSTD_PERIODIC &&
+        !(grid->n[a] <= 16385 && fft_axis_possible(static_cast<int>(grid->n[a]), precision)))
       return fail(PSTD_E_UNSUPPORTED,
                   "axis %d: %lld nodes; above 4097 the FFT path needs 2(n-1) = 16 x 2^a 3^b 5^c within %d (%s)", a,
                   (long long)grid->n[a], fft_capacity(precision == PSTD_FP64),
@@ -426,8 +431,9 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
       return fail(PSTD_E_UNSUPPORTED, "axis %d: half-step walls run on the dense path (at most 4097 nodes)", a);
     if ((bc_per_face[2 * a] == PSTD_PERIODIC) != (bc_per_face[2 * a + 1] == PSTD_PERIODIC))
       return fail(PSTD_E_INVALID_ARG, "axis %d: a periodic axis has both faces periodic", a);
-    if (bc_per_face[2 * a] == PSTD_PERIODIC && grid->n[a] > 4097)
-      return fail(PSTD_E_UNSUPPORTED, "axis %d: periodic axes run on the dense path (at most 4097 nodes)", a);
+    if (bc_per_face[2 * a] == PSTD_PERIODIC && grid->n[a] > 4097 && !per_fft)
+      return fail(PSTD_E_UNSUPPORTED,
+                  "axis %d: periodic axes above 4097 points need n a power of two up to 8192 and a float state", a);
   }
   if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
     return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");

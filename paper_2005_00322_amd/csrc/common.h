@@ -204,6 +204,7 @@ struct FftAxis {
   void* tw = nullptr;           // w, w^2, w^4, w^8 of each Stockham pass after the first, per j mod Ns
   void* hb = nullptr;           // e^{i pi (2t + a) / (2L)}, t < L/16 (a = 1 for mixed walls)
   void* pre = nullptr;          // e^{-i pi t / L}, t < L/16 (mixed walls)
+  bool periodic = false;        // a periodic axis: L = n, no extension (fft_pow2_kernel only)
 };
 
 struct FftArgs {
@@ -220,6 +221,7 @@ struct FftArgs {
   int nin, nout;                // extents of X and Y along the axis
   int dir;                      // 0: G (nodes -> half nodes), 1: D (half nodes -> nodes)
   int sL, sR, anti;
+  int periodic;                 // a periodic axis (fft_pow2_kernel): L = n input and output values per line
   int F;                        // transforms per block (2F lines)
   int npass;
   int radix[8];

@@ -57,11 +57,19 @@ int upload_complex(const std::vector<std::complex<double>>& h, void** out) {
 int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   FftAxis& f = P->fft[a];
   const int n = static_cast<int>(P->n[a]);
-  if (!fft_axis_possible(n, P->prec) || P->bc[2 * a] == PSTD_PERIODIC || half_wall(P->bc[2 * a + 1]))
-    return PSTD_OK;  // dense path only
-  const int N = n - 1, L = 2 * N;
+  const bool per = P->bc[2 * a] == PSTD_PERIODIC;
+  if (half_wall(P->bc[2 * a + 1])) return PSTD_OK;   // dense path only
+  if (per) {
+    // a periodic axis is its own period: L = n, the Fourier modes of §3.2's periodic case; only the FP32
+    // power-of-two kernel takes it
+    if (P->prec == PSTD_FP64 || fft_pow2_lines(n) == 0) return PSTD_OK;
+  } else if (!fft_axis_possible(n, P->prec)) {
+    return PSTD_OK;
+  }
+  const int L = per ? n : 2 * (n - 1), N = L / 2;
   f.N = N;
   f.L = L;
+  f.periodic = per;
   fft_factor(L, &f.npass, f.radix);
   f.sL = P->bc[2 * a] == PSTD_DIRICHLET ? -1 : 1;
   f.sR = P->bc[2 * a + 1] == PSTD_DIRICHLET ? -1 : 1;
@@ -77,7 +85,7 @@ int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   const bool dbl = P->prec == PSTD_FP64;
   int st = dbl ? upload_complex<double>(tab, &f.tab) : upload_complex<float>(tab, &f.tab);
   if (st != PSTD_OK) return st;
-  if (P->prec == PSTD_FP32 && fft_pow2_lines(L) > 0) {
+  if (P->prec != PSTD_FP64 && fft_pow2_lines(L) > 0) {
     // fft_pow2_kernel: radix-16 passes, then one pass of the remaining factor 2, 4 or 8.  Per pass after
     // the first, w, w^2, w^4, w^8 for w = e^{-2 pi i (j mod Ns) / (Ns R)}; per thread t < L/16 of a
     // transform, e^{i pi (2t + a) / (2L)} (a = 1 for mixed walls: the multiplier's phase, whose other

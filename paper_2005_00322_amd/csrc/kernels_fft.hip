@@ -552,6 +552,7 @@ struct Pow2 {
   static constexpr int NP = (LG + 3) / 4;               // passes
   static constexpr int RL = 1 << (LG - 4 * (NP - 1));   // radix of the last pass
   static constexpr int EPT = 17;                        // input / output elements per thread (2F lines)
+  static constexpr int EPT_PER = 32;                    // the same on a periodic axis (L values per line)
   static constexpr int radix(int p) { return p < NP - 1 ? 16 : RL; }
   static constexpr int ns(int p) { return 1 << (4 * p); }
   // offset of pass p's twiddles in the table (passes 1 .. NP-1, four entries per j mod Ns)
@@ -691,10 +692,12 @@ __device__ __forceinline__ void pow2_gather(const f2v (&v)[16], f2v (&u)[16]) {
     for (int r = 0; r < R; ++r) u[b + r * NB] = v[b * R + r];
 }
 
-template <int LG, bool CONTIG>
+template <int LG, bool CONTIG, bool PER>
 __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kernel(FftArgs a) {
   typedef Pow2<LG> C;
-  constexpr int L = C::L, N = C::N, Q = C::Q, W = 2 * C::F, EPT = C::EPT;
+  constexpr int L = C::L, N = C::N, Q = C::Q, W = 2 * C::F, EPT = PER ? C::EPT_PER : C::EPT;
+  // the old output values load with the input where they fit the registers (unit stride, walls)
+  constexpr bool YPRE = CONTIG && !PER;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   f2v* z = reinterpret_cast<f2v*>(smem);
   const f2v* tw = static_cast<const f2v*>(a.tw);
@@ -759,7 +762,7 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
     xv[u] = ok ? t : 0.0f;
   }
   float yv[EPT];
-  if (CONTIG) {
+  if (YPRE) {
     const int t0 = fresh(tid);
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
@@ -790,15 +793,21 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   // ---- first forward pass: extension (mirror about the right wall, sign sR for G, -sR for D; Dirichlet
   // wall nodes enter as 0), pre-twiddle for mixed walls, radix 16 without twiddles
   {
-    const float sg = a.dir == 0 ? static_cast<float>(a.sR) : static_cast<float>(-a.sR);
-    const int mo = a.dir == 0 ? -jt : -1 - jt;   // mirrored entry: (16 - r) Q + mo
+    if (PER) {
+      // a periodic line is its own period
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = i < 8 ? z[sw_add(A, jt, i * Q)] : z[slot + sw((16 - i) * Q + mo)];
+      for (int i = 0; i < 16; ++i) v[i] = z[sw_add(A, jt, i * Q)];
+    } else {
+      const float sg = a.dir == 0 ? static_cast<float>(a.sR) : static_cast<float>(-a.sR);
+      const int mo = a.dir == 0 ? -jt : -1 - jt;   // mirrored entry: (16 - r) Q + mo
 #pragma unroll
-    for (int r = 8; r < 16; ++r) v[r] = f2v{v[r].x * sg, v[r].y * sg};
-    if (a.dir == 0 && jt == 0) {
-      if (a.sL < 0) v[0] = f2v{0.f, 0.f};
-      if (a.sR < 0) v[8] = f2v{0.f, 0.f};
+      for (int i = 0; i < 16; ++i) v[i] = i < 8 ? z[sw_add(A, jt, i * Q)] : z[slot + sw((16 - i) * Q + mo)];
+#pragma unroll
+      for (int r = 8; r < 16; ++r) v[r] = f2v{v[r].x * sg, v[r].y * sg};
+      if (a.dir == 0 && jt == 0) {
+        if (a.sL < 0) v[0] = f2v{0.f, 0.f};
+        if (a.sR < 0) v[8] = f2v{0.f, 0.f};
+      }
     }
     if (a.anti) {
       // e^{-i pi (jt + r Q) / L} = e^{-i pi jt / L} e^{-i pi r / 16}
@@ -866,7 +875,7 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   // positions recomputed from an opaque thread index: the compiler would otherwise keep the load phase's
   // offsets live through the transforms
   const int tid3 = fresh(tid);
-  if (!CONTIG) {
+  if (!YPRE) {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const Pos p(tid3 + u * C::NT, nout, inv_nout);
@@ -888,7 +897,7 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
       const f2v v2 = z[(c >> 1) * L + sw(m)];
       float ov = (c & 1) ? v2.y : v2.x;
       // pressure at a Dirichlet wall node stays 0
-      if (a.dir == 1 && ((m == 0 && a.sL < 0) || (m == N && a.sR < 0))) ov = 0.0f;
+      if (!PER && a.dir == 1 && ((m == 0 && a.sL < 0) || (m == N && a.sR < 0))) ov = 0.0f;
       Y[off] = static_cast<float>(a.beta * static_cast<double>(yv[u]) +
                                   a.alpha * static_cast<double>(sv) * static_cast<double>(ov));
     }
@@ -901,10 +910,14 @@ hipError_t launch_pow2(const FftArgs& a, hipStream_t s) {
   const size_t shm = static_cast<size_t>(C::F) * C::L * sizeof(f2v);
   int64_t blocks = a.groups;
   if (a.xcd_spread) blocks = round_up(blocks, 8);
-  if (a.contig)
-    hipLaunchKernelGGL((fft_pow2_kernel<LG, true>), dim3(static_cast<unsigned>(blocks)), dim3(C::NT), shm, s, a);
-  else
-    hipLaunchKernelGGL((fft_pow2_kernel<LG, false>), dim3(static_cast<unsigned>(blocks)), dim3(C::NT), shm, s, a);
+  const dim3 g(static_cast<unsigned>(blocks)), t(C::NT);
+  if (a.periodic) {
+    if (a.contig) hipLaunchKernelGGL((fft_pow2_kernel<LG, true, true>), g, t, shm, s, a);
+    else hipLaunchKernelGGL((fft_pow2_kernel<LG, false, true>), g, t, shm, s, a);
+  } else {
+    if (a.contig) hipLaunchKernelGGL((fft_pow2_kernel<LG, true, false>), g, t, shm, s, a);
+    else hipLaunchKernelGGL((fft_pow2_kernel<LG, false, false>), g, t, shm, s, a);
+  }
   return hipGetLastError();
 }
 

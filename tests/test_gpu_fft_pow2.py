@@ -3,7 +3,9 @@
 Each case applies the velocity and the pressure term along every such axis once, on unit-stride
 (contiguous) and strided axes and on every pair of wall types, and compares with the FP64 oracle's DTT
 recipe element by element (FP32 bound 2e-6, as for the mixed-radix kernel) and with the mixed-radix
-kernel on the same input (the two agree to the same bound and differ in rounding, so both ran).
+kernel on the same input (the two agree to the same bound and differ in rounding, so both ran).  Periodic
+axes of n = 256 .. 8192 points (a power of two: the transform is the line itself) are compared with the
+oracle's Fourier recipe and, up to 4096 points, with the dense contraction.
 """
 import numpy as np
 import pytest
@@ -26,6 +28,9 @@ CASES = [
     ((6, 4097), ((N, N), (N, D))),
     ((129, 20, 257), ((D, N), (N, N), (N, D))),
 ]
+
+
+P = opstd.PERIODIC
 
 
 def _pow2_axis(n):
@@ -97,3 +102,51 @@ def test_pow2_kernel_steps_with_c0_map():
     print("rel_l2 pow2", rel_l2(got, ref_p), "mixed radix", rel_l2(gen, ref_p), flush=True)
     assert rel_l2(got, ref_p) < 1e-5
     assert rel_l2(gen, ref_p) < 1e-5
+
+
+PERIODIC_CASES = [
+    ((256, 24), ((P, P), (D, N))),
+    ((20, 1024), ((N, D), (P, P))),
+    ((2048, 8), ((P, P), (N, N))),
+    ((8, 4096), ((D, D), (P, P))),
+    ((8192, 4), ((P, P), (D, D))),
+]
+
+
+@pytest.mark.parametrize("shape,bcs", PERIODIC_CASES)
+def test_pow2_kernel_periodic_axes(shape, bcs):
+    import torch
+    from paper_2005_00322_amd import Plan
+
+    print("case", shape, bcs, flush=True)
+    dx, c0 = 1e-3, 1500.0
+    dt = 0.25 * dx / c0
+    prob = opstd.Problem(shape, bcs, dx, dt, c0)
+    rng = np.random.default_rng(sum(shape) + 1)
+    p = prob.project(rng.standard_normal(shape))
+    a = [i for i in range(len(shape)) if bcs[i][0] == P][0]
+    u = rng.standard_normal(prob.u_shape(a))
+    refs = (-(dt / prob.rho0) * prob.grad(p, a), -(dt * prob.rho0 * c0 ** 2) * prob.div(u, a))
+    paths = ("fft", "per_axis") if shape[a] <= 4096 else ("fft",)
+    got = {}
+    for path in paths:
+        with Plan(shape, dx, dt, c0, bcs, precision="fp32") as plan:
+            plan.set_path(path)
+            st = plan.new_state(p)
+            for b in range(len(shape)):
+                st.u[b].zero_()
+            plan.apply_axis(st, a, 0)
+            torch.cuda.synchronize()
+            got[(path, 0)] = st.u[a].double().cpu().numpy()
+            st = plan.new_state(np.zeros(shape))
+            st.u[a].copy_(torch.from_numpy(u).to(st.u[a].dtype))
+            plan.apply_axis(st, a, 1)
+            torch.cuda.synchronize()
+            got[(path, 1)] = st.p.double().cpu().numpy()
+    for which in (0, 1):
+        e = rel_l2(got[("fft", which)], refs[which])
+        print("axis", a, "which", which, "rel_l2", e, flush=True)
+        assert e < 2e-6
+        if "per_axis" in paths:
+            assert rel_l2(got[("per_axis", which)], refs[which]) < 2e-6
+            assert not np.array_equal(got[("fft", which)], got[("per_axis", which)])
