@@ -84,6 +84,21 @@ def test_argument_errors_need_no_device():
     assert b"nodes" in lib.pstd_last_error()
 
 
+def test_periodic_axis_size_limits_need_no_device():
+    # a periodic axis above 4097 points runs only on the FFT path: a power of two up to 8192 with a float
+    # state; every other case is refused before any device work
+    lib = _lib.load()
+    h = C.c_void_p()
+    P = opstd.PERIODIC
+    dx, c0 = 1e-4, 1500.0
+    dt = 0.1 * dx / c0
+    for n, prec in ((8193, _lib.FP32), (12288, _lib.FP32), (16384, _lib.FP32), (8192, _lib.FP64)):
+        st = lib.pstd_plan_create_ex(C.byref(_grid((n, 8))), dx, dt, c0, _faces(P, P, N, D), 1000.0, prec, None,
+                                     None, C.byref(h))
+        assert st == _lib.E_UNSUPPORTED, (n, prec)
+        assert b"periodic" in lib.pstd_last_error()
+
+
 @pytest.mark.parametrize("shape,bcs", [((65,), (N, N)), ((33, 40), (N, N, D, N)), ((20, 20, 20), (N, D, D, D, N, N))])
 def test_stability_limit_enforced(shape, bcs):
     lib = _lib.load()

@@ -150,3 +150,26 @@ def test_pow2_kernel_periodic_axes(shape, bcs):
         if "per_axis" in paths:
             assert rel_l2(got[("per_axis", which)], refs[which]) < 2e-6
             assert not np.array_equal(got[("fft", which)], got[("per_axis", which)])
+
+
+@pytest.mark.parametrize("shape,bcs,steps", [((512, 96), ((P, P), (N, D)), 60),
+                                             ((64, 48, 256), ((D, N), (N, N), (P, P)), 30)])
+def test_pow2_kernel_periodic_steps(shape, bcs, steps):
+    # full steps with a periodic axis on the FFT path and wall-bounded axes on the dense path, against the
+    # oracle's run of the same steps
+    import workloads
+    from gpu_helpers import oracle_problem, run_gpu
+
+    print("case", shape, bcs, steps, flush=True)
+    dx, c0 = 1e-3, 1500.0
+    dt = (0.25 if len(shape) == 2 else 0.2) * dx / c0
+    centre = tuple(s * dx / 2.2 for s in shape)
+    p0 = workloads.gaussian(shape, dx, centre, 5 * dx)
+    case = workloads.Case("pow2_periodic", shape, bcs, dx, dt, c0, steps, p0)
+    ref_p, ref_u = oracle_problem(case).run(p0, steps)
+    got_p, got_u = run_gpu(case, precision="fp32", path="fft")
+    e = rel_l2(got_p, ref_p)
+    print("rel_l2 p", e, "u", [rel_l2(g, r) for g, r in zip(got_u, ref_u)], flush=True)
+    assert e < 1e-5
+    for g, r in zip(got_u, ref_u):
+        assert rel_l2(g, r) < 1e-5
