@@ -735,6 +735,20 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
         k = e / W;
       }
     }
+    // the position of element e + NT (n >= N: at most NT / N + 1 wraps to the next line)
+    __device__ void next(int n) {
+      if (CONTIG) {
+        k += C::NT;
+#pragma unroll
+        for (int i = 0; i < (C::NT + N - 1) / N; ++i) {
+          const bool w = k >= n;
+          k -= w ? n : 0;
+          c += w ? 1 : 0;
+        }
+      } else {
+        k += C::NT / W;
+      }
+    }
   };
   auto in_off = [&](int c, int k) { return CONTIG ? c * nin + k : k * ld + c; };
   auto out_off = [&](int c, int m) { return CONTIG ? c * nout + m : m * ld + c; };
@@ -773,13 +787,10 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   {
     // positions recomputed, not kept live across the loads
     float* zs = reinterpret_cast<float*>(z);
-    const int t0 = fresh(tid);
+    Pos p(fresh(tid), nin, inv_nin);
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = t0 + u * C::NT;
-      const Pos p(e, nin, inv_nin);
-      if (e < W * nin) zs[2 * ((p.c >> 1) * L + sw(p.k)) + (p.c & 1)] = xv[u];
-    }
+    for (int u = 0; u < EPT; ++u, p.next(nin))
+      if (p.c < W && p.k < nin) zs[2 * ((p.c >> 1) * L + sw(p.k)) + (p.c & 1)] = xv[u];
   }
   lds_barrier();
 
@@ -886,10 +897,10 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
 #pragma unroll
   for (int u = 0; u < EPT; ++u) asm volatile("" : "+v"(yv[u]));   // widened to FP64 here, not at the load
   const int tid4 = fresh(tid3);
+  Pos p(tid4, nout, inv_nout);
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
+  for (int u = 0; u < EPT; ++u, p.next(nout)) {
     const int e = tid4 + u * C::NT;
-    const Pos p(e, nout, inv_nout);
     const int c = p.c, m = p.k;
     if (c < nl && m < nout) {
       const int off = CONTIG ? e : out_off(c, m);
