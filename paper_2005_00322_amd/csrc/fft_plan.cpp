@@ -60,8 +60,8 @@ int fft_axis_setup(pstd_plan_s* P, int a, double sG, double sD) {
   const bool per = P->bc[2 * a] == PSTD_PERIODIC;
   if (half_wall(P->bc[2 * a + 1])) return PSTD_OK;   // dense path only
   if (per) {
-    // a periodic axis is its own period: L = n, the Fourier modes of §3.2's periodic case; only the FP32
-    // power-of-two kernel takes it
+    // a periodic axis is its own period: L = n, the Fourier modes of Eq. (fourier_pstd_solution); only the
+    // power-of-two kernel (float state) takes it
     if (P->prec == PSTD_FP64 || fft_pow2_lines(n) == 0) return PSTD_OK;
   } else if (!fft_axis_possible(n, P->prec)) {
     return PSTD_OK;

@@ -533,7 +533,7 @@ hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
 //   passes   radix 16, then one radix 2, 4 or 8 pass for the remaining factor; thread t of a transform
 //            holds entries t + s L/16 (s < 16) at the start of the first pass and at the end of the last;
 //   tables   formed in FP64 on the host and rounded once: per pass after the first, w, w^2, w^4, w^8 for
-//            w = W_{Ns R}^{j mod Ns} (the other powers as products of at most three of them); per thread
+//            w = W_{Ns R}^{j mod Ns} (the other powers as products of at most four of them); per thread
 //            t < L/16, e^{i pi (2t + a)/(2L)} (a = 1 for mixed walls) for the spectral multiplier and
 //            e^{-i pi t/L} for the mixed-wall pre-twiddle.  The entries t + s L/16 add a factor
 //            e^{+-i pi s/16} (constants) to these;
@@ -542,8 +542,9 @@ hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
 //            conj(H X) and that inverse pass follow in registers; the conjugation (and post-twiddle) is
 //            applied as the last inverse pass writes;
 //   memory   every thread issues all its loads of the input lines at once, and of the old output values
-//            at once, without branches; on unit-stride axes the old output values are loaded with the
-//            input (their loads overlap), on strided ones in the epilogue (registers).
+//            at once, without branches; on unit-stride axes with walls the old output values are loaded
+//            with the input (their loads overlap), on strided and periodic ones in the epilogue
+//            (registers).
 template <int LG>
 struct Pow2 {
   static constexpr int L = 1 << LG, N = L / 2, Q = L / 16;
@@ -692,6 +693,7 @@ __device__ __forceinline__ void pow2_gather(const f2v (&v)[16], f2v (&u)[16]) {
     for (int r = 0; r < R; ++r) u[b + r * NB] = v[b * R + r];
 }
 
+// (second bound: waves per SIMD the registers are planned for, five 4-wave blocks per CU up to L = 4096)
 template <int LG, bool CONTIG, bool PER>
 __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kernel(FftArgs a) {
   typedef Pow2<LG> C;
@@ -753,7 +755,8 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   auto in_off = [&](int c, int k) { return CONTIG ? c * nin + k : k * ld + c; };
   auto out_off = [&](int c, int m) { return CONTIG ? c * nout + m : m * ld + c; };
 
-  // ---- loads: the input lines and the old output values (W lines of at most N + 1 values: 17 per thread)
+  // ---- loads: the input lines and the old output values (W lines of at most N + 1 values, 17 per thread;
+  // L values and 32 per thread on a periodic axis)
   const bool read_y = a.beta != 0.0;
   // every thread issues all its loads (an element past the lines reads the group's first element and
   // is dropped), so no load waits behind a branch
