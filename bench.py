@@ -92,13 +92,20 @@ def fft_factorable(n):
 
 def uses_fft(shape, axis, precision, periodic=False):
     """Mirrors the library's automatic choice: wall-bounded axes above 512 nodes (1D: above 1365) with
-    2(n-1) = 16 x 2^a 3^b 5^c run on the FFT path; periodic axes always take the dense path."""
-    if periodic:
-        return False
+    2(n-1) = 16 x 2^a 3^b 5^c run on the FFT path, and so do periodic axes of a float state whose n is a
+    power of two up to 8192; other periodic axes take the dense path."""
     n = shape[axis]
     lim = 1365 if len(shape) == 1 else 512
+    if periodic:
+        return precision != "fp64" and lim < n <= 8192 and n & (n - 1) == 0
     cap = 8192 if precision == "fp64" else 16384
     return n > lim and fft_factorable(n) and 2 * (n - 1) <= cap
+
+
+def uses_step1d(shape, precision, periodic):
+    """Mirrors the library: 1D plans with walls on nodes, at most 1365 nodes and off the FFT path run the
+    whole time loop in one workgroup (one launch per pstd_step call)."""
+    return len(shape) == 1 and not periodic[0] and shape[0] <= 1365 and not uses_fft(shape, 0, precision)
 
 
 def contraction_cost(shape, axis, which, precision, periodic=False):
@@ -1234,6 +1241,27 @@ def main():
     # axes with n staggered points: periodic, or a right wall half a step beyond the last node
     periodic = [l == 2 or r in (3, 4) for l, r in case.bcs]
     fused = uses_fused_path(case.shape, precision)
+    if uses_step1d(case.shape, precision, periodic):
+        # one workgroup runs the whole time loop: its two matrix-vector products per step are FP64
+        # vector FMAs on one CU (operators held in registers or streamed from L2, the state in LDS), so
+        # the bound is that CU's FP64 vector rate and no HBM traffic is made per step
+        n = case.shape[0]
+        flops = 4.0 * n * (n - 1)
+        step_ms = elapsed / K * 1e3
+        peak_cu = PEAK["fp64_TFs"] / 256
+        tfs = flops / (step_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(tfs, 5), "peak": round(peak_cu, 4), "unit": "TFLOP/s",
+                "frac": round(tfs / peak_cu, 4), "traffic": None,
+                "kernel": "step1d (one launch for all steps; per step)", "avg_ms": round(step_ms, 6),
+                "algorithmic_bytes": 0, "algorithmic_flops": int(flops),
+                "peak_basis": "FP64 vector FMA rate of one CU (78.6 TFLOP/s / 256 CUs)"}
+        plan.close()
+        cpu = err = None
+        if not args.no_cpu_baseline:
+            cpu, err = cpu_baseline_leg(case, p_final, W + K)
+        print(json.dumps(single_grid_line(case, precision, value, K, W, elapsed, err, roof, cpu,
+                                          kernel_source_hash(args.workload))))
+        return
     if fused:
         durs = time_fused_phases(case, precision)
     else:
@@ -1271,8 +1299,13 @@ def main():
     if not args.no_cpu_baseline:
         cpu, err = cpu_baseline_leg(case, p_final, W + K)
 
+    print(json.dumps(single_grid_line(case, precision, value, K, W, elapsed, err, roof, cpu, src_hash)))
+
+
+def single_grid_line(case, precision, value, K, W, elapsed, err, roof, cpu, src_hash):
+    """The JSON line of a single-grid workload."""
     dtype = {"fp32": "f32", "fp64": "f64", "split_bf16": "bf16x3->f32"}[precision]
-    line = {
+    return {
         "metric": "grid-point updates/s at stated L2 err vs FP64 oracle",
         "value": value,
         "unit": "grid-point updates/s",
@@ -1294,7 +1327,6 @@ def main():
         "cpu_baseline": cpu,
         "kernel_source_hash": src_hash,
     }
-    print(json.dumps(line))
 
 
 if __name__ == "__main__":

@@ -55,6 +55,53 @@ __global__ __launch_bounds__(1024) void step1d_kernel(const T* __restrict__ GT, 
   for (int i = tid; i < n - 1; i += nt) u[i] = su[i];
 }
 
+// The same time loop for n <= 128 with both operators in registers for all steps: thread t owns row
+// t / 8 of each operator and its 16 entries in columns 16 (t % 8) .. 16 (t % 8) + 15, so a step reads no
+// global memory.  A row's eight partial dot products are added across its eight lanes (xor shuffles, a
+// fixed order); the state vectors live in LDS.  Per step: u += G~ p, a barrier, p += D~ u (times c0(x)^2
+// with a map), a barrier.  Sums and updates in FP64, rounded once into the state, as above.
+template <typename T>
+__global__ __launch_bounds__(1024) void step1d_reg_kernel(const T* __restrict__ G, int ldg, const T* __restrict__ D,
+                                                          int ldd, T* __restrict__ p, T* __restrict__ u, int n,
+                                                          int64_t steps, const T* __restrict__ scale) {
+  __shared__ T sp[128], su[128];
+  const int tid = threadIdx.x, i = tid >> 3, q = tid & 7;
+  const int nm = n - 1;
+  T g[16], d[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = 16 * q + j;
+    g[j] = (i < nm && k < n) ? G[static_cast<int64_t>(i) * ldg + k] : T(0);
+    d[j] = (i < n && k < nm) ? D[static_cast<int64_t>(i) * ldd + k] : T(0);
+  }
+  const double sc = (scale && i < n) ? static_cast<double>(scale[i]) : 1.0;
+  if (tid < 128) {
+    sp[tid] = tid < n ? p[tid] : T(0);
+    su[tid] = tid < nm ? u[tid] : T(0);
+  }
+  __syncthreads();
+  for (int64_t s = 0; s < steps; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc += static_cast<double>(g[j]) * static_cast<double>(sp[16 * q + j]);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (q == 0 && i < nm) su[i] = static_cast<T>(su[i] + acc);
+    __syncthreads();
+    acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc += static_cast<double>(d[j]) * static_cast<double>(su[16 * q + j]);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (q == 0 && i < n) sp[i] = static_cast<T>(sp[i] + acc * sc);
+    __syncthreads();
+  }
+  if (tid < n) p[tid] = sp[tid];
+  if (tid < nm) u[tid] = su[tid];
+}
+
 template <typename T>
 __global__ void zero_dirichlet_kernel(T* p, int ndim, int64_t n0, int64_t n1, int64_t n2, int lo0, int hi0, int lo1,
                                       int hi1, int lo2, int hi2) {
@@ -149,6 +196,17 @@ unsigned blocks_for(int64_t count, int threads) {
 
 hipError_t launch_step1d(int prec, const DevOperator& G, const DevOperator& D, void* p, void* u, int n,
                          int64_t steps, const void* scale, hipStream_t s) {
+  if (n <= 128) {
+    if (prec == PSTD_FP64)
+      hipLaunchKernelGGL(step1d_reg_kernel<double>, dim3(1), dim3(1024), 0, s, static_cast<const double*>(G.data),
+                         G.Kp, static_cast<const double*>(D.data), D.Kp, static_cast<double*>(p),
+                         static_cast<double*>(u), n, steps, static_cast<const double*>(scale));
+    else
+      hipLaunchKernelGGL(step1d_reg_kernel<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(G.data),
+                         G.Kp, static_cast<const float*>(D.data), D.Kp, static_cast<float*>(p),
+                         static_cast<float*>(u), n, steps, static_cast<const float*>(scale));
+    return hipGetLastError();
+  }
   const size_t esz = prec == PSTD_FP64 ? 8 : 4;
   const size_t shmem = ((esz * 2 * static_cast<size_t>(n) + 7) & ~static_cast<size_t>(7)) + 8 * static_cast<size_t>(4) * n;
   if (shmem > 64 * 1024) return hipErrorInvalidConfiguration;
