@@ -59,7 +59,8 @@ typedef enum {
 
 /* Arithmetic of the transform contractions.  FP64: state and operators in double.  FP32: state and
  * operators in float, FP32 accumulation.  SPLIT_BF16: float state; each contraction is
- * A_hi X_hi + A_hi X_lo + A_lo X_hi with bfloat16 hi/lo parts and FP32 accumulation. */
+ * A_hi X_hi + A_hi X_lo + A_lo X_hi with bfloat16 hi/lo parts and FP32 accumulation (2D and 3D grids; a
+ * 1D plan, a single line with no matrix-matrix product, computes as FP32). */
 typedef enum { PSTD_FP64 = 0, PSTD_FP32 = 1, PSTD_SPLIT_BF16 = 2 } pstd_precision;
 
 typedef struct {

@@ -435,8 +435,9 @@ int pstd_plan_create_ex(const pstd_grid* grid, double dx, double dt, double c0, 
       return fail(PSTD_E_UNSUPPORTED,
                   "axis %d: periodic axes above 4097 points need n a power of two up to 8192 and a float state", a);
   }
-  if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16)
-    return fail(PSTD_E_UNSUPPORTED, "split-bf16 contractions are for 2D/3D grids");
+  // a single line has no matrix-matrix product for the bf16 matrix cores: a 1D split-bf16 plan (float
+  // state) computes as an FP32 plan
+  if (grid->ndim == 1 && precision == PSTD_SPLIT_BF16) precision = PSTD_FP32;
   // 1D walls on nodes: the single-workgroup kernel up to 1365 nodes, above that the FFT path where 2(n-1)
   // factors and the dense contraction path otherwise (up to 4097 nodes, checked above)
   int64_t total = 1;

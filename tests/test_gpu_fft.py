@@ -55,8 +55,6 @@ def test_single_operator_application(prec, seed, ndim):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16"])
 @pytest.mark.parametrize("seed,ndim", [(10, 1), (11, 2), (12, 2), (13, 3), (14, 3), (15, 2), (16, 3)])
 def test_steps_forced_fft(prec, seed, ndim):
-    if ndim == 1 and prec == "split_bf16":
-        pytest.skip("split-bf16 plans are 2D/3D")
     case = workloads.fft_small_case(seed, ndim, steps=40)
     _print("case", case.name, case.shape, case.bcs, prec)
     p, u = run_gpu(case, prec, path="fft")

@@ -56,9 +56,8 @@ GRIDS = [
 ]
 
 
-# split-bf16 plans are 2D/3D only
-@pytest.mark.parametrize("prec,seed,shape,bcs", [(p,) + g for p in ("fp64", "fp32", "split_bf16") for g in GRIDS
-                                                 if not (p == "split_bf16" and len(g[1]) == 1)])
+# (a 1D split-bf16 plan computes as FP32)
+@pytest.mark.parametrize("prec,seed,shape,bcs", [(p,) + g for p in ("fp64", "fp32", "split_bf16") for g in GRIDS])
 def test_parity(prec, seed, shape, bcs):
     _run(shape, bcs, prec, seed)
 
