@@ -107,9 +107,10 @@ def test_fft_with_sound_speed_map():
     assert rel_l2(p, po) < TOL["fp32"]
 
 
-@pytest.mark.parametrize("prec,n", [("fp64", 2049), ("fp32", 2049), ("fp32", 4097)])
+@pytest.mark.parametrize("prec,n", [("fp64", 2049), ("fp32", 2049), ("fp32", 4097), ("fp64", 4097), ("fp32", 8193)])
 def test_1d_long_axis(prec, n):
-    # 1D plans above 1365 nodes run on the FFT path
+    # 1D plans above 1365 nodes run on the FFT path; 4097 (FP64) and 8193 (FP32) are the largest a plan
+    # takes there (transforms of 8192 and 16384 points, one per block in more than 64 KB of LDS)
     dx, c0 = 1e-4, 1500.0
     bcs = ((N, D),)
     p0 = workloads.gaussian((n,), dx, (0.37 * n * dx,), 8 * dx)
