@@ -701,7 +701,7 @@ def surrogate_speedup(args, B=256):
             "solver_steps": workloads.NOP_STEPS, "weights": os.path.basename(wpath),
             "accuracy": {"rel_l2_vs_fp32_pstd": {"mean": float(err.mean()), "median": float(np.median(err)),
                                                  "p95": float(np.quantile(err, 0.95))},
-                         "note": "the FP32 batched solver is the judge; it matches the FP64 oracle to 2e-6"},
+                         "note": "errors are against the FP32 batched solver, which matches the FP64 oracle to 2e-6"},
             "coarse_pstd": coarse,
             "vs_coarse_pstd_at_matched_p95": None if match is None else {
                 "grid": match["grid"], "coarse_ms": match["solve_ms"] + match["resample_ms"],
@@ -1156,7 +1156,7 @@ def run_nop(args, K, W):
                    "trained_pairs": int(d["train"]), "trained_epochs": int(d["epochs"]), "parallelism": "single-gpu"},
         "accuracy": {"rel_l2_vs_fp32_pstd": {"mean": float(err.mean()), "median": float(np.median(err)),
                                              "p95": float(np.quantile(err, 0.95))},
-                     "note": "the FP32 batched solver is the judge; it matches the FP64 oracle to 2e-6"},
+                     "note": "errors are against the FP32 batched solver, which matches the FP64 oracle to 2e-6"},
         "surrogate_speedup": {"vs_batched_fp32_pstd": t_pstd / t_nop, "pstd_s": t_pstd, "surrogate_s": t_nop,
                               "sample": "the same 256 inputs, %d steps each" % workloads.NOP_STEPS},
         # flops / bytes is about 33, far below the bf16 ridge (2500 / 8 = 312): bound by HBM

@@ -307,7 +307,7 @@ int pstd_batch_destroy(pstd_batch batch);
 /* ---- DCT-basis neural-operator surrogate -------------------------------------------------------------
  * Not a method of the paper: a learned map from (p0, c0 map) on an H x W grid to the pressure after a
  * fixed number of PSTD steps, trained on fields the solver produces; the solver remains its fallback and
- * the judge of its error.  Network (all parameters FP32, contractions on bf16 matrix cores with FP32
+ * the reference for its error.  Network (all parameters FP32, contractions on bf16 matrix cores with FP32
  * accumulation):
  *   features f = [p0, (c0 - 1500)/100, x, y] with x = i/(H-1), y = j/(W-1)
  *   lift     v = P f + pb                                   P: C x 4
@@ -388,7 +388,7 @@ typedef struct {
  * stability limit from the map's maximum), whose pressure is stepped in place in out.  fallback (host,
  * batch entries, nullable) receives 1 for solver answers; n_fallback (nullable) their count.
  * Synchronous; allocates the fallback solves' velocity buffers for the duration of the call.
- * Not a method of the paper: the solver remains the surrogate's fallback and the judge of its error. */
+ * Not a method of the paper: the solver remains the surrogate's fallback and the reference for its error. */
 int pstd_nop_predict(pstd_nop nop, const pstd_nop_gate* gate, const pstd_nop_problem* problem, const float* p0,
                      const float* c0, float* out, int32_t batch, double tol, int32_t* fallback, int32_t* n_fallback);
 

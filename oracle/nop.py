@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Not a method of the paper: the surrogate is an extension whose training data and error judge are the
+Not a method of the paper: the surrogate is an extension whose training data and error reference are the
 PSTD solver of §4.  The network maps an initial pressure p0 and a sound-speed map c0 on an H x W grid to
 the pressure after a fixed number of steps:
 

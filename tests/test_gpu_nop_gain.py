@@ -3,7 +3,7 @@
 The shipped network (weights/) against FP32 PSTD of the same 128 held-out inputs on coarser grids of the
 same box (the accuracy-versus-cost knob of the convergence study, §4.2): inputs resampled spectrally onto
 m x m nodes, the coarse solve over the same final time, its result evaluated back on the 128 x 128 nodes,
-both judged against the fine FP32 solver.  The coarse error falls as the grid is refined; the cheapest
+both measured against the fine FP32 solver.  The coarse error falls as the grid is refined; the cheapest
 coarse grid whose 95th-percentile error is at or below the surrogate's takes longer than the surrogate's
 inference of the same batch.
 """
