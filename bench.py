@@ -102,6 +102,23 @@ def uses_fft(shape, axis, precision, periodic=False):
     return n > lim and fft_factorable(n) and 2 * (n - 1) <= cap
 
 
+def uses_fft_velocity_launch(shape, bcs, precision):
+    """Mirrors the library: when every axis of a 2D/3D float plan runs on the power-of-two FFT kernel with
+    one transform length (all periodic or none), a step launches the velocity terms of all axes as one."""
+    if len(shape) < 2 or precision == "fp64":
+        return False
+    kinds = set()
+    for a, (n, (l, r)) in enumerate(zip(shape, bcs)):
+        if r in (3, 4):
+            return False                     # a wall half a step beyond the last node: dense path
+        per = l == 2
+        L = n if per else 2 * (n - 1)
+        if not (uses_fft(shape, a, precision, per) and 256 <= L <= 8192 and L & (L - 1) == 0):
+            return False
+        kinds.add((L, per))
+    return len(kinds) == 1
+
+
 def uses_step1d(shape, precision, periodic):
     """Mirrors the library: 1D plans with walls on nodes, at most 1365 nodes and off the FFT path run the
     whole time loop in one workgroup (one launch per pstd_step call)."""
@@ -156,16 +173,17 @@ def uses_fused_path(shape, precision):
     return len(shape) == 2 and precision == "fp32" and max(shape) <= 512
 
 
-def time_dominant_kernel(plan, st, fused, reps=50):
+def time_dominant_kernel(plan, st, fused, reps=50, velocity_launch=False):
     """Average duration (ms) of each kernel launch of the step, timed with events on the plan's stream.
 
-    Keys are (axis, which); axis -1 is a fused phase kernel covering every axis.
+    Keys are (axis, which); axis -1 is one launch covering every axis (a fused phase kernel, or with
+    velocity_launch the FFT velocity terms of all axes).
     """
     import torch
     stream = plan._stream
     out = {}
     for which in (0, 1):
-        for a in ([-1] if fused else range(plan.ndim)):
+        for a in ([-1] if fused or (velocity_launch and which == 0) else range(plan.ndim)):
             plan.apply_axis(st, a, which)          # warm
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -1262,12 +1280,13 @@ def main():
         print(json.dumps(single_grid_line(case, precision, value, K, W, elapsed, err, roof, cpu,
                                           kernel_source_hash(args.workload))))
         return
+    vel_fft = uses_fft_velocity_launch(case.shape, case.bcs, precision)
     if fused:
         durs = time_fused_phases(case, precision)
     else:
         state_copy = plan.new_state(case.p0)
         plan.init_state(state_copy)
-        durs = time_dominant_kernel(plan, state_copy, fused)
+        durs = time_dominant_kernel(plan, state_copy, fused, velocity_launch=vel_fft)
     (axis, which), dur_ms = max(durs.items(), key=lambda kv: kv[1])
     if axis < 0:
         flops, bytes_ = phase_cost(case.shape, which, precision, periodic)
@@ -1276,13 +1295,15 @@ def main():
     gbs = bytes_ / (dur_ms * 1e-3) / 1e9
     tfs = flops / (dur_ms * 1e-3) / 1e12
     peak_c = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"], "split_bf16": PEAK["bf16_TFs"]}[precision]
-    if axis >= 0 and uses_fft(case.shape, axis, precision, periodic[axis]):
+    fft_launch = (axis >= 0 and uses_fft(case.shape, axis, precision, periodic[axis])) or (axis < 0 and vel_fft)
+    if fft_launch:
         peak_c = PEAK["fp64_TFs"] if precision == "fp64" else PEAK["fp32_TFs"]   # FFT butterflies: vector ALU
     ai = flops / bytes_
     ridge = peak_c * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     src_hash = kernel_source_hash(args.workload)
-    key = ("fused" if axis < 0 else "axis%d" % axis) + "_" + ("velocity" if which == 0 else "pressure")
-    if axis >= 0 and uses_fft(case.shape, axis, precision, periodic[axis]):
+    key = ("all_axes" if axis < 0 and vel_fft else "fused" if axis < 0 else "axis%d" % axis) + "_" + \
+        ("velocity" if which == 0 else "pressure")
+    if fft_launch:
         key += "_fft"
     traffic = load_traffic(args.workload, key, src_hash)
     if ai < ridge:

@@ -154,8 +154,10 @@ int pstd_plan_set_path(pstd_plan plan, int32_t path);
  * u_a += -(dt/rho0) G_a p (Eq. (dtt_pstd_solution_a) along that axis); which = 1 applies that axis's share
  * of the pressure update, p += -(dt rho0 c0^2) D_a u_a (one summand of Eq. (dtt_pstd_solution_b) in the
  * form of §4.3).  A full step is every which = 0 term followed by every which = 1 term.  axis = -1
- * applies the whole phase (every axis) the way pstd_step does it: one kernel on the FUSED path, one per
- * axis otherwise.  Asynchronous on the plan's stream; state->step is not changed. */
+ * applies the whole phase (every axis) the way pstd_step does it: one kernel on the FUSED path; one for
+ * the velocity terms of all axes when every axis runs on the FFT path with one power-of-two transform
+ * length (float state); one per axis otherwise.  Asynchronous on the plan's stream; state->step is not
+ * changed. */
 int pstd_apply_axis(pstd_plan plan, pstd_state* state, int32_t axis, int32_t which);
 
 /* p_out = (1+R)/2 * p_neumann + (1-R)/2 * p_dirichlet, elementwise over count floats.

@@ -239,13 +239,13 @@ hipError_t contract(const pstd_plan_s* P, const DevOperator& op, int a, const vo
   return launch_contract_split(c, contiguous, s);
 }
 
-// Y = beta Y + alpha scale (op X) along axis a with the velocity (which = 0) or pressure (which = 1)
-// operator, on the axis's FFT or dense path.
-hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void* Y, double alpha, double beta,
-                    const void* scale, hipStream_t s) {
-  if (!axis_fft(P, a)) return contract(P, which == 0 ? P->G[a] : P->D[a], a, X, Y, alpha, beta, scale, s);
+// The launch arguments of Y = beta Y + alpha scale (op X) along FFT axis a; true when the axis runs on the
+// power-of-two kernel.
+bool fft_args(const pstd_plan_s* P, int a, int which, const void* X, void* Y, double alpha, double beta,
+              const void* scale, FftArgs* out) {
   const FftAxis& f = P->fft[a];
-  FftArgs x{};
+  FftArgs& x = *out;
+  x = FftArgs{};
   x.X = X;
   x.Y = Y;
   x.scale = scale;
@@ -300,7 +300,30 @@ hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void*
     x.y_bstride = static_cast<int64_t>(x.nout) * inner;
   }
   x.xcd_spread = x.groups >= 64;
-  return pow2 ? launch_fft_pow2(x, s) : launch_fft_axis(P->prec == PSTD_FP64, x, s);
+  return pow2;
+}
+
+// Y = beta Y + alpha scale (op X) along axis a with the velocity (which = 0) or pressure (which = 1)
+// operator, on the axis's FFT or dense path.
+hipError_t apply_op(const pstd_plan_s* P, int a, int which, const void* X, void* Y, double alpha, double beta,
+                    const void* scale, hipStream_t s) {
+  if (!axis_fft(P, a)) return contract(P, which == 0 ? P->G[a] : P->D[a], a, X, Y, alpha, beta, scale, s);
+  FftArgs x;
+  return fft_args(P, a, which, X, Y, alpha, beta, scale, &x) ? launch_fft_pow2(x, s)
+                                                                : launch_fft_axis(P->prec == PSTD_FP64, x, s);
+}
+
+// The velocity half step of every axis as one launch when all of them run on the power-of-two FFT
+// kernel with one transform length (each reads p and writes its own u_a); false: not applicable.
+bool velocity_fft_multi(const pstd_plan_s* P, pstd_state* st, hipStream_t s, hipError_t* err) {
+  if (P->ndim < 2) return false;
+  FftArgs x[3];
+  for (int a = 0; a < P->ndim; ++a) {
+    if (!axis_fft(P, a) || !fft_args(P, a, 0, st->p, st->u[a], 1.0, 1.0, nullptr, &x[a])) return false;
+    if (x[a].L != x[0].L || x[a].periodic != x[0].periodic) return false;
+  }
+  *err = launch_fft_pow2_multi(x, P->ndim, s);
+  return true;
 }
 
 bool use_fused2d(const pstd_plan_s* P) {
@@ -317,12 +340,17 @@ hipError_t enqueue_steps(pstd_plan_s* P, pstd_state* st, int64_t nsteps, hipStre
                           static_cast<const float*>(P->c2map), static_cast<int>(P->n[0]), static_cast<int>(P->n[1]),
                           nsteps, s);
   for (int64_t t = 0; t < nsteps; ++t) {
-    for (int a = 0; a < P->ndim; ++a) {
-      hipError_t e = apply_op(P, a, 0, st->p, st->u[a], 1.0, 1.0, nullptr, s);
+    hipError_t e = hipSuccess;
+    if (velocity_fft_multi(P, st, s, &e)) {
       if (e != hipSuccess) return e;
+    } else {
+      for (int a = 0; a < P->ndim; ++a) {
+        e = apply_op(P, a, 0, st->p, st->u[a], 1.0, 1.0, nullptr, s);
+        if (e != hipSuccess) return e;
+      }
     }
     for (int a = 0; a < P->ndim; ++a) {
-      hipError_t e = apply_op(P, a, 1, st->u[a], st->p, 1.0, 1.0, P->c2map, s);
+      e = apply_op(P, a, 1, st->u[a], st->p, 1.0, 1.0, P->c2map, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -628,6 +656,13 @@ int pstd_apply_axis(pstd_plan P, pstd_state* st, int32_t axis, int32_t which) {
                                   static_cast<float*>(st->u[0]), static_cast<float*>(st->u[1]),
                                   static_cast<const float*>(P->c2map), static_cast<int>(P->n[0]),
                                   static_cast<int>(P->n[1]), P->stream));
+      return PSTD_OK;
+    }
+    const int pst = prepare_axes(P);
+    if (pst != PSTD_OK) return pst;
+    hipError_t e = hipSuccess;
+    if (which == 0 && velocity_fft_multi(P, st, P->stream, &e)) {
+      PSTD_HIP(e);
       return PSTD_OK;
     }
     for (int a = 0; a < P->ndim; ++a) {

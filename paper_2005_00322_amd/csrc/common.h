@@ -245,6 +245,9 @@ hipError_t launch_fft_axis(bool dbl, const FftArgs& a, hipStream_t s);
 // its launch (F = lines / 2 transforms per block, tables tw, h, pre set)
 int fft_pow2_lines(int L);
 hipError_t launch_fft_pow2(const FftArgs& a, hipStream_t s);
+// the launches of up to three axes as one (one transform length, all periodic or none; each a[i] as for
+// launch_fft_pow2); the axes must write different outputs
+hipError_t launch_fft_pow2_multi(const FftArgs* a, int count, hipStream_t s);
 
 // ---- neural-operator surrogate (kernels_nop.hip, capi_nop.hip) ----------------------------------------
 // C[z] = alpha A[z] B[z] (+ beta C[z]) (+ bias_m[m]) (+ D[z]) (* GELU'(dgelu[z])), then with act set

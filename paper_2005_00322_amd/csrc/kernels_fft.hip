@@ -543,8 +543,10 @@ hipError_t launch_typed(const FftArgs& a, hipStream_t s) {
 //            applied as the last inverse pass writes;
 //   memory   every thread issues all its loads of the input lines at once, and of the old output values
 //            at once, without branches; on unit-stride axes with walls the old output values are loaded
-//            with the input (their loads overlap), on strided and periodic ones in the epilogue
-//            (registers).
+//            with the input (their loads overlap; all but the last one to four per thread, which would
+//            spill), on strided and periodic ones in the epilogue (registers);
+//   launches one per axis, or the velocity terms of every axis of a step in one launch (below): the
+//            blocks of the slower strided axes first, then the unit-stride ones fill the CUs as those end.
 template <int LG>
 struct Pow2 {
   static constexpr int L = 1 << LG, N = L / 2, Q = L / 16;
@@ -693,9 +695,10 @@ __device__ __forceinline__ void pow2_gather(const f2v (&v)[16], f2v (&u)[16]) {
     for (int r = 0; r < R; ++r) u[b + r * NB] = v[b * R + r];
 }
 
-// (second bound: waves per SIMD the registers are planned for, five 4-wave blocks per CU up to L = 4096)
+// One block of a launch over the line groups of one axis: block `blk` of `nblk` (nblk a multiple of 8
+// when the groups are spread per XCD).
 template <int LG, bool CONTIG, bool PER>
-__global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kernel(FftArgs a) {
+__device__ __forceinline__ void fft_pow2_block(const FftArgs& a, unsigned blk, unsigned nblk) {
   typedef Pow2<LG> C;
   constexpr int L = C::L, N = C::N, Q = C::Q, W = 2 * C::F, EPT = PER ? C::EPT_PER : C::EPT;
   // the old output values load with the input where they fit the registers (unit stride, walls)
@@ -703,8 +706,8 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   f2v* z = reinterpret_cast<f2v*>(smem);
   const f2v* tw = static_cast<const f2v*>(a.tw);
-  int64_t grp = blockIdx.x;
-  if (a.xcd_spread) grp = static_cast<int64_t>(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  int64_t grp = blk;
+  if (a.xcd_spread) grp = static_cast<int64_t>(blk % 8) * (nblk / 8) + blk / 8;
   if (grp >= a.groups) return;
   const int tid = threadIdx.x;
   int64_t b = 0, l0;
@@ -778,11 +781,14 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
     const float t = X[ok ? off : 0];
     xv[u] = ok ? t : 0.0f;
   }
+  // (the first YP of each thread's values; the rest, among them the last, which only a few threads of a
+  // group hold, load in the epilogue: fewer registers through the transforms, where they would spill)
+  constexpr int YP = LG >= 12 ? EPT - 1 : EPT - 4;
   float yv[EPT];
   if (YPRE) {
     const int t0 = fresh(tid);
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
+    for (int u = 0; u < YP; ++u) {
       const int e = t0 + u * C::NT;
       yv[u] = read_y ? Y[e < cout ? e : 0] : 0.0f;
     }
@@ -800,8 +806,8 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   const int f = tid / Q, jt = tid & (Q - 1);
   const int slot = f * L;
   const int A = slot + sw(jt);   // slot + sw(jt): the layout of transform f
-  // the multiplier's and the pre-twiddle's per-thread factors
-  const f2v hb = static_cast<const f2v*>(a.h)[jt];
+  // the pre-twiddle's per-thread factor (loaded again where it is used last, and the multiplier's just
+  // before it is used: neither is kept in registers through the passes)
   const f2v pb = a.anti ? static_cast<const f2v*>(a.pre)[jt] : f2v{1.f, 0.f};
   f2v v[16];
   // ---- first forward pass: extension (mirror about the right wall, sign sR for G, -sR for D; Dirichlet
@@ -843,6 +849,7 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
     // walls), sigma = +1 (G) or -1 (D): the signed frequency 2 m_k = t + s L/8 folded by -2L (which flips
     // the phase's sign) from s = 8 on, g_k = |2 m_k| kfac / 2
     const float sgm = a.dir == 0 ? 1.0f : -1.0f;
+    const f2v hb = static_cast<const f2v*>(a.h)[fresh(jt)];
     const f2v B = f2v{hb.x, sgm * hb.y};
     // kfac / 2 as a pair of floats: each g_k is rounded once, not every mode scaled by one rounded factor
     const double khd = 0.5 * a.kfac;
@@ -868,9 +875,10 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
     f2v u[16];
     pow2_gather<LG>(v, u);
     if (a.anti) {
+      const f2v pb2 = static_cast<const f2v*>(a.pre)[fresh(jt)];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        const f2v t = cmul(pb, f2v{kC32[s], -kS32[s]});   // e^{-i pi j / L}; the post-twiddle is its conjugate
+        const f2v t = cmul(pb2, f2v{kC32[s], -kS32[s]});   // e^{-i pi j / L}; the post-twiddle is its conjugate
         u[s] = f2v{u[s].x * t.x - u[s].y * t.y, -(u[s].x * t.y + u[s].y * t.x)};   // conj(u) conj(t)
       }
     } else {
@@ -889,7 +897,13 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   // positions recomputed from an opaque thread index: the compiler would otherwise keep the load phase's
   // offsets live through the transforms
   const int tid3 = fresh(tid);
-  if (!YPRE) {
+  if (YPRE) {
+#pragma unroll
+    for (int u = YP; u < EPT; ++u) {
+      const int e = tid3 + u * C::NT;
+      yv[u] = read_y ? Y[e < cout ? e : 0] : 0.0f;
+    }
+  } else {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const Pos p(tid3 + u * C::NT, nout, inv_nout);
@@ -918,13 +932,39 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
   }
 }
 
+// (second bound: waves per SIMD the registers are planned for, five 4-wave blocks per CU up to L = 4096)
+template <int LG, bool CONTIG, bool PER>
+__global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kernel(FftArgs a) {
+  fft_pow2_block<LG, CONTIG, PER>(a, blockIdx.x, gridDim.x);
+}
+
+// Several axes of one half step in one launch (transforms of one length, all periodic or none): the
+// blocks of axis i follow those of axes 0 .. i-1, each axis's range padded to a multiple of eight
+// blocks so that its line groups spread over the XCDs as in a launch of its own.  Blocks of different
+// axes then share the CUs, and the scheduler places the later ones where the earlier ones finish.
+struct FftMulti {
+  FftArgs a[3];
+  unsigned end[3];   // one past the last block of axis i
+  int count;
+};
+
+template <int LG, bool PER>
+__global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_multi_kernel(FftMulti m) {
+  unsigned blk = blockIdx.x, lo = 0;
+  int i = 0;
+  while (i + 1 < m.count && blk >= m.end[i]) lo = m.end[i++];
+  const FftArgs& a = m.a[i];
+  if (a.contig) fft_pow2_block<LG, true, PER>(a, blk - lo, m.end[i] - lo);
+  else fft_pow2_block<LG, false, PER>(a, blk - lo, m.end[i] - lo);
+}
+
+int64_t pow2_blocks(const FftArgs& a) { return a.xcd_spread ? round_up(a.groups, 8) : a.groups; }
+
 template <int LG>
 hipError_t launch_pow2(const FftArgs& a, hipStream_t s) {
   typedef Pow2<LG> C;
   const size_t shm = static_cast<size_t>(C::F) * C::L * sizeof(f2v);
-  int64_t blocks = a.groups;
-  if (a.xcd_spread) blocks = round_up(blocks, 8);
-  const dim3 g(static_cast<unsigned>(blocks)), t(C::NT);
+  const dim3 g(static_cast<unsigned>(pow2_blocks(a))), t(C::NT);
   if (a.periodic) {
     if (a.contig) hipLaunchKernelGGL((fft_pow2_kernel<LG, true, true>), g, t, shm, s, a);
     else hipLaunchKernelGGL((fft_pow2_kernel<LG, false, true>), g, t, shm, s, a);
@@ -932,6 +972,16 @@ hipError_t launch_pow2(const FftArgs& a, hipStream_t s) {
     if (a.contig) hipLaunchKernelGGL((fft_pow2_kernel<LG, true, false>), g, t, shm, s, a);
     else hipLaunchKernelGGL((fft_pow2_kernel<LG, false, false>), g, t, shm, s, a);
   }
+  return hipGetLastError();
+}
+
+template <int LG>
+hipError_t launch_pow2_multi(const FftMulti& m, hipStream_t s) {
+  typedef Pow2<LG> C;
+  const size_t shm = static_cast<size_t>(C::F) * C::L * sizeof(f2v);
+  const dim3 g(static_cast<unsigned>(m.end[m.count - 1])), t(C::NT);
+  if (m.a[0].periodic) hipLaunchKernelGGL((fft_pow2_multi_kernel<LG, true>), g, t, shm, s, m);
+  else hipLaunchKernelGGL((fft_pow2_multi_kernel<LG, false>), g, t, shm, s, m);
   return hipGetLastError();
 }
 
@@ -963,6 +1013,29 @@ hipError_t launch_fft_pow2(const FftArgs& a, hipStream_t s) {
     case 2048: return launch_pow2<11>(a, s);
     case 4096: return launch_pow2<12>(a, s);
     case 8192: return launch_pow2<13>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft_pow2_multi(const FftArgs* a, int count, hipStream_t s) {
+  if (count < 1 || count > 3) return hipErrorInvalidValue;
+  FftMulti m{};
+  m.count = count;
+  int64_t end = 0;
+  for (int i = 0; i < count; ++i) {
+    if (a[i].L != a[0].L || a[i].periodic != a[0].periodic) return hipErrorInvalidValue;
+    m.a[i] = a[i];
+    end += pow2_blocks(a[i]);
+    if (end > 0x7fffffff) return hipErrorInvalidValue;
+    m.end[i] = static_cast<unsigned>(end);
+  }
+  switch (a[0].L) {
+    case 256: return launch_pow2_multi<8>(m, s);
+    case 512: return launch_pow2_multi<9>(m, s);
+    case 1024: return launch_pow2_multi<10>(m, s);
+    case 2048: return launch_pow2_multi<11>(m, s);
+    case 4096: return launch_pow2_multi<12>(m, s);
+    case 8192: return launch_pow2_multi<13>(m, s);
     default: return hipErrorInvalidValue;
   }
 }

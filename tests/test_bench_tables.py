@@ -37,3 +37,20 @@ def test_cost_model_staggered_extents():
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_fft_velocity_launch_mirror():
+    # the library launches the velocity terms of all axes together when every axis runs on the
+    # power-of-two FFT kernel with one transform length (all periodic or none)
+    N, D, P, Nh = 0, 1, 2, 3
+    f = bench.uses_fft_velocity_launch
+    assert f((2049, 2049), ((D, D), (N, N)), "fp32")
+    assert f((1025, 1025, 1025), ((N, N), (D, N), (N, D)), "split_bf16")
+    assert f((1024, 1024), ((P, P), (P, P)), "fp32")
+    assert not f((2049, 2049), ((D, D), (N, N)), "fp64")         # FP64: mixed-radix kernel
+    assert not f((2049,), ((D, N),), "fp32")                       # 1D: one axis
+    assert not f((2049, 1025), ((D, D), (N, N)), "fp32")          # two transform lengths
+    assert not f((2049, 400), ((D, D), (N, N)), "fp32")           # a dense axis
+    assert not f((1024, 513), ((P, P), (N, D)), "fp32")           # periodic beside walls
+    assert not f((2049, 2049), ((D, D), (N, Nh)), "fp32")         # a half-step wall: dense
+    assert not f((1537, 1537), ((D, D), (N, N)), "fp32")          # L = 3072: mixed-radix kernel

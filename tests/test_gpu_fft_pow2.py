@@ -173,3 +173,63 @@ def test_pow2_kernel_periodic_steps(shape, bcs, steps):
     assert e < 1e-5
     for g, r in zip(got_u, ref_u):
         assert rel_l2(g, r) < 1e-5
+
+
+MULTI_CASES = [
+    ((129, 129), ((D, N), (N, D)), False, 40),
+    ((257, 257), ((N, N), (D, D)), True, 40),
+    ((256, 256), ((P, P), (P, P)), False, 40),
+    ((129, 129, 129), ((D, D), (N, D), (N, N)), False, 8),
+]
+
+
+@pytest.mark.parametrize("shape,bcs,medium,steps", MULTI_CASES)
+def test_pow2_velocity_axes_in_one_launch(shape, bcs, medium, steps):
+    # when every axis runs on the power-of-two kernel with one transform length, a step launches the
+    # velocity terms of all axes together; compare one step with the same terms launched axis by axis,
+    # and a few steps with the oracle
+    import torch
+    import workloads
+    from gpu_helpers import oracle_problem, run_gpu
+    from paper_2005_00322_amd import Plan
+
+    print("case", shape, bcs, "c0 map" if medium else "", steps, flush=True)
+    dx = 1e-3
+    rng = np.random.default_rng(sum(shape) + 7)
+    c0_map = workloads.smooth_c0_map(rng, shape) if medium else None
+    c0 = float(c0_map.max()) if medium else 1500.0
+    dt = (0.25 if len(shape) == 2 else 0.2) * dx / c0
+    centre = tuple(s * dx / 2.2 for s in shape)
+    p0 = workloads.gaussian(shape, dx, centre, 5 * dx)
+    prob = opstd.Problem(shape, bcs, dx, dt, c0)
+    p = prob.project(p0 + 0.1 * rng.standard_normal(shape))
+    us = [rng.standard_normal(prob.u_shape(a)) for a in range(len(shape))]
+    out = []
+    with Plan(shape, dx, dt, c0, bcs, precision="fp32", c0_map=c0_map) as plan:
+        plan.set_path("fft")
+        for merged in (True, False):
+            st = plan.new_state(p)
+            for a in range(len(shape)):
+                st.u[a].copy_(torch.from_numpy(us[a]).to(st.u[a].dtype))
+            if merged:
+                plan.step(st, 1)
+            else:
+                for which in (0, 1):
+                    for a in range(len(shape)):
+                        plan.apply_axis(st, a, which)
+            torch.cuda.synchronize()
+            out.append([st.p.double().cpu().numpy()] + [u.double().cpu().numpy() for u in st.u])
+    for x, y in zip(*out):
+        d = np.max(np.abs(x - y))
+        print("max |merged - per axis|", d, "bitwise" if d == 0 else "", flush=True)
+        assert d <= 1e-6 * np.max(np.abs(y))
+    case = workloads.Case("pow2_multi", shape, bcs, dx, dt, c0, steps, p0, c0_map=c0_map)
+    ref = workloads.Case("pow2_multi", shape, bcs, dx, dt, c0, steps, p0,
+                         c0_map=None if c0_map is None else c0_map.astype(np.float32).astype(np.float64))
+    ref_p, ref_u = oracle_problem(ref).run(p0, steps)
+    got_p, got_u = run_gpu(case, precision="fp32", path="fft")
+    e = rel_l2(got_p, ref_p)
+    print("rel_l2 p", e, "u", [rel_l2(g, r) for g, r in zip(got_u, ref_u)], flush=True)
+    assert e < 1e-5
+    for g, r in zip(got_u, ref_u):
+        assert rel_l2(g, r) < 1e-5
