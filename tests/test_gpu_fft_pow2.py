@@ -233,3 +233,21 @@ def test_pow2_velocity_axes_in_one_launch(shape, bcs, medium, steps):
     assert e < 1e-5
     for g, r in zip(got_u, ref_u):
         assert rel_l2(g, r) < 1e-5
+
+
+def test_pow2_velocity_launch_graph_chunks_bitwise():
+    # the two-axis velocity launch inside captured step graphs of several lengths gives bitwise the
+    # result of one long run
+    import workloads
+    from gpu_helpers import run_gpu
+
+    shape, bcs = (257, 257), ((D, N), (N, D))
+    dx, c0 = 1e-3, 1500.0
+    p0 = workloads.gaussian(shape, dx, (100 * dx, 140 * dx), 6 * dx)
+    case = workloads.Case("pow2_multi_chunks", shape, bcs, dx, 0.25 * dx / c0, c0, 120, p0)
+    print("case", shape, bcs, flush=True)
+    p1, u1 = run_gpu(case, "fp32", path="fft")
+    p2, u2 = run_gpu(case, "fp32", path="fft", chunks=[50, 3, 67])
+    assert np.array_equal(p1, p2)
+    for a, b in zip(u1, u2):
+        assert np.array_equal(a, b)
