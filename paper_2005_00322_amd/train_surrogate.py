@@ -1,13 +1,14 @@
 """Train and evaluate the DCT-basis neural-operator surrogate on solver-generated pairs.
 
     python -m paper_2005_00322_amd.train_surrogate [--train 20000] [--test 2000] [--epochs 20]
-        [--batch 64] [--lr 2e-3] [--save weights.npz] [--time-budget SECONDS]
+        [--batch 64] [--lr 2e-3] [--save weights.npz] [--init weights.npz] [--time-budget SECONDS]
 
 Inputs are the seeded 128 x 128 pairs of ``workloads.nop_inputs`` (1-3 Gaussian blobs, smooth c0 map in
 [1400, 1600] m/s); targets are the pressure after ``workloads.NOP_STEPS`` steps of the FP32 batched PSTD
 solver with the same c0 map (x faces Dirichlet, y faces Neumann).  Training runs the library's forward,
 backward and Adam kernels; this module only schedules batches and the learning rate.  Prints one JSON
-line with the held-out relative L2 errors against the solver.
+line with the held-out relative L2 errors against the solver.  ``--init`` starts from saved parameters (a
+warm restart: fresh Adam moments and a new cosine schedule) instead of the seeded initialisation.
 """
 from __future__ import annotations
 
@@ -100,6 +101,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--time-budget", type=float, default=None)
     ap.add_argument("--save", default=None)
+    ap.add_argument("--init", default=None, help="npz with 'theta' to start from")
     ap.add_argument("--workers", type=int, default=8)
     a = ap.parse_args(argv)
     # host inputs first, in child processes started before this process touches the GPU
@@ -120,16 +122,20 @@ def main(argv=None):
     pte_d, cte_d = torch.from_numpy(pte).to(dev), torch.from_numpy(cte).to(dev)
     cfg = SurrogateConfig()
     net = Surrogate(cfg, max_batch=a.batch)
-    net.set_params(workloads.nop_init(param_shapes(cfg), seed=a.seed))
+    if a.init:
+        with np.load(a.init) as z:
+            net.set_params(np.asarray(z["theta"], dtype=np.float32))
+    else:
+        net.set_params(workloads.nop_init(param_shapes(cfg), seed=a.seed))
     hist, t_train, steps = train(net, ptr_d, ctr_d, ttr, a.epochs, a.batch, a.lr, a.time_budget, seed=a.seed)
     err = evaluate(net, pte_d, cte_d, tte, a.batch)
     theta = net.get_params()
     if a.save:
         np.savez_compressed(a.save, theta=theta, train=a.train, epochs=len(hist), batch=a.batch, lr=a.lr,
-                            seed=a.seed)
+                            seed=a.seed, init=a.init or "")
     print(json.dumps({
         "train_pairs": a.train, "test_pairs": a.test, "epochs": len(hist), "steps": steps, "batch": a.batch,
-        "lr": a.lr, "loss_history": [round(x, 5) for x in hist], "train_s": round(t_train, 2),
+        "lr": a.lr, "init": a.init, "loss_history": [round(x, 5) for x in hist], "train_s": round(t_train, 2),
         "targets_s": round(t_targets, 2), "inputs_s": round(t_inputs, 2),
         "heldout_rel_l2": {"mean": float(err.mean()), "median": float(np.median(err)),
                            "p95": float(np.quantile(err, 0.95)), "max": float(err.max())},
