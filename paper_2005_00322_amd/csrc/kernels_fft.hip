@@ -939,9 +939,10 @@ __global__ __launch_bounds__(Pow2<LG>::NT, LG <= 12 ? 5 : 2) void fft_pow2_kerne
 }
 
 // Several axes of one half step in one launch (transforms of one length, all periodic or none): the
-// blocks of axis i follow those of axes 0 .. i-1, each axis's range padded to a multiple of eight
-// blocks so that its line groups spread over the XCDs as in a launch of its own.  Blocks of different
-// axes then share the CUs, and the scheduler places the later ones where the earlier ones finish.
+// blocks of axis i follow those of axes 0 .. i-1, each axis's range padded as in a launch of its own
+// (to a multiple of eight blocks where its line groups spread over the XCDs, so that they spread the
+// same way).  Blocks of different axes then share the CUs, and the scheduler places the later ones where
+// the earlier ones finish.
 struct FftMulti {
   FftArgs a[3];
   unsigned end[3];   // one past the last block of axis i
