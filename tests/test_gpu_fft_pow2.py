@@ -180,6 +180,7 @@ MULTI_CASES = [
     ((257, 257), ((N, N), (D, D)), True, 40),
     ((256, 256), ((P, P), (P, P)), False, 40),
     ((129, 129, 129), ((D, D), (N, D), (N, N)), False, 8),
+    ((256, 256, 256), ((P, P), (P, P), (P, P)), False, 4),
 ]
 
 
