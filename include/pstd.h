@@ -39,7 +39,7 @@ typedef enum {
   PSTD_OK = 0,
   PSTD_E_INVALID_ARG = -1,  /* null pointer, bad enum, n < 3, non-positive dx/dt/c0/rho0 ...      */
   PSTD_E_UNSTABLE = -2,     /* c0 dt / dx above 2 / (dx max|k|) (the 2/pi limit of §4.2 in 1D)    */
-  PSTD_E_UNSUPPORTED = -3,  /* size or mode this build does not handle                             */
+  PSTD_E_UNSUPPORTED = -3,  /* size or mode the library does not handle                            */
   PSTD_E_HIP = -4,          /* a HIP runtime call failed (message in pstd_last_error)              */
   PSTD_E_OOM = -5,          /* device allocation failed                                            */
   PSTD_E_NONFINITE = -6     /* the state holds NaN or Inf (pstd_check_finite)                      */
